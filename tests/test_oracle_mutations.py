@@ -1,0 +1,53 @@
+"""The oracle pins reject plausible mistakes.
+
+Each case plants one mistake in a copy of the oracle source (a dropped term, a
+flipped sign, a wrong index or weight), builds it into a temporary library, and
+runs the pin suite against it in a subprocess: the suite must fail.  Nothing here
+touches the GPU or the product library.
+"""
+import os
+import subprocess
+import sys
+
+import pytest
+
+import oracle
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "phx_oracle.c")
+
+MUTATIONS = {
+    "kinetic_sign": ("cplx h = -(p->hbar * p->hbar / (2.0 * p->mass))", "cplx h = (p->hbar * p->hbar / (2.0 * p->mass))"),
+    "kinetic_mass": ("(2.0 * p->mass)) * laplacian", "(p->mass)) * laplacian"),
+    "laplacian_y_index": ("at(p, f, i, j + 1) + at(p, f, i, j - 1)", "at(p, f, i, j + 1) + at(p, f, i, j + 1)"),
+    "periodic_wrap": ("i = ((i % p->nx) + p->nx) % p->nx;", "i = 0;"),
+    "zero_ghost": ("if (p->bc_x == ORC_BC_ZERO) return 0.0;", "if (p->bc_x == ORC_BC_ZERO) i = i < 0 ? 0 : p->nx - 1;"),
+    "nonlinear_sign": ("(pot + p->g * rho +", "(pot - p->g * rho +"),
+    "cross_interaction_dropped": ("+ p->g_x * rho_o", "+ 0.0 * rho_o"),
+    "tetm_mixed_sign": ("- 2.0 * sgn * I * d_xy(p, po, i, j));", "+ 2.0 * sgn * I * d_xy(p, po, i, j));"),
+    "tetm_dyy_sign": ("h += p->delta_lt * (d_xx(p, po, i, j) - d_yy(p, po, i, j)", "h += p->delta_lt * (d_xx(p, po, i, j) + d_yy(p, po, i, j)"),
+    "gain_dropped": ("0.5 * (p->R * nn - p->gamma_c) * v;", "0.5 * (-p->gamma_c) * v;"),
+    "loss_factor": ("0.5 * (p->R * nn - p->gamma_c) * v;", "(p->R * nn - p->gamma_c) * v;"),
+    "reservoir_depletion": ("(p->gamma_r + p->R * rho) * nn;", "(p->gamma_r + rho) * nn;"),
+    "rk4_stage_offset": ("const double a[4] = {0.0, 0.5, 0.5, 1.0};", "const double a[4] = {0.0, 0.5, 1.0, 1.0};"),
+    "rk4_weight": ("(k[0][q] + 2.0 * k[1][q] + 2.0 * k[2][q] + k[3][q])", "(k[0][q] + 2.0 * k[1][q] + k[2][q] + 2.0 * k[3][q])"),
+    "dp_bhat_coeff": ("393.0 / 640.0", "393.0 / 641.0"),
+    "dp_a_coeff": ("-355.0 / 33.0", "-355.0 / 34.0"),
+    "kinetic_energy_ghost_link": ("const int ilo = (p->bc_x == ORC_BC_ZERO) ? -1 : 0;", "const int ilo = 0;"),
+    "energy_int_half": ("o->e_int = 0.5 * p->g * dA * s_int;", "o->e_int = p->g * dA * s_int;"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTATIONS))
+def test_pins_reject_planted_mistake(name, tmp_path):
+    old, new = MUTATIONS[name]
+    src = open(SRC).read()
+    assert src.count(old) >= 1, f"mutation anchor for {name} no longer in the oracle source"
+    mutated = tmp_path / "mutant.c"
+    mutated.write_text(src.replace(old, new, 1))
+    lib = oracle.compile_library(str(mutated), str(tmp_path / "libmutant.so"))
+    env = dict(os.environ, PHX_ORACLE_LIB=lib, OMP_NUM_THREADS="2")
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                        os.path.join(ROOT, "tests", "test_oracle_pins.py")],
+                       cwd=ROOT, env=env, capture_output=True, text=True, timeout=300)
+    assert r.returncode != 0, f"pins passed with planted mistake {name}:\n{r.stdout[-2000:]}"
