@@ -1,0 +1,187 @@
+#!/usr/bin/env python3
+"""Throughput of the RK4 time stepper on one MI355X.
+
+Workload: the driven-dissipative GP + reservoir equation (Eqs. PULSE_psi /
+PULSE_res, one component: Laplacian, g|psi|^2 psi, pump, reservoir rate equation;
+V = 0) on a 4096^2 periodic grid, complex64 psi and float32 n, RK4 dt 0.02, ring
+pump 2 P_th, seeded noise start.  Inputs are generated on the host and resident in
+HBM before the timed region starts.
+
+Metric: grid-point RK4 updates per second, U = Nx Ny steps / seconds (Sec. 4 of
+the paper).  Printed as one JSON line together with
+  roofline      the dominant kernel's algorithmic bytes per launch over its mean
+                launch time (HIP events on the solver's stream) against 8 TB/s;
+                traffic = HBM bytes per launch from rocprofv3 counters when a
+                measurement for the current kernel source is on file;
+  cpu_baseline  the CPU oracle (complex128, OpenMP) timed on a bounded sample of
+                the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "grid-point RK4 updates/s + HBM GB/s at 4096² c64; surrogate vs plain at L2 1e-3"
+HBM_PEAK_GBPS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "rk4_stage_traffic.json")
+KERNEL_SOURCES = ["paper_2411_18341_amd/csrc/rk4.hip", "paper_2411_18341_amd/csrc/stencil.h",
+                  "paper_2411_18341_amd/csrc/phx_kernels.h"]
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of `kernel` from the counter summary, if it was taken
+    on the current kernel source; else None."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    with open(TRAFFIC_FILE) as f:
+        t = json.load(f)
+    if t.get("source_hash") != kernel_source_hash() or t.get("workload") != workload:
+        return None
+    k = t.get("kernels", {}).get(kernel)
+    return None if k is None else k.get("bytes_per_launch")
+
+
+def copy_bandwidth_gbps(torch, nbytes=1 << 30, reps=20):
+    """Read+write bandwidth of a plain device-to-device copy (calibration)."""
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    src.fill_(1.0)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    del src, dst
+    return 2.0 * nbytes * reps / dt / 1e9
+
+
+def cpu_baseline(ph, psi, n0, P, steps: int) -> dict:
+    import oracle
+    op = oracle.Physics(**{k: getattr(ph, k) for k in (
+        "nx", "ny", "dx", "dy", "bc_x", "bc_y", "components", "reservoir", "hbar", "mass", "g",
+        "g_x", "g_r", "R", "gamma_c", "gamma_r", "delta_lt")})
+    t0 = time.perf_counter()
+    oracle.rk4(op, psi, n0, None, P, dt=ph.dt, steps=steps)
+    dt = time.perf_counter() - t0
+    return {"value": ph.nx * ph.ny * steps / dt, "unit": "UP/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"full {ph.nx}x{ph.ny} grid of the same workload, {steps} RK4 steps, "
+                      f"complex128 plain C oracle, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--n", type=int, default=4096, help="grid side (default 4096)")
+    ap.add_argument("--precision", choices=["c64", "c128"], default="c64")
+    ap.add_argument("--cpu-steps", type=int, default=10, help="oracle steps for the CPU baseline")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures a single GPU: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2411_18341_amd import bytemodel, inputs, phx
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    precision = phx.PHX_C64 if args.precision == "c64" else phx.PHX_C128
+    real_bytes = 4 if precision == phx.PHX_C64 else 8
+
+    ph, psi0, n0, P = inputs.driven(args.n)
+    workload = (f"driven-dissipative GP + reservoir, {args.n}x{args.n}, periodic, "
+                f"{'complex64 psi + float32 n' if real_bytes == 4 else 'complex128 psi + float64 n'}, "
+                f"ring pump 2 P_th (radius 20, width 3), RK4 dt {ph.dt}")
+    cdt, rdt = phx.torch_dtypes(precision)
+    dev = torch.device("cuda:0")
+    psi = torch.from_numpy(psi0).to(dtype=cdt, device=dev).contiguous()
+    n = torch.from_numpy(n0).to(dtype=rdt, device=dev).contiguous()
+    Pd = torch.from_numpy(P).to(dtype=rdt, device=dev).contiguous()
+    cfg = phx.config_from_physics(ph, precision=precision)
+    solver = phx.Solver(cfg, psi, n, None, Pd)
+
+    copy_gbps = copy_bandwidth_gbps(torch)
+
+    solver.step(args.warmup)
+    torch.cuda.synchronize()
+    solver.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    solver.step(args.steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    times = solver.kernel_times()
+    obs = solver.observables()
+    solver.close()
+
+    cells = args.n * args.n
+    value = cells * args.steps / wall
+    model = bytemodel.rk4_stage_fused(real_bytes, reservoir=True, has_v=False)
+    kernels = {}
+    for s in range(1, 5):
+        name = f"rk4_stage{s}"
+        t = times[name]
+        avg_ms = t["ms_total"] / t["launches"]
+        nbytes = model[f"stage{s}"] * cells
+        kernels[name] = {"avg_us": avg_ms * 1e3, "bytes_per_launch": nbytes,
+                         "GBps": nbytes / (avg_ms * 1e-3) / 1e9}
+    dom = max(kernels, key=lambda k: kernels[k]["avg_us"] * times[k]["launches"])
+    d = kernels[dom]
+    traffic = measured_traffic(dom, workload)
+    roofline = {"bound": "hbm", "achieved": round(d["GBps"], 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                "frac": round(d["GBps"] / HBM_PEAK_GBPS, 4), "traffic": traffic,
+                "kernel": dom, "bytes_per_launch": d["bytes_per_launch"],
+                "avg_launch_us": round(d["avg_us"], 2)}
+    step_gbps = model["step"] * cells * args.steps / wall / 1e9
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(ph, psi0, n0, P, args.cpu_steps)
+
+    line = {
+        "metric": METRIC, "value": value, "unit": "UP/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32" if real_bytes == 4 else "f64",
+        "data": "synthetic",
+        "config": {"workload": workload, "grid": [args.n, args.n], "integrator": "rk4",
+                   "kernel_family": "stage-fused (4 launches per step)"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "step_model_bytes_per_point": model["step"],
+        "step_algorithmic_GBps": round(step_gbps, 1),
+        "copy_bandwidth_GBps": round(copy_gbps, 1),
+        "kernels": {k: {kk: round(vv, 2) if isinstance(vv, float) else vv for kk, vv in v.items()}
+                    for k, v in kernels.items()},
+        "final_norm": obs["norm"][0], "nonfinite": obs["nonfinite"],
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

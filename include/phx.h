@@ -1,0 +1,232 @@
+/*
+ * phx.h -- C interface of libphx, an MI355X (gfx950) solver for the 2D dissipative
+ * nonlinear Schroedinger / Gross-Pitaevskii equation of arXiv 2411.18341 (PHOENIX):
+ * fixed-step RK4 and adaptive Dormand-Prince 5(4) time stepping of Eq. (1) and of
+ * its extended form, Eqs. (PULSE_psi) and (PULSE_res) of Sec. 5 (spinor components,
+ * cross interaction, TE-TM coupling, pump-fed reservoir), on a uniform grid with the
+ * five-point Laplacian of Sec. 3.2.8 and periodic or zero boundaries (Sec. 5).
+ *
+ * Conventions shared by every call:
+ *   - Units are the caller's: hbar and mass are parameters.
+ *   - Grid cell (i, j), i in [0, nx) along x, j in [0, ny); storage index j*nx + i
+ *     (x fastest), row-major, contiguous.
+ *   - psi is interleaved complex: {re, im} pairs of float (PHX_C64) or double
+ *     (PHX_C128), shaped [components][ny][nx].  n and P (reservoir) are real
+ *     [components][ny][nx]; V is real [ny][nx] and shared by both components.
+ *     Real arrays are float for PHX_C64 and double for PHX_C128.
+ *   - All device pointers are HIP device memory owned by the caller, 256-byte
+ *     aligned.  The library never allocates or frees device memory: scratch space
+ *     is the caller's workspace, sized by phx_workspace_bytes.  It allocates only
+ *     host memory (handles, a small pinned read-back buffer).
+ *   - All device work is enqueued on the caller's HIP stream (hipStream_t passed as
+ *     void*; NULL is the null stream).  Calls return after enqueueing unless a
+ *     call's description says it synchronizes; then it waits on that stream only.
+ *   - Every call returns a phx_status; no C++ exception crosses this interface.
+ *     phx_last_error() gives a message for the calling thread's last failure.
+ *   - A handle is not thread-safe; distinct handles may be used concurrently from
+ *     distinct threads and streams.
+ */
+#ifndef PHX_H
+#define PHX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum phx_status {
+    PHX_OK = 0,
+    PHX_EINVAL = -1,        /* invalid configuration, pointer, size or alignment        */
+    PHX_EWORKSPACE = -2,    /* workspace missing or smaller than phx_workspace_bytes     */
+    PHX_EHIP = -3,          /* a HIP runtime call failed (message has the HIP error)     */
+    PHX_ENONFINITE = -4,    /* a non-finite value appeared in the state                  */
+    PHX_EDTMIN = -5,        /* adaptive step size fell below dt_min                      */
+    PHX_EUNSUPPORTED = -6,  /* valid combination this build does not implement           */
+    PHX_ESTATE = -7         /* call not valid in the handle's current state              */
+} phx_status;
+
+enum { PHX_BC_PERIODIC = 0, PHX_BC_ZERO = 1 };  /* zero: ghost cells outside hold 0      */
+enum { PHX_C64 = 0, PHX_C128 = 1 };             /* complex64 + float32 / complex128 + float64 */
+enum { PHX_RK4 = 0, PHX_RK45 = 1 };             /* Eqs. rk4_K1-rk4_final / Dormand-Prince 5(4) */
+enum { PHX_KERNEL_AUTO = 0, PHX_KERNEL_STAGE = 1, PHX_KERNEL_STEP = 2 };
+
+/* Equation, grid and integrator parameters.  All real values are given in double
+ * precision; the library forms every derived coefficient (hbar/2m/dx^2, dt/2, dt/6,
+ * ...) in double and rounds it once to the kernel precision.
+ *
+ * Right-hand side advanced by the integrators, per component s (o = other component,
+ * sgn = +1 for psi_+, -1 for psi_-; Eq. 1 for one component, Eqs. PULSE_psi/res):
+ *   d psi_s/dt = -(i/hbar) [ -(hbar^2/2m) Lap psi_s + (V + g|psi_s|^2 + g_x|psi_o|^2
+ *                + g_r n_s) psi_s + delta_lt (Dxx - Dyy - 2 i sgn Dxy) psi_o ]
+ *                + (R n_s - gamma_c) psi_s / 2
+ *   d n_s/dt   = P_s - (gamma_r + R |psi_s|^2) n_s
+ * Lap = Dxx + Dyy, Dxx/Dyy the 3-point second differences, Dxy the 4-corner cross
+ * difference (psi[i+1,j+1] - psi[i+1,j-1] - psi[i-1,j+1] + psi[i-1,j-1])/(4 dx dy). */
+typedef struct phx_config {
+    int32_t nx, ny;         /* grid size, >= 1 each; nx*ny*components < 2^31          */
+    double dx, dy;          /* grid spacing, > 0                                        */
+    int32_t bc_x, bc_y;     /* PHX_BC_PERIODIC or PHX_BC_ZERO, independently             */
+    int32_t components;     /* 1 scalar, 2 spinor                                        */
+    int32_t reservoir;      /* 0 or 1: evolve n with pump P                              */
+    int32_t precision;      /* PHX_C64 or PHX_C128                                       */
+    int32_t integrator;     /* PHX_RK4 or PHX_RK45                                       */
+    double hbar, mass;      /* > 0                                                       */
+    double g, g_x, g_r;     /* self, cross and reservoir interaction                     */
+    double R, gamma_c, gamma_r; /* gain, condensate loss, reservoir loss                 */
+    double delta_lt;        /* TE-TM splitting (spinor only)                             */
+    double dt;              /* RK4: fixed step.  RK45: first step to try                 */
+    double rtol, atol;      /* RK45 tolerances (>= 0, not both 0)                        */
+    double dt_min, dt_max;  /* RK45 step bounds (0 < dt_min <= dt_max; dt_max may be inf) */
+    int32_t kernel;         /* PHX_KERNEL_AUTO picks the fastest applicable kernel family */
+    int32_t tile_wx;        /* 0 = automatic, else waves across x per workgroup: 1, 2, 4 */
+    int32_t tile_rows;      /* 0 = automatic, else rows each wave marches: 1..64         */
+    int32_t reserved;       /* must be 0                                                 */
+} phx_config;
+
+/* Caller-owned device arrays bound to a handle (borrowed until phx_destroy). */
+typedef struct phx_fields {
+    void *psi;              /* [components][ny][nx] complex, read and written            */
+    void *n;                /* [components][ny][nx] real, read and written (reservoir)   */
+    const void *V;          /* [ny][nx] real potential, or NULL for V = 0                */
+    const void *P;          /* [components][ny][nx] real pump (required with reservoir)  */
+    void *workspace;        /* scratch of at least phx_workspace_bytes, 256-B aligned    */
+    size_t workspace_bytes;
+} phx_fields;
+
+/* Observables of the current state, all accumulated in double precision over the
+ * whole grid (A = dx*dy the cell area, rho_s = |psi_s|^2):
+ *   norm[s]   = A sum rho_s                 reservoir = A sum n
+ *   e_kin     = (hbar^2/2m) A sum over all grid links |forward difference|^2 (with a
+ *               zero boundary the links to the ghost cells count), which equals
+ *               -(hbar^2/2m) A sum Re(psi* Lap psi)
+ *   e_pot     = A sum V rho                 e_int  = (g/2) A sum rho_s^2
+ *   e_cross   = g_x A sum rho_+ rho_-        e_tetm = A sum 2 Re(psi_+* J_+ psi_-)
+ *   e_res     = g_r A sum n_s rho_s          energy = sum of the six terms
+ *   max_density = max rho_s
+ *   steady_res_density   = ||2 Re(psi* dpsi/dt)||_2 / ||rho||_2   (d rho/dt residual)
+ *   steady_res_reservoir = ||dn/dt||_2 / ||P||_2 (0 without reservoir or pump)
+ *   nonfinite = number of non-finite entries in psi and n. */
+typedef struct phx_obs {
+    double norm[2];
+    double reservoir;
+    double energy, e_kin, e_pot, e_int, e_cross, e_tetm, e_res;
+    double max_density;
+    double steady_res_density, steady_res_reservoir;
+    int64_t nonfinite;
+} phx_obs;
+
+/* Integrator progress of a handle. */
+typedef struct phx_info {
+    double t;               /* simulated time reached                                   */
+    double dt;              /* RK4: the fixed step.  RK45: next step size to try        */
+    int64_t steps_accepted; /* RK4 steps, or accepted RK45 steps                        */
+    int64_t steps_rejected; /* rejected RK45 attempts                                   */
+    int32_t last_rejected;  /* RK45: 1 if the last attempt was rejected                 */
+    int32_t nonfinite;      /* 1 once a non-finite state was detected                   */
+} phx_info;
+
+typedef struct phx_handle phx_handle;
+
+/* Bytes of device workspace a handle with this configuration needs.
+ * Host-only; no device access.  PHX_EINVAL on an invalid configuration. */
+phx_status phx_workspace_bytes(const phx_config *cfg, size_t *out);
+
+/* Validate cfg and fields, form the coefficients and bind the caller's arrays and
+ * stream to a new handle (*out).  Host-only apart from querying the current device;
+ * no kernel runs.  The stage arguments of Eqs. rk4_K2-rk4_K4 and the Dormand-Prince
+ * stage values live in the workspace.  Errors: PHX_EINVAL (bad value, NULL required
+ * pointer, misalignment, RK4 dt beyond the linear stability bound of the kinetic
+ * term, |lambda| dt > 2 sqrt(2)), PHX_EWORKSPACE, PHX_EUNSUPPORTED, PHX_EHIP. */
+phx_status phx_create(const phx_config *cfg, const phx_fields *fields, void *hip_stream,
+                      phx_handle **out);
+
+/* Advance the bound state.  RK4: n_steps steps of Eqs. rk4_K1-rk4_final (Sec. 2),
+ * enqueued asynchronously.  RK45: attempts Dormand-Prince steps until n_steps are
+ * accepted; each attempt reads its error norm back to the host, so the call
+ * synchronizes the stream once per attempt.  n_steps >= 0.  *out_or_null receives
+ * the progress when not NULL (for RK4 without waiting for the device).
+ * PHX_ENONFINITE is returned by the first call that finds the device-side
+ * non-finite flag set by an earlier step; PHX_EDTMIN when RK45 cannot meet the
+ * tolerance with dt >= dt_min (the state then holds the last accepted step). */
+phx_status phx_step(phx_handle *h, int64_t n_steps, phx_info *out_or_null);
+
+/* Compute phx_obs for the current state.  Two-pass deterministic FP64 reduction
+ * (fixed block partition and fixed summation order), then a read-back: the call
+ * synchronizes the handle's stream. */
+phx_status phx_observables(phx_handle *h, phx_obs *out);
+
+/* Read or overwrite the integrator progress (checkpoint and restore: the caller
+ * saves psi and n itself and restores them together with this record). */
+phx_status phx_get_info(const phx_handle *h, phx_info *out);
+phx_status phx_set_info(phx_handle *h, const phx_info *in);
+
+/* Release host resources of a handle (NULL is a no-op).  Does not synchronize;
+ * the caller keeps its arrays alive until enqueued work has finished. */
+void phx_destroy(phx_handle *h);
+
+/* Message of the calling thread's last failed call ("" if none). */
+const char *phx_last_error(void);
+
+/* ---------------------------------------------------------------- kernel timing
+ * Per-kernel GPU time of a handle's own launches, measured with HIP events
+ * recorded on the handle's stream around every kernel launch while timing is on
+ * (the per-kernel view of Sec. 4.4).  Kernel kinds are named, e.g. "rk4_stage2". */
+#define PHX_MAX_KERNEL_KINDS 16
+typedef struct phx_timing {
+    int32_t count;                          /* kinds with at least one launch            */
+    int32_t reserved;
+    char name[PHX_MAX_KERNEL_KINDS][32];    /* NUL-terminated kernel kind names          */
+    int64_t launches[PHX_MAX_KERNEL_KINDS]; /* launches timed since timing was enabled   */
+    double ms_total[PHX_MAX_KERNEL_KINDS];  /* summed GPU time in milliseconds           */
+} phx_timing;
+
+/* Turn timing on (enable = 1, also resets the totals) or off (0).  Host-only. */
+phx_status phx_set_timing(phx_handle *h, int32_t enable);
+
+/* Totals since timing was enabled; synchronizes the handle's stream. */
+phx_status phx_kernel_times(phx_handle *h, phx_timing *out);
+
+/* ---------------------------------------------------------------- batches
+ * Many independent driven-dissipative scalar instances (Eq. PULSE_psi/res with one
+ * component) on grids of different sizes, advanced together by one persistent
+ * kernel launch per RK4 stage.  Instance k uses params[instances[k].param_index]
+ * (its nx, ny, precision, components, integrator and kernel fields are ignored and
+ * taken from the instance record and the descriptor) on its own slice of packed
+ * device buffers. */
+typedef struct phx_instance {
+    int32_t nx, ny;         /* grid of this instance, >= 1                              */
+    int32_t param_index;    /* index into phx_batch_desc.params                         */
+    int32_t reserved;       /* must be 0                                                */
+    int64_t offset;         /* element offset of this instance in psi, n, P (and V)     */
+} phx_instance;
+
+typedef struct phx_batch_desc {
+    int32_t count;          /* number of instances, >= 1                                */
+    int32_t precision;      /* PHX_C64 or PHX_C128 for all instances                    */
+    const phx_instance *instances;  /* host array [count]                              */
+    const phx_config *params;       /* host array [n_params]                           */
+    int32_t n_params;
+    int32_t has_V;          /* 1: V holds a potential slice per instance                */
+    void *psi;              /* packed complex, instance k at [offset, offset + nx*ny)   */
+    void *n;                /* packed real, same offsets                                */
+    const void *P;          /* packed real pump, same offsets                           */
+    const void *V;          /* packed real potential or NULL                            */
+    void *workspace;        /* scratch of at least phx_batch_workspace_bytes            */
+    size_t workspace_bytes;
+} phx_batch_desc;
+
+/* Workspace bytes phx_batch_step needs for this descriptor (host-only). */
+phx_status phx_batch_workspace_bytes(const phx_batch_desc *desc, size_t *out);
+
+/* Advance every instance of the batch by n_steps RK4 steps (Eqs. rk4_K1-rk4_final),
+ * enqueued on hip_stream; instances must not overlap in the packed buffers.
+ * Errors: PHX_EINVAL, PHX_EWORKSPACE, PHX_EUNSUPPORTED, PHX_EHIP. */
+phx_status phx_batch_step(const phx_batch_desc *desc, int64_t n_steps, void *hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PHX_H */

@@ -1,0 +1,42 @@
+"""Algorithmic HBM bytes of the time-stepping kernels, per grid point.
+
+"Algorithmic" counts each array a kernel must read or write exactly once per point
+(halo re-reads served by caches are not counted).  These are the figures behind
+the roofline numbers the benchmark reports.
+
+paper_unfused_rk4 restates the read/write counts of Table 1 (Sec. 3.2.8): four
+derivative kernels (3 reads, 1 write), three two-term sums (2 reads, 1 write) and
+one five-term sum (5 reads, 1 write), 23 reads and 8 writes of complex buffers per
+step, i.e. 2 (n_r + n_w) d bytes with d the size of one real number.
+"""
+from __future__ import annotations
+
+# Table 1 of the paper: (reads, writes, launches per RK4 step), scalar, no reservoir
+PAPER_TABLE1 = {"derivative": (3, 1, 4), "two_term_sum": (2, 1, 3), "five_term_sum": (5, 1, 1)}
+
+
+def paper_unfused_rk4(real_bytes: int) -> dict:
+    reads = sum(r * k for r, _, k in PAPER_TABLE1.values())
+    writes = sum(w * k for _, w, k in PAPER_TABLE1.values())
+    return {"reads": reads, "writes": writes, "bytes_per_point": 2 * (reads + writes) * real_bytes}
+
+
+def rk4_stage_fused(real_bytes: int, reservoir: bool, has_v: bool, components: int = 1) -> dict:
+    """Bytes per point of the four stage-fused RK4 launches (stage 1..4) and of
+    one whole step.  Complex arrays are 2*real_bytes per component, real arrays
+    real_bytes per component, V real_bytes (shared by the components)."""
+    c = 2 * real_bytes * components
+    r = real_bytes * components if reservoir else 0
+    v = real_bytes if has_v else 0
+    p = r                                      # pump, read by every stage with the reservoir
+    s1 = (c + r + p + v) + (2 * c + 2 * r)     # read y=psi,n,P,V; write y2,acc (+n parts)
+    s23 = (3 * c + 3 * r + p + v) + (2 * c + 2 * r)  # read y,psi,acc (+n parts),P,V; write y,acc
+    s4 = (3 * c + 3 * r + p + v) + (c + r)     # read y,psi,acc,...; write psi,n
+    return {"stage1": s1, "stage2": s23, "stage3": s23, "stage4": s4, "step": s1 + 2 * s23 + s4}
+
+
+def state_minimum(real_bytes: int, reservoir: bool, has_v: bool, components: int = 1) -> int:
+    """Whole-step floor: state read and written once, static fields read once."""
+    c = 2 * real_bytes * components
+    r = real_bytes * components if reservoir else 0
+    return 2 * c + 2 * r + (r if reservoir else 0) + (real_bytes if has_v else 0)

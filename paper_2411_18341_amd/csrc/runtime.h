@@ -1,0 +1,91 @@
+// Host-side internals of libphx shared by the runtime translation units: error
+// reporting, workspace layout, tile plans, coefficient formation and the handle.
+#pragma once
+
+#include <stddef.h>
+
+#include <vector>
+
+#include "phx_kernels.h"
+
+namespace phx {
+
+struct TilePlan {
+    TileShape ts;
+    int tiles_x;
+    int tiles;
+};
+
+// Byte offsets of the workspace regions of one handle (all 256-byte aligned).
+struct Layout {
+    size_t flag;        // non-finite flag word(s)
+    size_t obs;         // OBS_SLOTS doubles: reduced observables
+    size_t partials;    // obs_blocks * OBS_SLOTS doubles
+    size_t y[2], yn[2]; // RK4 stage arguments (ping-pong)
+    size_t acc, accn;   // RK4 running sum K1 + 2 K2 + 2 K3
+    size_t k[7];        // Dormand-Prince stage derivatives
+    size_t ys;          // Dormand-Prince stage argument
+    size_t alt;         // Dormand-Prince second state buffer (psi)
+    size_t err;         // Dormand-Prince error partials
+    int obs_blocks;
+    int err_blocks;
+    TilePlan tiles;
+    size_t total;
+};
+
+phx_status fail(phx_status s, const char* fmt, ...);
+void clear_error();
+const char* last_error();
+size_t align_up(size_t x);
+phx_status validate_config(const phx_config* c);
+Layout make_layout(const phx_config& c);
+TilePlan plan_tiles(int nx, int ny, int wx, int rows);
+template <typename R> Coef<R> make_coef(const phx_config& c);
+
+}  // namespace phx
+
+struct phx_handle {
+    phx_config cfg;
+    phx_fields f;
+    hipStream_t stream;
+    phx::Layout L;
+    char* ws;
+    phx_info info;
+    double* host;           // pinned: [0, OBS_SLOTS) observables, [OBS_SLOTS] flag word,
+                            // [OBS_SLOTS + 1] error norm
+    hipEvent_t flag_ready;  // recorded after the flag read-back of the last phx_step
+    bool flag_pending;
+    // Dormand-Prince: where the current state lives (the caller's psi or the
+    // workspace copy) and whether K1 = f(state) is valid in k[fsal].
+    void* cur;
+    void* other;
+    int fsal;               // index of the buffer that holds K1 of the current state
+    bool k1_valid;
+    // kernel timing (phx_set_timing / phx_kernel_times)
+    struct TimedLaunch {
+        hipEvent_t start, stop;
+        int kind;
+    };
+    bool timing;
+    std::vector<hipEvent_t> free_events;
+    std::vector<TimedLaunch> pending;
+    double kind_ms[PHX_MAX_KERNEL_KINDS];
+    int64_t kind_launches[PHX_MAX_KERNEL_KINDS];
+};
+
+namespace phx {
+// Kernel kinds for phx_kernel_times; names in kernel_kind_name().
+enum KernelKind {
+    K_RK4_S1 = 0, K_RK4_S2, K_RK4_S3, K_RK4_S4, K_OBS, K_DP_S1, K_DP_S2, K_DP_S3, K_DP_S4,
+    K_DP_S5, K_DP_S6, K_DP_S7, K_DP_ERR, K_BATCH, K_RK4_STEP, K_KINDS_
+};
+const char* kernel_kind_name(int k);
+// Timing brackets around one launch (no-ops unless timing is on).
+hipError_t timing_begin(phx_handle* h, hipEvent_t* start);
+hipError_t timing_end(phx_handle* h, hipEvent_t start, int kind);
+const void* state_psi(const phx_handle* h);
+const void* state_n(const phx_handle* h);
+phx_status create_rk45(phx_handle* h);
+phx_status step_rk45(phx_handle* h, int64_t n, phx_info* out);
+phx_status set_info_rk45(phx_handle* h, const phx_info* in);
+}  // namespace phx

@@ -1,0 +1,517 @@
+// Host side of libphx: validation, workspace layout, coefficients, launch plans and
+// the C-ABI entry points declared in include/phx.h.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+#include <string>
+
+#include "phx_kernels.h"
+#include "runtime.h"
+
+namespace phx {
+
+static thread_local std::string g_err;
+
+phx_status fail(phx_status s, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+void clear_error() { g_err.clear(); }
+const char* last_error() { return g_err.c_str(); }
+
+static bool finite_pos(double x) { return isfinite(x) && x > 0.0; }
+static bool aligned(const void* p) { return ((uintptr_t)p & 255u) == 0; }
+
+size_t align_up(size_t x) { return (x + 255u) & ~(size_t)255u; }
+
+phx_status validate_config(const phx_config* c)
+{
+    if (!c) return fail(PHX_EINVAL, "config is NULL");
+    if (c->nx < 1 || c->ny < 1) return fail(PHX_EINVAL, "nx=%d ny=%d must be >= 1", c->nx, c->ny);
+    if (c->components != 1 && c->components != 2)
+        return fail(PHX_EINVAL, "components=%d must be 1 or 2", c->components);
+    if ((int64_t)c->nx * c->ny * c->components >= ((int64_t)1 << 31))
+        return fail(PHX_EINVAL, "nx*ny*components must be < 2^31");
+    if (!finite_pos(c->dx) || !finite_pos(c->dy)) return fail(PHX_EINVAL, "dx, dy must be finite and > 0");
+    if ((c->bc_x != PHX_BC_PERIODIC && c->bc_x != PHX_BC_ZERO) ||
+        (c->bc_y != PHX_BC_PERIODIC && c->bc_y != PHX_BC_ZERO))
+        return fail(PHX_EINVAL, "bc_x=%d bc_y=%d must be PHX_BC_PERIODIC or PHX_BC_ZERO", c->bc_x, c->bc_y);
+    if (c->reservoir != 0 && c->reservoir != 1) return fail(PHX_EINVAL, "reservoir must be 0 or 1");
+    if (c->precision != PHX_C64 && c->precision != PHX_C128)
+        return fail(PHX_EINVAL, "precision=%d must be PHX_C64 or PHX_C128", c->precision);
+    if (c->integrator != PHX_RK4 && c->integrator != PHX_RK45)
+        return fail(PHX_EINVAL, "integrator=%d must be PHX_RK4 or PHX_RK45", c->integrator);
+    if (c->kernel < PHX_KERNEL_AUTO || c->kernel > PHX_KERNEL_STEP)
+        return fail(PHX_EINVAL, "kernel=%d is not a PHX_KERNEL_* value", c->kernel);
+    if (c->reserved != 0) return fail(PHX_EINVAL, "reserved field must be 0");
+    if ((c->tile_wx != 0 && c->tile_wx != 1 && c->tile_wx != 2 && c->tile_wx != 4) ||
+        c->tile_rows < 0 || c->tile_rows > 64 || ((c->tile_wx == 0) != (c->tile_rows == 0)))
+        return fail(PHX_EINVAL, "tile_wx must be 0, 1, 2 or 4 and tile_rows 0..64, both 0 or both set");
+    if (!finite_pos(c->hbar) || !finite_pos(c->mass)) return fail(PHX_EINVAL, "hbar, mass must be finite and > 0");
+    const double coefs[] = {c->g, c->g_x, c->g_r, c->R, c->gamma_c, c->gamma_r, c->delta_lt};
+    for (double x : coefs)
+        if (!isfinite(x)) return fail(PHX_EINVAL, "equation parameters must be finite");
+    if (!finite_pos(c->dt)) return fail(PHX_EINVAL, "dt must be finite and > 0");
+    if (c->integrator == PHX_RK4) {
+        // Largest |lambda| of the kinetic term on the grid: (hbar/2m) 4 (1/dx^2 + 1/dy^2);
+        // RK4 is unstable on the imaginary axis beyond |lambda dt| = 2 sqrt(2).
+        const double lam = c->hbar / (2.0 * c->mass) * 4.0 * (1.0 / (c->dx * c->dx) + 1.0 / (c->dy * c->dy));
+        if (lam * c->dt > 2.0 * sqrt(2.0))
+            return fail(PHX_EINVAL, "dt=%g exceeds the RK4 stability bound %g of the kinetic term",
+                        c->dt, 2.0 * sqrt(2.0) / lam);
+    } else {
+        if (!(c->rtol >= 0.0) || !(c->atol >= 0.0) || !isfinite(c->rtol) || !isfinite(c->atol) ||
+            c->rtol + c->atol <= 0.0)
+            return fail(PHX_EINVAL, "rtol, atol must be finite, >= 0 and not both 0");
+        if (!finite_pos(c->dt_min) || !(c->dt_max >= c->dt_min))
+            return fail(PHX_EINVAL, "need 0 < dt_min <= dt_max");
+    }
+    return PHX_OK;
+}
+
+Layout make_layout(const phx_config& c)
+{
+    Layout L{};
+    const size_t rs = c.precision == PHX_C64 ? 4 : 8;
+    const size_t cells = (size_t)c.nx * c.ny * c.components;
+    const size_t cb = align_up(cells * 2 * rs), rb = align_up(cells * rs);
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off += align_up(bytes); return o; };
+    L.flag = take(256);
+    L.obs = take(OBS_SLOTS * sizeof(double));
+    L.tiles = plan_tiles(c.nx, c.ny, c.tile_wx, c.tile_rows);
+    L.obs_blocks = L.tiles.tiles < 1024 ? L.tiles.tiles : 1024;
+    L.partials = take((size_t)L.obs_blocks * OBS_SLOTS * sizeof(double));
+    if (c.integrator == PHX_RK4) {
+        L.y[0] = take(cb);
+        L.y[1] = take(cb);
+        L.acc = take(cb);
+        if (c.reservoir) {
+            L.yn[0] = take(rb);
+            L.yn[1] = take(rb);
+            L.accn = take(rb);
+        }
+    }
+    L.total = off;
+    return L;
+}
+
+// Tile plan for a grid: waves across x chosen from the width; rows per wave halved
+// until the launch has enough workgroups to cover the 256 CUs several times.
+TilePlan plan_tiles(int nx, int ny, int wx, int rows)
+{
+    TilePlan t{};
+    if (wx > 0) {
+        t.ts.wx = wx;
+        t.ts.rows = rows;
+        t.tiles_x = (nx + 64 * wx - 1) / (64 * wx);
+        const int th = rows * (4 / wx);
+        t.tiles = t.tiles_x * ((ny + th - 1) / th);
+        return t;
+    }
+    t.ts.wx = nx >= 192 ? 4 : (nx >= 96 ? 2 : 1);
+    t.tiles_x = (nx + 64 * t.ts.wx - 1) / (64 * t.ts.wx);
+    t.ts.rows = 16;
+    for (;;) {
+        const int th = t.ts.rows * (4 / t.ts.wx);
+        t.tiles = t.tiles_x * ((ny + th - 1) / th);
+        if (t.tiles >= 2048 || t.ts.rows == 1) break;
+        t.ts.rows >>= 1;
+    }
+    return t;
+}
+
+template <typename R>
+Coef<R> make_coef(const phx_config& c)
+{
+    Coef<R> k;
+    k.ax = (R)(c.hbar / (2.0 * c.mass * c.dx * c.dx));
+    k.ay = (R)(c.hbar / (2.0 * c.mass * c.dy * c.dy));
+    k.inv_hbar = (R)(1.0 / c.hbar);
+    k.g = (R)c.g;
+    k.g_x = (R)c.g_x;
+    k.g_r = (R)c.g_r;
+    k.half_R = (R)(0.5 * c.R);
+    k.half_gamma = (R)(0.5 * c.gamma_c);
+    k.R_ = (R)c.R;
+    k.gamma_r = (R)c.gamma_r;
+    k.bx = (R)(c.delta_lt / (c.hbar * c.dx * c.dx));
+    k.by = (R)(c.delta_lt / (c.hbar * c.dy * c.dy));
+    k.bxy = (R)(c.delta_lt / (2.0 * c.hbar * c.dx * c.dy));
+    return k;
+}
+
+template Coef<float> make_coef<float>(const phx_config&);
+template Coef<double> make_coef<double>(const phx_config&);
+
+}  // namespace phx
+
+using namespace phx;
+
+#define HIP_OR_FAIL(call)                                                                   \
+    do {                                                                                    \
+        hipError_t e_ = (call);                                                             \
+        if (e_ != hipSuccess) return fail(PHX_EHIP, "%s failed: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+
+phx_status phx_workspace_bytes(const phx_config* cfg, size_t* out)
+{
+    clear_error();
+    if (!out) return fail(PHX_EINVAL, "out is NULL");
+    phx_status s = validate_config(cfg);
+    if (s != PHX_OK) return s;
+    *out = make_layout(*cfg).total;
+    return PHX_OK;
+}
+
+phx_status phx_create(const phx_config* cfg, const phx_fields* f, void* stream,
+                                 phx_handle** out)
+{
+    clear_error();
+    if (!out) return fail(PHX_EINVAL, "out is NULL");
+    *out = nullptr;
+    phx_status s = validate_config(cfg);
+    if (s != PHX_OK) return s;
+    if (!f) return fail(PHX_EINVAL, "fields is NULL");
+    if (!f->psi) return fail(PHX_EINVAL, "psi is NULL");
+    if (cfg->reservoir && (!f->n || !f->P)) return fail(PHX_EINVAL, "reservoir needs n and P");
+    const void* ptrs[] = {f->psi, f->n, f->V, f->P, f->workspace};
+    for (const void* p : ptrs)
+        if (p && !aligned(p)) return fail(PHX_EINVAL, "device pointers must be 256-byte aligned");
+    const Layout L = make_layout(*cfg);
+    if (!f->workspace || f->workspace_bytes < L.total)
+        return fail(PHX_EWORKSPACE, "workspace of %zu bytes needed, %zu given", L.total,
+                    f->workspace ? f->workspace_bytes : (size_t)0);
+    phx_handle* h = new (std::nothrow) phx_handle();
+    if (!h) return fail(PHX_EINVAL, "out of host memory");
+    h->cfg = *cfg;
+    h->f = *f;
+    h->stream = (hipStream_t)stream;
+    h->L = L;
+    h->ws = (char*)f->workspace;
+    h->info.t = 0.0;
+    h->info.dt = cfg->dt;
+    hipError_t e = hipHostMalloc((void**)&h->host, (OBS_SLOTS + 2) * sizeof(double), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&h->flag_ready, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipMemsetAsync(h->ws + L.flag, 0, 256, h->stream);
+    if (e != hipSuccess) {
+        if (h->host) (void)hipHostFree(h->host);
+        delete h;
+        return fail(PHX_EHIP, "phx_create: %s", hipGetErrorString(e));
+    }
+    memset(h->host, 0, (OBS_SLOTS + 2) * sizeof(double));
+    h->cur = f->psi;
+    if (cfg->integrator == PHX_RK45) {
+        s = create_rk45(h);
+        if (s != PHX_OK) {
+            phx_destroy(h);
+            return s;
+        }
+    }
+    *out = h;
+    return PHX_OK;
+}
+
+// Reads the non-finite flag copied back by an earlier phx_step, if that copy has
+// completed; never blocks.
+static void poll_flag(phx_handle* h)
+{
+    if (!h->flag_pending) return;
+    if (hipEventQuery(h->flag_ready) != hipSuccess) return;
+    h->flag_pending = false;
+    unsigned int v;
+    memcpy(&v, &h->host[OBS_SLOTS], sizeof(v));
+    if (v) h->info.nonfinite = 1;
+}
+
+template <typename R>
+static phx_status rk4_steps(phx_handle* h, int64_t n)
+{
+    const phx_config& c = h->cfg;
+    const Layout& L = h->L;
+    using C = typename cvec<R>::type;
+    Rk4Args<R> a{};
+    a.nx = c.nx;
+    a.ny = c.ny;
+    a.bcx = c.bc_x;
+    a.bcy = c.bc_y;
+    a.comps = c.components;
+    a.tiles_x = L.tiles.tiles_x;
+    a.tiles = L.tiles.tiles;
+    a.ts = L.tiles.ts;
+    a.cstride = (int64_t)c.nx * c.ny;
+    a.c = make_coef<R>(c);
+    a.V = (const R*)h->f.V;
+    a.P = (const R*)h->f.P;
+    a.flag = (unsigned int*)(h->ws + L.flag);
+    C* psi = (C*)h->f.psi;
+    R* n0 = (R*)h->f.n;
+    C* Y[2] = {(C*)(h->ws + L.y[0]), (C*)(h->ws + L.y[1])};
+    R* YN[2] = {c.reservoir ? (R*)(h->ws + L.yn[0]) : nullptr, c.reservoir ? (R*)(h->ws + L.yn[1]) : nullptr};
+    a.acc = (C*)(h->ws + L.acc);
+    a.accn = c.reservoir ? (R*)(h->ws + L.accn) : nullptr;
+    a.psi = psi;
+    a.n = n0;
+    a.psi_io = psi;
+    a.n_io = n0;
+    const R half_dt = (R)(0.5 * c.dt), full_dt = (R)c.dt;
+    a.dt6 = (R)(c.dt / 6.0);
+    const bool res = c.reservoir != 0, hv = h->f.V != nullptr;
+    for (int64_t k = 0; k < n; ++k) {
+        // stage 1: argument = state; stage s reads y written by stage s-1
+        const C* yin[4] = {psi, Y[0], Y[1], Y[0]};
+        const R* ynin[4] = {n0, YN[0], YN[1], YN[0]};
+        C* yout[4] = {Y[0], Y[1], Y[0], nullptr};
+        R* ynout[4] = {YN[0], YN[1], YN[0], nullptr};
+        const R adt[4] = {half_dt, half_dt, full_dt, (R)0};
+        for (int s = 0; s < 4; ++s) {
+            a.y = yin[s];
+            a.yn = ynin[s];
+            a.y_out = yout[s];
+            a.yn_out = ynout[s];
+            a.a_dt = adt[s];
+            hipEvent_t t0 = nullptr;
+            hipError_t e = timing_begin(h, &t0);
+            if (e == hipSuccess) e = launch_rk4_stage<R>(s + 1, res, hv, a, h->stream);
+            if (e == hipSuccess) e = timing_end(h, t0, K_RK4_S1 + s);
+            if (e != hipSuccess) return fail(PHX_EHIP, "RK4 stage %d launch: %s", s + 1, hipGetErrorString(e));
+        }
+    }
+    return PHX_OK;
+}
+
+phx_status phx_step(phx_handle* h, int64_t n_steps, phx_info* out)
+{
+    clear_error();
+    if (!h) return fail(PHX_EINVAL, "handle is NULL");
+    if (n_steps < 0) return fail(PHX_EINVAL, "n_steps must be >= 0");
+    if (h->cfg.integrator == PHX_RK45) return step_rk45(h, n_steps, out);
+    poll_flag(h);
+    if (h->info.nonfinite) {
+        if (out) *out = h->info;
+        return fail(PHX_ENONFINITE, "a non-finite value appeared in the state before step %lld",
+                    (long long)h->info.steps_accepted);
+    }
+    if (n_steps > 0) {
+        phx_status s = h->cfg.precision == PHX_C64 ? rk4_steps<float>(h, n_steps) : rk4_steps<double>(h, n_steps);
+        if (s != PHX_OK) return s;
+        HIP_OR_FAIL(hipMemcpyAsync(&h->host[OBS_SLOTS], h->ws + h->L.flag, sizeof(unsigned int),
+                                   hipMemcpyDeviceToHost, h->stream));
+        HIP_OR_FAIL(hipEventRecord(h->flag_ready, h->stream));
+        h->flag_pending = true;
+        h->info.steps_accepted += n_steps;
+        h->info.t += (double)n_steps * h->cfg.dt;
+    }
+    if (out) *out = h->info;
+    return PHX_OK;
+}
+
+template <typename R>
+static phx_status observables_t(phx_handle* h)
+{
+    const phx_config& c = h->cfg;
+    ObsArgs<R> a{};
+    a.nx = c.nx;
+    a.ny = c.ny;
+    a.bcx = c.bc_x;
+    a.bcy = c.bc_y;
+    a.comps = c.components;
+    a.reservoir = c.reservoir;
+    a.tiles_x = h->L.tiles.tiles_x;
+    a.tiles = h->L.tiles.tiles;
+    a.ts = h->L.tiles.ts;
+    a.cstride = (int64_t)c.nx * c.ny;
+    a.c = make_coef<R>(c);
+    a.inv_dx2 = 1.0 / (c.dx * c.dx);
+    a.inv_dy2 = 1.0 / (c.dy * c.dy);
+    a.delta_lt = c.delta_lt;
+    a.inv_4dxdy = 1.0 / (4.0 * c.dx * c.dy);
+    a.psi = (const typename cvec<R>::type*)state_psi(h);
+    a.n = (const R*)state_n(h);
+    a.V = (const R*)h->f.V;
+    a.P = (const R*)h->f.P;
+    a.partials = (double*)(h->ws + h->L.partials);
+    a.out = (double*)(h->ws + h->L.obs);
+    hipEvent_t t0 = nullptr;
+    hipError_t e = timing_begin(h, &t0);
+    if (e == hipSuccess) e = launch_observables<R>(a, h->L.obs_blocks, h->stream);
+    if (e == hipSuccess) e = timing_end(h, t0, K_OBS);
+    if (e != hipSuccess) return fail(PHX_EHIP, "observables launch: %s", hipGetErrorString(e));
+    return PHX_OK;
+}
+
+phx_status phx_observables(phx_handle* h, phx_obs* out)
+{
+    clear_error();
+    if (!h || !out) return fail(PHX_EINVAL, "handle or out is NULL");
+    phx_status s = h->cfg.precision == PHX_C64 ? observables_t<float>(h) : observables_t<double>(h);
+    if (s != PHX_OK) return s;
+    HIP_OR_FAIL(hipMemcpyAsync(h->host, h->ws + h->L.obs, OBS_SLOTS * sizeof(double),
+                               hipMemcpyDeviceToHost, h->stream));
+    HIP_OR_FAIL(hipStreamSynchronize(h->stream));
+    const double* q = h->host;
+    const phx_config& c = h->cfg;
+    const double A = c.dx * c.dy;
+    memset(out, 0, sizeof(*out));
+    out->norm[0] = A * q[O_NORM0];
+    out->norm[1] = A * q[O_NORM1];
+    out->reservoir = A * q[O_NSUM];
+    out->e_kin = c.hbar * c.hbar / (2.0 * c.mass) * A * q[O_KIN];
+    out->e_pot = A * q[O_POT];
+    out->e_int = 0.5 * c.g * A * q[O_RHO2];
+    out->e_cross = c.g_x * A * q[O_CROSS];
+    out->e_tetm = A * q[O_TETM];
+    out->e_res = c.g_r * A * q[O_RES];
+    out->energy = out->e_kin + out->e_pot + out->e_int + out->e_cross + out->e_tetm + out->e_res;
+    out->max_density = q[O_MAXRHO];
+    out->steady_res_density = q[O_RHO2] > 0 ? sqrt(q[O_DRHO2]) / sqrt(q[O_RHO2]) : 0.0;
+    out->steady_res_reservoir = (c.reservoir && q[O_P2] > 0) ? sqrt(q[O_FN2]) / sqrt(q[O_P2]) : 0.0;
+    out->nonfinite = (int64_t)q[O_NONFINITE];
+    poll_flag(h);
+    return PHX_OK;
+}
+
+phx_status phx_get_info(const phx_handle* h, phx_info* out)
+{
+    clear_error();
+    if (!h || !out) return fail(PHX_EINVAL, "handle or out is NULL");
+    poll_flag(const_cast<phx_handle*>(h));
+    *out = h->info;
+    return PHX_OK;
+}
+
+phx_status phx_set_info(phx_handle* h, const phx_info* in)
+{
+    clear_error();
+    if (!h || !in) return fail(PHX_EINVAL, "handle or in is NULL");
+    if (!isfinite(in->t) || !finite_pos(in->dt) || in->steps_accepted < 0 || in->steps_rejected < 0)
+        return fail(PHX_EINVAL, "invalid info record");
+    if (h->cfg.integrator == PHX_RK4 && in->dt != h->cfg.dt)
+        return fail(PHX_EINVAL, "RK4 dt is fixed by the configuration");
+    if (h->cfg.integrator == PHX_RK45) return set_info_rk45(h, in);
+    if (!in->nonfinite) {
+        // the caller restored a good state: clear the device flag and any pending read
+        HIP_OR_FAIL(hipStreamSynchronize(h->stream));
+        HIP_OR_FAIL(hipMemsetAsync(h->ws + h->L.flag, 0, 256, h->stream));
+        h->flag_pending = false;
+    }
+    h->info = *in;
+    return PHX_OK;
+}
+
+// ---------------------------------------------------------------- kernel timing
+
+namespace phx {
+
+const char* kernel_kind_name(int k)
+{
+    static const char* names[K_KINDS_] = {
+        "rk4_stage1", "rk4_stage2", "rk4_stage3", "rk4_stage4", "observables",
+        "dp_stage1", "dp_stage2", "dp_stage3", "dp_stage4", "dp_stage5", "dp_stage6",
+        "dp_stage7", "dp_error", "batch_stage", "rk4_step"};
+    return (k >= 0 && k < K_KINDS_) ? names[k] : "unknown";
+}
+
+static hipError_t get_event(phx_handle* h, hipEvent_t* ev)
+{
+    if (!h->free_events.empty()) {
+        *ev = h->free_events.back();
+        h->free_events.pop_back();
+        return hipSuccess;
+    }
+    return hipEventCreate(ev);
+}
+
+hipError_t timing_begin(phx_handle* h, hipEvent_t* start)
+{
+    *start = nullptr;
+    if (!h->timing) return hipSuccess;
+    hipError_t e = get_event(h, start);
+    if (e != hipSuccess) return e;
+    return hipEventRecord(*start, h->stream);
+}
+
+hipError_t timing_end(phx_handle* h, hipEvent_t start, int kind)
+{
+    if (!h->timing || !start) return hipSuccess;
+    hipEvent_t stop;
+    hipError_t e = get_event(h, &stop);
+    if (e != hipSuccess) return e;
+    e = hipEventRecord(stop, h->stream);
+    if (e != hipSuccess) return e;
+    h->pending.push_back({start, stop, kind});
+    return hipSuccess;
+}
+
+}  // namespace phx
+
+phx_status phx_set_timing(phx_handle* h, int32_t enable)
+{
+    clear_error();
+    if (!h) return fail(PHX_EINVAL, "handle is NULL");
+    if (enable != 0 && enable != 1) return fail(PHX_EINVAL, "enable must be 0 or 1");
+    h->timing = enable != 0;
+    for (int k = 0; k < PHX_MAX_KERNEL_KINDS; ++k) {
+        h->kind_ms[k] = 0.0;
+        h->kind_launches[k] = 0;
+    }
+    return PHX_OK;
+}
+
+phx_status phx_kernel_times(phx_handle* h, phx_timing* out)
+{
+    clear_error();
+    if (!h || !out) return fail(PHX_EINVAL, "handle or out is NULL");
+    HIP_OR_FAIL(hipStreamSynchronize(h->stream));
+    for (const auto& t : h->pending) {
+        float ms = 0.f;
+        HIP_OR_FAIL(hipEventElapsedTime(&ms, t.start, t.stop));
+        h->kind_ms[t.kind] += ms;
+        h->kind_launches[t.kind] += 1;
+        h->free_events.push_back(t.start);
+        h->free_events.push_back(t.stop);
+    }
+    h->pending.clear();
+    memset(out, 0, sizeof(*out));
+    for (int k = 0; k < K_KINDS_ && k < PHX_MAX_KERNEL_KINDS; ++k) {
+        if (!h->kind_launches[k]) continue;
+        const int c = out->count++;
+        snprintf(out->name[c], sizeof(out->name[c]), "%s", kernel_kind_name(k));
+        out->launches[c] = h->kind_launches[k];
+        out->ms_total[c] = h->kind_ms[k];
+    }
+    return PHX_OK;
+}
+
+void phx_destroy(phx_handle* h)
+{
+    if (!h) return;
+    if (!h->pending.empty()) (void)hipStreamSynchronize(h->stream);
+    for (const auto& t : h->pending) {
+        (void)hipEventDestroy(t.start);
+        (void)hipEventDestroy(t.stop);
+    }
+    for (hipEvent_t e : h->free_events) (void)hipEventDestroy(e);
+    if (h->host) (void)hipHostFree(h->host);
+    (void)hipEventDestroy(h->flag_ready);
+    delete h;
+}
+
+const char* phx_last_error(void) { return last_error(); }
+
+// Accessors used by the other translation units.
+namespace phx {
+const void* state_psi(const phx_handle* h) { return h->cur ? h->cur : h->f.psi; }
+const void* state_n(const phx_handle* h) { return h->f.n; }
+}  // namespace phx

@@ -1,0 +1,316 @@
+"""ctypes binding of libphx (include/phx.h): the same entry points under the same
+names, plus a small `Solver` convenience wrapper.
+
+This layer only marshals arguments: every step of the time integration runs in the
+HIP kernels of libphx.so.  PyTorch supplies device memory and the current HIP
+stream.  If the library has not been built the first call raises; there is no
+fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libphx.so")
+
+# enums of phx.h
+PHX_OK, PHX_EINVAL, PHX_EWORKSPACE, PHX_EHIP, PHX_ENONFINITE, PHX_EDTMIN, PHX_EUNSUPPORTED, PHX_ESTATE = (
+    0, -1, -2, -3, -4, -5, -6, -7)
+PHX_BC_PERIODIC, PHX_BC_ZERO = 0, 1
+PHX_C64, PHX_C128 = 0, 1
+PHX_RK4, PHX_RK45 = 0, 1
+PHX_KERNEL_AUTO, PHX_KERNEL_STAGE, PHX_KERNEL_STEP = 0, 1, 2
+
+STATUS_NAMES = {0: "PHX_OK", -1: "PHX_EINVAL", -2: "PHX_EWORKSPACE", -3: "PHX_EHIP",
+                -4: "PHX_ENONFINITE", -5: "PHX_EDTMIN", -6: "PHX_EUNSUPPORTED", -7: "PHX_ESTATE"}
+
+
+class phx_config(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+        ("dx", ctypes.c_double), ("dy", ctypes.c_double),
+        ("bc_x", ctypes.c_int32), ("bc_y", ctypes.c_int32),
+        ("components", ctypes.c_int32), ("reservoir", ctypes.c_int32),
+        ("precision", ctypes.c_int32), ("integrator", ctypes.c_int32),
+        ("hbar", ctypes.c_double), ("mass", ctypes.c_double),
+        ("g", ctypes.c_double), ("g_x", ctypes.c_double), ("g_r", ctypes.c_double),
+        ("R", ctypes.c_double), ("gamma_c", ctypes.c_double), ("gamma_r", ctypes.c_double),
+        ("delta_lt", ctypes.c_double),
+        ("dt", ctypes.c_double), ("rtol", ctypes.c_double), ("atol", ctypes.c_double),
+        ("dt_min", ctypes.c_double), ("dt_max", ctypes.c_double),
+        ("kernel", ctypes.c_int32), ("tile_wx", ctypes.c_int32), ("tile_rows", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+    ]
+
+
+class phx_fields(ctypes.Structure):
+    _fields_ = [("psi", ctypes.c_void_p), ("n", ctypes.c_void_p), ("V", ctypes.c_void_p),
+                ("P", ctypes.c_void_p), ("workspace", ctypes.c_void_p),
+                ("workspace_bytes", ctypes.c_size_t)]
+
+
+class phx_obs(ctypes.Structure):
+    _fields_ = [("norm", ctypes.c_double * 2), ("reservoir", ctypes.c_double),
+                ("energy", ctypes.c_double), ("e_kin", ctypes.c_double), ("e_pot", ctypes.c_double),
+                ("e_int", ctypes.c_double), ("e_cross", ctypes.c_double), ("e_tetm", ctypes.c_double),
+                ("e_res", ctypes.c_double), ("max_density", ctypes.c_double),
+                ("steady_res_density", ctypes.c_double), ("steady_res_reservoir", ctypes.c_double),
+                ("nonfinite", ctypes.c_int64)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "norm"}
+        d["norm"] = (self.norm[0], self.norm[1])
+        return d
+
+
+class phx_info(ctypes.Structure):
+    _fields_ = [("t", ctypes.c_double), ("dt", ctypes.c_double),
+                ("steps_accepted", ctypes.c_int64), ("steps_rejected", ctypes.c_int64),
+                ("last_rejected", ctypes.c_int32), ("nonfinite", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+PHX_MAX_KERNEL_KINDS = 16
+
+
+class phx_timing(ctypes.Structure):
+    _fields_ = [("count", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("name", (ctypes.c_char * 32) * PHX_MAX_KERNEL_KINDS),
+                ("launches", ctypes.c_int64 * PHX_MAX_KERNEL_KINDS),
+                ("ms_total", ctypes.c_double * PHX_MAX_KERNEL_KINDS)]
+
+    def as_dict(self):
+        return {self.name[k].value.decode(): {"launches": self.launches[k], "ms_total": self.ms_total[k]}
+                for k in range(self.count)}
+
+
+class phx_instance(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("param_index", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("offset", ctypes.c_int64)]
+
+
+class phx_batch_desc(ctypes.Structure):
+    _fields_ = [("count", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("instances", ctypes.POINTER(phx_instance)), ("params", ctypes.POINTER(phx_config)),
+                ("n_params", ctypes.c_int32), ("has_V", ctypes.c_int32),
+                ("psi", ctypes.c_void_p), ("n", ctypes.c_void_p), ("P", ctypes.c_void_p),
+                ("V", ctypes.c_void_p), ("workspace", ctypes.c_void_p),
+                ("workspace_bytes", ctypes.c_size_t)]
+
+
+# names of every exported entry point (kept in step with include/phx.h)
+ENTRY_POINTS = ("phx_workspace_bytes", "phx_create", "phx_step", "phx_observables", "phx_get_info",
+                "phx_set_info", "phx_destroy", "phx_last_error", "phx_set_timing", "phx_kernel_times",
+                "phx_batch_workspace_bytes", "phx_batch_step")
+
+_lib = None
+
+
+def load(path: str | None = None):
+    """Load libphx.so (built by `paper_2411_18341_amd.build`); raises if absent."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise RuntimeError(f"{p} is missing: build the HIP library first "
+                           "(python -m paper_2411_18341_amd.build)")
+    lib = ctypes.CDLL(p)
+    P = ctypes.POINTER
+    vp = ctypes.c_void_p
+    st = ctypes.c_int
+    lib.phx_workspace_bytes.argtypes = [P(phx_config), P(ctypes.c_size_t)]
+    lib.phx_workspace_bytes.restype = st
+    lib.phx_create.argtypes = [P(phx_config), P(phx_fields), vp, P(vp)]
+    lib.phx_create.restype = st
+    lib.phx_step.argtypes = [vp, ctypes.c_int64, P(phx_info)]
+    lib.phx_step.restype = st
+    lib.phx_observables.argtypes = [vp, P(phx_obs)]
+    lib.phx_observables.restype = st
+    lib.phx_get_info.argtypes = [vp, P(phx_info)]
+    lib.phx_get_info.restype = st
+    lib.phx_set_info.argtypes = [vp, P(phx_info)]
+    lib.phx_set_info.restype = st
+    lib.phx_destroy.argtypes = [vp]
+    lib.phx_destroy.restype = None
+    lib.phx_last_error.argtypes = []
+    lib.phx_last_error.restype = ctypes.c_char_p
+    lib.phx_set_timing.argtypes = [vp, ctypes.c_int32]
+    lib.phx_set_timing.restype = st
+    lib.phx_kernel_times.argtypes = [vp, P(phx_timing)]
+    lib.phx_kernel_times.restype = st
+    lib.phx_batch_workspace_bytes.argtypes = [P(phx_batch_desc), P(ctypes.c_size_t)]
+    lib.phx_batch_workspace_bytes.restype = st
+    lib.phx_batch_step.argtypes = [P(phx_batch_desc), ctypes.c_int64, vp]
+    lib.phx_batch_step.restype = st
+    if path is None:
+        _lib = lib
+    return lib
+
+
+class PhxError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+def _check(status: int):
+    if status != PHX_OK:
+        raise PhxError(status, (load().phx_last_error() or b"").decode())
+
+
+# ------------------------------------------------------------ C-ABI mirrors
+
+def phx_workspace_bytes(cfg: phx_config) -> int:
+    out = ctypes.c_size_t(0)
+    _check(load().phx_workspace_bytes(ctypes.byref(cfg), ctypes.byref(out)))
+    return out.value
+
+
+def phx_create(cfg: phx_config, fields: phx_fields, stream: int | None) -> ctypes.c_void_p:
+    h = ctypes.c_void_p()
+    _check(load().phx_create(ctypes.byref(cfg), ctypes.byref(fields), stream or None, ctypes.byref(h)))
+    return h
+
+
+def phx_step(h, n_steps: int) -> phx_info:
+    info = phx_info()
+    _check(load().phx_step(h, int(n_steps), ctypes.byref(info)))
+    return info
+
+
+def phx_observables(h) -> phx_obs:
+    o = phx_obs()
+    _check(load().phx_observables(h, ctypes.byref(o)))
+    return o
+
+
+def phx_get_info(h) -> phx_info:
+    info = phx_info()
+    _check(load().phx_get_info(h, ctypes.byref(info)))
+    return info
+
+
+def phx_set_info(h, info: phx_info) -> None:
+    _check(load().phx_set_info(h, ctypes.byref(info)))
+
+
+def phx_destroy(h) -> None:
+    load().phx_destroy(h)
+
+
+def phx_last_error() -> str:
+    return (load().phx_last_error() or b"").decode()
+
+
+def phx_set_timing(h, enable: bool) -> None:
+    _check(load().phx_set_timing(h, int(bool(enable))))
+
+
+def phx_kernel_times(h) -> phx_timing:
+    out = phx_timing()
+    _check(load().phx_kernel_times(h, ctypes.byref(out)))
+    return out
+
+
+def phx_batch_workspace_bytes(desc: phx_batch_desc) -> int:
+    out = ctypes.c_size_t(0)
+    _check(load().phx_batch_workspace_bytes(ctypes.byref(desc), ctypes.byref(out)))
+    return out.value
+
+
+def phx_batch_step(desc: phx_batch_desc, n_steps: int, stream: int | None) -> None:
+    _check(load().phx_batch_step(ctypes.byref(desc), int(n_steps), stream or None))
+
+
+# ------------------------------------------------------------ conveniences
+
+def make_config(nx, ny, dx, dy=None, *, bc_x=PHX_BC_PERIODIC, bc_y=PHX_BC_PERIODIC, components=1,
+                reservoir=False, precision=PHX_C64, integrator=PHX_RK4, hbar=1.0, mass=1.0, g=0.0,
+                g_x=0.0, g_r=0.0, R=0.0, gamma_c=0.0, gamma_r=0.0, delta_lt=0.0, dt=1e-3,
+                rtol=1e-6, atol=1e-6, dt_min=1e-12, dt_max=float("inf"),
+                kernel=PHX_KERNEL_AUTO, tile_wx=0, tile_rows=0) -> phx_config:
+    return phx_config(int(nx), int(ny), float(dx), float(dx if dy is None else dy), int(bc_x), int(bc_y),
+                      int(components), int(bool(reservoir)), int(precision), int(integrator),
+                      float(hbar), float(mass), float(g), float(g_x), float(g_r), float(R),
+                      float(gamma_c), float(gamma_r), float(delta_lt), float(dt), float(rtol),
+                      float(atol), float(dt_min), float(dt_max), int(kernel), int(tile_wx),
+                      int(tile_rows), 0)
+
+
+def config_from_physics(ph, **kw) -> phx_config:
+    """phx_config from a workload description with the fields of inputs.Physics."""
+    d = dict(nx=ph.nx, ny=ph.ny, dx=ph.dx, dy=ph.dy, bc_x=ph.bc_x, bc_y=ph.bc_y,
+             components=ph.components, reservoir=ph.reservoir, hbar=ph.hbar, mass=ph.mass, g=ph.g,
+             g_x=ph.g_x, g_r=ph.g_r, R=ph.R, gamma_c=ph.gamma_c, gamma_r=ph.gamma_r,
+             delta_lt=ph.delta_lt, dt=ph.dt)
+    d.update(kw)
+    nx, ny, dx = d.pop("nx"), d.pop("ny"), d.pop("dx")
+    return make_config(nx, ny, dx, **d)
+
+
+def torch_dtypes(precision: int):
+    import torch
+    return (torch.complex64, torch.float32) if precision == PHX_C64 else (torch.complex128, torch.float64)
+
+
+class Solver:
+    """A handle bound to torch tensors on the current GPU and stream.
+
+    psi: complex tensor [components, ny, nx] (complex64 for PHX_C64, complex128 for
+    PHX_C128); n, P: real [components, ny, nx] when the reservoir is on; V: real
+    [ny, nx] or None.  The tensors are updated in place by `step`."""
+
+    def __init__(self, cfg: phx_config, psi, n=None, V=None, P=None, stream=None):
+        import torch
+        cdt, rdt = torch_dtypes(cfg.precision)
+        shape = (cfg.components, cfg.ny, cfg.nx)
+        if psi.dtype != cdt or tuple(psi.shape) != shape or not psi.is_contiguous() or not psi.is_cuda:
+            raise ValueError(f"psi must be a contiguous {cdt} CUDA tensor of shape {shape}")
+        for name, t, shp in (("n", n, shape), ("P", P, shape), ("V", V, (cfg.ny, cfg.nx))):
+            if t is not None and (t.dtype != rdt or tuple(t.shape) != shp or not t.is_contiguous() or not t.is_cuda):
+                raise ValueError(f"{name} must be a contiguous {rdt} CUDA tensor of shape {shp}")
+        self.cfg = cfg
+        self.psi, self.n, self.V, self.P = psi, n, V, P
+        nbytes = phx_workspace_bytes(cfg)
+        self.workspace = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=psi.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(psi.device)
+        ptr = lambda t: None if t is None else t.data_ptr()
+        self.fields = phx_fields(ptr(psi), ptr(n), ptr(V), ptr(P), self.workspace.data_ptr(), nbytes)
+        self.handle = phx_create(cfg, self.fields, self.stream.cuda_stream)
+
+    def step(self, n_steps: int = 1) -> dict:
+        return phx_step(self.handle, n_steps).as_dict()
+
+    def observables(self) -> dict:
+        return phx_observables(self.handle).as_dict()
+
+    def info(self) -> dict:
+        return phx_get_info(self.handle).as_dict()
+
+    def set_info(self, **kw) -> None:
+        cur = phx_get_info(self.handle)
+        for k, v in kw.items():
+            setattr(cur, k, v)
+        phx_set_info(self.handle, cur)
+
+    def set_timing(self, enable: bool = True) -> None:
+        phx_set_timing(self.handle, enable)
+
+    def kernel_times(self) -> dict:
+        return phx_kernel_times(self.handle).as_dict()
+
+    def close(self):
+        if getattr(self, "handle", None):
+            phx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

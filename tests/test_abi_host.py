@@ -1,0 +1,157 @@
+"""Host-side checks of the C-ABI boundary that need no GPU: the library loads and
+exports every entry point declared in include/phx.h, the ctypes structures match
+the C layout, configuration validation rejects bad input with the documented
+status, and the byte model reproduces Table 1 of the paper."""
+import json
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_2411_18341_amd import bytemodel, phx
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "phx.h")
+
+
+def header_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(phx_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_entry_point():
+    lib = phx.load()
+    names = header_functions()
+    assert set(names) == set(phx.ENTRY_POINTS), (names, phx.ENTRY_POINTS)
+    for name in names:
+        assert hasattr(lib, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", phx.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r"\bT (phx_\w+)", out))
+    assert set(names) <= exported
+
+
+def _c_layout():
+    prog = r'''
+#include <stdio.h>
+#include <stddef.h>
+#include "phx.h"
+#define F(T, m) printf(#T "." #m " %zu\n", offsetof(T, m));
+int main(void) {
+  printf("phx_config %zu\n", sizeof(phx_config)); F(phx_config, dx) F(phx_config, bc_x) F(phx_config, hbar)
+  F(phx_config, delta_lt) F(phx_config, dt) F(phx_config, dt_max) F(phx_config, kernel) F(phx_config, tile_rows) F(phx_config, reserved)
+  printf("phx_fields %zu\n", sizeof(phx_fields)); F(phx_fields, workspace_bytes)
+  printf("phx_obs %zu\n", sizeof(phx_obs)); F(phx_obs, energy) F(phx_obs, max_density) F(phx_obs, nonfinite)
+  printf("phx_info %zu\n", sizeof(phx_info)); F(phx_info, steps_rejected) F(phx_info, nonfinite)
+  printf("phx_timing %zu\n", sizeof(phx_timing)); F(phx_timing, launches) F(phx_timing, ms_total)
+  printf("phx_instance %zu\n", sizeof(phx_instance)); F(phx_instance, offset)
+  printf("phx_batch_desc %zu\n", sizeof(phx_batch_desc)); F(phx_batch_desc, params) F(phx_batch_desc, psi)
+  F(phx_batch_desc, workspace_bytes)
+  return 0; }
+'''
+    return prog
+
+
+def test_ctypes_structures_match_c_layout(tmp_path):
+    src = tmp_path / "layout.c"
+    src.write_text(_c_layout())
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    got = {}
+    for line in subprocess.run([str(exe)], capture_output=True, text=True).stdout.splitlines():
+        k, v = line.split()
+        got[k] = int(v)
+    import ctypes
+    for cname, cls in (("phx_config", phx.phx_config), ("phx_fields", phx.phx_fields), ("phx_obs", phx.phx_obs),
+                       ("phx_info", phx.phx_info), ("phx_timing", phx.phx_timing),
+                       ("phx_instance", phx.phx_instance), ("phx_batch_desc", phx.phx_batch_desc)):
+        assert got[cname] == ctypes.sizeof(cls), cname
+        for key, off in got.items():
+            if key.startswith(cname + "."):
+                field = key.split(".", 1)[1]
+                assert getattr(cls, field).offset == off, key
+
+
+def good_config(**kw):
+    d = dict(g=1.0, dt=1e-3)
+    d.update(kw)
+    return phx.make_config(64, 48, 0.1, **d)
+
+
+def test_workspace_bytes_scale_with_precision_and_reservoir():
+    a = phx.phx_workspace_bytes(good_config())
+    b = phx.phx_workspace_bytes(good_config(precision=phx.PHX_C128))
+    c = phx.phx_workspace_bytes(good_config(reservoir=True))
+    assert 0 < a < b and a < c
+    # three complex stage buffers (two stage arguments and the running sum)
+    assert a >= 3 * 64 * 48 * 8
+
+
+@pytest.mark.parametrize("field,value", [
+    ("nx", 0), ("ny", -3), ("dx", 0.0), ("dy", float("nan")), ("bc_x", 2), ("components", 3),
+    ("reservoir", 2), ("precision", 5), ("integrator", 9), ("hbar", 0.0), ("mass", -1.0),
+    ("g", float("inf")), ("dt", 0.0), ("dt", 1.0), ("kernel", 7), ("reserved", 1),
+    ("tile_wx", 3), ("tile_rows", 5), ("tile_rows", 65),
+])
+def test_invalid_config_rejected(field, value):
+    cfg = good_config()
+    setattr(cfg, field, value)
+    with pytest.raises(phx.PhxError) as e:
+        phx.phx_workspace_bytes(cfg)
+    assert e.value.status == phx.PHX_EINVAL
+    assert phx.phx_last_error()
+
+
+def test_rk45_tolerance_validation():
+    cfg = good_config(integrator=phx.PHX_RK45, rtol=0.0, atol=0.0)
+    with pytest.raises(phx.PhxError) as e:
+        phx.phx_workspace_bytes(cfg)
+    assert e.value.status == phx.PHX_EINVAL
+    cfg = good_config(integrator=phx.PHX_RK45, dt_min=1e-3, dt_max=1e-4)
+    with pytest.raises(phx.PhxError):
+        phx.phx_workspace_bytes(cfg)
+
+
+def test_grid_size_limit():
+    cfg = phx.make_config(65536, 32768, 0.1, g=1.0, dt=1e-3)
+    with pytest.raises(phx.PhxError) as e:
+        phx.phx_workspace_bytes(cfg)
+    assert e.value.status == phx.PHX_EINVAL
+
+
+def test_create_rejects_bad_fields_without_touching_the_gpu():
+    """Field validation happens on the host before any HIP call."""
+    cfg = good_config(reservoir=True)
+    ws = phx.phx_workspace_bytes(cfg)
+    bad = [phx.phx_fields(None, 256, None, 512, 1024, ws),          # psi NULL
+           phx.phx_fields(256, None, None, 512, 1024, ws),          # reservoir without n
+           phx.phx_fields(256 + 8, 512, None, 768, 1024, ws)]       # misaligned psi
+    for f in bad:
+        with pytest.raises(phx.PhxError) as e:
+            phx.phx_create(cfg, f, None)
+        assert e.value.status == phx.PHX_EINVAL
+    with pytest.raises(phx.PhxError) as e:
+        phx.phx_create(cfg, phx.phx_fields(256, 512, None, 768, 1024, ws - 1), None)
+    assert e.value.status == phx.PHX_EWORKSPACE
+
+
+def test_byte_model_reproduces_table1(golden_dir):
+    g = json.load(open(os.path.join(golden_dir, "table1_rw_counts.json")))
+    for k, v in g["kernels"].items():
+        assert bytemodel.PAPER_TABLE1[k] == (v["reads"], v["writes"], v["launches_per_step"])
+    m32, m64 = bytemodel.paper_unfused_rk4(4), bytemodel.paper_unfused_rk4(8)
+    assert (m32["reads"], m32["writes"]) == (g["rk4_iteration"]["reads"], g["rk4_iteration"]["writes"])
+    assert m32["bytes_per_point"] == g["bytes_per_point_per_step"]["fp32"]
+    assert m64["bytes_per_point"] == g["bytes_per_point_per_step"]["fp64"]
+
+
+def test_stage_fused_byte_model():
+    # scalar, no reservoir, no V, complex64: 3 launches of (read 3 c + write 2 c) ...
+    m = bytemodel.rk4_stage_fused(4, False, False)
+    assert m["stage1"] == 8 + 16 and m["stage2"] == 24 + 16 and m["stage4"] == 24 + 8
+    assert m["step"] == 136
+    # driven-dissipative physics (reservoir, pump, no V): 220 B per point and step
+    assert bytemodel.rk4_stage_fused(4, True, False)["step"] == 220
+    assert bytemodel.rk4_stage_fused(8, True, False)["step"] == 440
+    assert bytemodel.state_minimum(4, True, False) == 28
