@@ -100,6 +100,7 @@ struct ObsArgs {
     Coef<R> c;
     double inv_dx2, inv_dy2;   // kinetic links
     double delta_lt, inv_4dxdy;  // TE-TM energy (spinor)
+    double gamma_r_d, R_d;       // reservoir residual, in double precision
     const C* psi; const R* n; const R* V; const R* P;
     double* partials;          // [blocks][OBS_SLOTS]
     double* out;               // [OBS_SLOTS]

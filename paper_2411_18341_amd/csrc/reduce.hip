@@ -107,7 +107,7 @@ __global__ __launch_bounds__(256) void obs_pass1(const ObsArgs<R> a, double delt
                 if (RES) {
                     const double nd = nn[s];
                     const double pd = a.P[s * cs + idx];
-                    const double fn = pd - ((double)a.c.gamma_r + (double)a.c.R_ * r) * nd;
+                    const double fn = pd - (a.gamma_r_d + a.R_d * r) * nd;
                     q[O_NSUM] += nd;
                     q[O_RES] += nd * r;
                     q[O_FN2] += fn * fn;

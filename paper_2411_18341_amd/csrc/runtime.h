@@ -59,6 +59,8 @@ struct phx_handle {
     // workspace copy) and whether K1 = f(state) is valid in k[fsal].
     void* cur;
     void* other;
+    void* cur_n;
+    void* other_n;
     int fsal;               // index of the buffer that holds K1 of the current state
     bool k1_valid;
     // kernel timing (phx_set_timing / phx_kernel_times)

@@ -102,6 +102,12 @@ Layout make_layout(const phx_config& c)
             L.accn = take(rb);
         }
     }
+    if (c.integrator == PHX_RK45) {
+        // K_1..K_7, two stage arguments and a second state, for psi and n
+        L.k[0] = take(10 * cb + (c.reservoir ? 10 * rb : 0));
+        L.err_blocks = L.tiles.tiles;
+        L.err = take((size_t)L.tiles.tiles * sizeof(double));
+    }
     L.total = off;
     return L;
 }
@@ -337,6 +343,8 @@ static phx_status observables_t(phx_handle* h)
     a.inv_dy2 = 1.0 / (c.dy * c.dy);
     a.delta_lt = c.delta_lt;
     a.inv_4dxdy = 1.0 / (4.0 * c.dx * c.dy);
+    a.gamma_r_d = c.gamma_r;
+    a.R_d = c.R;
     a.psi = (const typename cvec<R>::type*)state_psi(h);
     a.n = (const R*)state_n(h);
     a.V = (const R*)h->f.V;
