@@ -19,7 +19,6 @@ the paper).  Printed as one JSON line together with
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -31,16 +30,7 @@ sys.path.insert(0, ROOT)
 METRIC = "grid-point RK4 updates/s + HBM GB/s at 4096² c64; surrogate vs plain at L2 1e-3"
 HBM_PEAK_GBPS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "rk4_stage_traffic.json")
-KERNEL_SOURCES = ["paper_2411_18341_amd/csrc/rk4.hip", "paper_2411_18341_amd/csrc/stencil.h",
-                  "paper_2411_18341_amd/csrc/phx_kernels.h"]
-
-
-def kernel_source_hash() -> str:
-    h = hashlib.sha256()
-    for p in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, p), "rb") as f:
-            h.update(f.read())
-    return h.hexdigest()[:16]
+COPY_BYTES = 1 << 30
 
 
 def measured_traffic(kernel: str, workload: str):
@@ -50,13 +40,14 @@ def measured_traffic(kernel: str, workload: str):
         return None
     with open(TRAFFIC_FILE) as f:
         t = json.load(f)
+    from paper_2411_18341_amd.profiling import kernel_source_hash
     if t.get("source_hash") != kernel_source_hash() or t.get("workload") != workload:
         return None
     k = t.get("kernels", {}).get(kernel)
     return None if k is None else k.get("bytes_per_launch")
 
 
-def copy_bandwidth_gbps(torch, nbytes=1 << 30, reps=20):
+def copy_bandwidth_gbps(torch, nbytes=COPY_BYTES, reps=20):
     """Read+write bandwidth of a plain device-to-device copy (calibration)."""
     src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)

@@ -1,0 +1,129 @@
+"""Summaries of rocprofv3 output for the solver's kernels.
+
+`stats_summary` condenses a `--kernel-trace --stats --output-format csv` run
+(the *_kernel_stats.csv file) into a short text table; `traffic_summary` turns two
+`--pmc FETCH_SIZE` / `--pmc WRITE_SIZE` runs (the *_counter_collection.csv files)
+into HBM bytes per launch for each kernel, scaled by what the same counters read
+for a plain device copy of known size that ran in the same process.
+
+    python -m paper_2411_18341_amd.profiling stats <kernel_stats.csv> <command...>
+    python -m paper_2411_18341_amd.profiling traffic <fetch.csv> <write.csv> <copy_bytes> <out.json> <workload>
+"""
+from __future__ import annotations
+
+import csv
+import hashlib
+import json
+import os
+import re
+import sys
+from collections import defaultdict
+
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+# sources whose change invalidates a stored counter measurement of the RK4 kernels
+KERNEL_SOURCES = ["paper_2411_18341_amd/csrc/rk4.hip", "paper_2411_18341_amd/csrc/stencil.h",
+                  "paper_2411_18341_amd/csrc/phx_kernels.h", "paper_2411_18341_amd/csrc/rk4_step.hip"]
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        path = os.path.join(ROOT, p)
+        if os.path.exists(path):
+            with open(path, "rb") as f:
+                h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def kernel_kind(name: str) -> str:
+    """Kernel kind as the solver's timing API names it (rk4_stage2, dp_stage7, ...),
+    or a shortened name for other kernels."""
+    m = re.search(r"(rk4_stage_kernel|dp_stage_kernel)<[^>]*?(\d+)>", name)
+    if m:
+        return ("rk4_stage" if m.group(1).startswith("rk4") else "dp_stage") + m.group(2)
+    for k in ("rk4_step_kernel", "batch_stage_kernel", "dp_restart_kernel", "dp_err_sum_kernel",
+              "obs_pass1", "obs_pass2"):
+        if k in name:
+            return k
+    return name[:60]
+
+
+def read_stats(path: str):
+    rows = []
+    with open(path) as f:
+        for r in csv.DictReader(f):
+            rows.append({"name": r["Name"], "calls": int(r["Calls"]),
+                         "total_ns": float(r["TotalDurationNs"]), "avg_ns": float(r["AverageNs"]),
+                         "pct": float(r["Percentage"]), "min_ns": float(r["MinNs"]),
+                         "max_ns": float(r["MaxNs"])})
+    return sorted(rows, key=lambda r: -r["total_ns"])
+
+
+def stats_summary(path: str, command: str, top: int = 12) -> str:
+    rows = read_stats(path)
+    out = [f"command: {command}", "",
+           f"{'kernel':70s} {'calls':>6s} {'avg_us':>10s} {'min_us':>10s} {'max_us':>10s} {'pct':>6s}"]
+    for r in rows[:top]:
+        out.append(f"{r['name'][:70]:70s} {r['calls']:6d} {r['avg_ns'] / 1e3:10.2f} "
+                   f"{r['min_ns'] / 1e3:10.2f} {r['max_ns'] / 1e3:10.2f} {r['pct']:6.2f}")
+    return "\n".join(out) + "\n"
+
+
+def read_counter(path: str, counter: str):
+    """{kernel name: [value per dispatch]} for one counter (summed over its
+    dimensions, as rocprofv3 reports one row per dispatch and counter)."""
+    per = defaultdict(lambda: defaultdict(float))
+    with open(path) as f:
+        for r in csv.DictReader(f):
+            if r.get("Counter_Name") != counter:
+                continue
+            per[r["Kernel_Name"]][r["Dispatch_Id"]] += float(r["Counter_Value"])
+    return {k: list(v.values()) for k, v in per.items()}
+
+
+def traffic_summary(fetch_csv: str, write_csv: str, copy_bytes: float, workload: str):
+    """Bytes per launch (read, write, total) per kernel, each counter scaled by
+    copy_bytes over the counter's mean reading for the copy kernel (a copy reads
+    and writes copy_bytes each)."""
+    fetch = read_counter(fetch_csv, "FETCH_SIZE")
+    write = read_counter(write_csv, "WRITE_SIZE")
+    copy_f = [v for k, vs in fetch.items() if "copy" in k for v in vs]
+    copy_w = [v for k, vs in write.items() if "copy" in k for v in vs]
+    if not copy_f or not copy_w:
+        raise RuntimeError("no copy kernel found in the counter runs")
+    # FETCH_SIZE and WRITE_SIZE are in KiB
+    med = lambda v: sorted(v)[len(v) // 2]
+    f_scale = copy_bytes / (1024.0 * med(copy_f))
+    w_scale = copy_bytes / (1024.0 * med(copy_w))
+    kernels = {}
+    for k in sorted(set(fetch) | set(write)):
+        if "copy" in k:
+            continue
+        fr = fetch.get(k, [])
+        wr = write.get(k, [])
+        if not fr or not wr:
+            continue
+        rd = sum(fr) / len(fr) * 1024.0 * f_scale
+        wb = sum(wr) / len(wr) * 1024.0 * w_scale
+        kernels[kernel_kind(k)] = {"read_bytes": rd, "write_bytes": wb, "bytes_per_launch": rd + wb,
+                                   "dispatches": len(fr), "fetch_kib_raw": sum(fr) / len(fr),
+                                   "write_kib_raw": sum(wr) / len(wr)}
+    return {"workload": workload, "source_hash": kernel_source_hash(), "fetch_scale": f_scale,
+            "write_scale": w_scale, "copy_bytes": copy_bytes, "kernels": kernels}
+
+
+def main(argv):
+    if argv[0] == "stats":
+        sys.stdout.write(stats_summary(argv[1], " ".join(argv[2:])))
+    elif argv[0] == "traffic":
+        t = traffic_summary(argv[1], argv[2], float(argv[3]), argv[5])
+        with open(argv[4], "w") as f:
+            json.dump(t, f, indent=1)
+        print(json.dumps(t, indent=1))
+    else:
+        raise SystemExit(__doc__)
+
+
+if __name__ == "__main__":
+    main(sys.argv[1:])
