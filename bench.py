@@ -87,6 +87,8 @@ def main():
     ap.add_argument("--precision", choices=["c64", "c128"], default="c64")
     ap.add_argument("--cpu-steps", type=int, default=10, help="oracle steps for the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--kernel", choices=["auto", "stage", "step"], default="auto",
+                    help="RK4 kernel family (auto: whole-step kernel)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -114,7 +116,8 @@ def main():
     psi = torch.from_numpy(psi0).to(dtype=cdt, device=dev).contiguous()
     n = torch.from_numpy(n0).to(dtype=rdt, device=dev).contiguous()
     Pd = torch.from_numpy(P).to(dtype=rdt, device=dev).contiguous()
-    cfg = phx.config_from_physics(ph, precision=precision)
+    family = {"auto": phx.PHX_KERNEL_AUTO, "stage": phx.PHX_KERNEL_STAGE, "step": phx.PHX_KERNEL_STEP}[args.kernel]
+    cfg = phx.config_from_physics(ph, precision=precision, kernel=family)
     solver = phx.Solver(cfg, psi, n, None, Pd)
 
     copy_gbps = copy_bandwidth_gbps(torch)
@@ -133,23 +136,28 @@ def main():
 
     cells = args.n * args.n
     value = cells * args.steps / wall
-    model = bytemodel.rk4_stage_fused(real_bytes, reservoir=True, has_v=False)
+    stage_model = bytemodel.rk4_stage_fused(real_bytes, reservoir=True, has_v=False)
+    step_model = bytemodel.rk4_whole_step(real_bytes, reservoir=True, has_v=False)
+    per_launch = {f"rk4_stage{s}": stage_model[f"stage{s}"] for s in range(1, 5)}
+    per_launch["rk4_step"] = step_model["step"]
     kernels = {}
-    for s in range(1, 5):
-        name = f"rk4_stage{s}"
-        t = times[name]
+    for name, t in times.items():
+        if name not in per_launch:
+            continue
         avg_ms = t["ms_total"] / t["launches"]
-        nbytes = model[f"stage{s}"] * cells
-        kernels[name] = {"avg_us": avg_ms * 1e3, "bytes_per_launch": nbytes,
+        nbytes = per_launch[name] * cells
+        kernels[name] = {"launches": t["launches"], "avg_us": avg_ms * 1e3, "bytes_per_launch": nbytes,
                          "GBps": nbytes / (avg_ms * 1e-3) / 1e9}
-    dom = max(kernels, key=lambda k: kernels[k]["avg_us"] * times[k]["launches"])
+    dom = max(kernels, key=lambda k: kernels[k]["avg_us"] * kernels[k]["launches"])
     d = kernels[dom]
     traffic = measured_traffic(dom, workload)
     roofline = {"bound": "hbm", "achieved": round(d["GBps"], 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                 "frac": round(d["GBps"] / HBM_PEAK_GBPS, 4), "traffic": traffic,
                 "kernel": dom, "bytes_per_launch": d["bytes_per_launch"],
                 "avg_launch_us": round(d["avg_us"], 2)}
-    step_gbps = model["step"] * cells * args.steps / wall / 1e9
+    family_name = "whole-step (1 launch per step)" if dom == "rk4_step" else "stage-fused (4 launches per step)"
+    step_bytes = step_model["step"] if dom == "rk4_step" else stage_model["step"]
+    step_gbps = step_bytes * cells * args.steps / wall / 1e9
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -161,10 +169,10 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f32" if real_bytes == 4 else "f64",
         "data": "synthetic",
         "config": {"workload": workload, "grid": [args.n, args.n], "integrator": "rk4",
-                   "kernel_family": "stage-fused (4 launches per step)"},
+                   "kernel_family": family_name},
         "roofline": roofline,
         "cpu_baseline": cpu,
-        "step_model_bytes_per_point": model["step"],
+        "step_model_bytes_per_point": step_bytes,
         "step_algorithmic_GBps": round(step_gbps, 1),
         "copy_bandwidth_GBps": round(copy_gbps, 1),
         "kernels": {k: {kk: round(vv, 2) if isinstance(vv, float) else vv for kk, vv in v.items()}

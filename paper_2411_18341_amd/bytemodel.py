@@ -40,3 +40,11 @@ def state_minimum(real_bytes: int, reservoir: bool, has_v: bool, components: int
     c = 2 * real_bytes * components
     r = real_bytes * components if reservoir else 0
     return 2 * c + 2 * r + (r if reservoir else 0) + (real_bytes if has_v else 0)
+
+
+def rk4_whole_step(real_bytes: int, reservoir: bool, has_v: bool, components: int = 1) -> dict:
+    """Algorithmic bytes per point of the whole-step kernel (one launch per step):
+    the state read and written once, pump and potential read once.  Reading the
+    4-cell halo of each region again is redundant traffic, not counted here."""
+    b = state_minimum(real_bytes, reservoir, has_v, components)
+    return {"step": b}

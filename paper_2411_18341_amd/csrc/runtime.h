@@ -25,7 +25,9 @@ struct Layout {
     size_t acc, accn;   // RK4 running sum K1 + 2 K2 + 2 K3
     size_t k[7];        // Dormand-Prince stage derivatives
     size_t ys;          // Dormand-Prince stage argument
-    size_t alt;         // Dormand-Prince second state buffer (psi)
+    size_t alt;         // second state buffer for psi (whole-step RK4, Dormand-Prince)
+    size_t alt_n;       // second state buffer for n (whole-step RK4)
+    int family;         // PHX_KERNEL_STAGE or PHX_KERNEL_STEP for RK4
     size_t err;         // Dormand-Prince error partials
     int obs_blocks;
     int err_blocks;
@@ -88,6 +90,8 @@ hipError_t timing_end(phx_handle* h, hipEvent_t start, int kind);
 const void* state_psi(const phx_handle* h);
 const void* state_n(const phx_handle* h);
 phx_status create_rk45(phx_handle* h);
+template <typename R> phx_status rk4_fused_steps(phx_handle* h, int64_t n);
+int rk4_family(const phx_config& c);
 phx_status step_rk45(phx_handle* h, int64_t n, phx_info* out);
 phx_status set_info_rk45(phx_handle* h, const phx_info* in);
 }  // namespace phx

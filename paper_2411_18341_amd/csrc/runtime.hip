@@ -54,6 +54,8 @@ phx_status validate_config(const phx_config* c)
     if (c->kernel < PHX_KERNEL_AUTO || c->kernel > PHX_KERNEL_STEP)
         return fail(PHX_EINVAL, "kernel=%d is not a PHX_KERNEL_* value", c->kernel);
     if (c->reserved != 0) return fail(PHX_EINVAL, "reserved field must be 0");
+    if (c->kernel == PHX_KERNEL_STEP && (c->integrator != PHX_RK4 || c->components != 1))
+        return fail(PHX_EUNSUPPORTED, "the whole-step kernel covers RK4 with one component");
     if ((c->tile_wx != 0 && c->tile_wx != 1 && c->tile_wx != 2 && c->tile_wx != 4) ||
         c->tile_rows < 0 || c->tile_rows > 64 || ((c->tile_wx == 0) != (c->tile_rows == 0)))
         return fail(PHX_EINVAL, "tile_wx must be 0, 1, 2 or 4 and tile_rows 0..64, both 0 or both set");
@@ -93,13 +95,19 @@ Layout make_layout(const phx_config& c)
     L.obs_blocks = L.tiles.tiles < 1024 ? L.tiles.tiles : 1024;
     L.partials = take((size_t)L.obs_blocks * OBS_SLOTS * sizeof(double));
     if (c.integrator == PHX_RK4) {
-        L.y[0] = take(cb);
-        L.y[1] = take(cb);
-        L.acc = take(cb);
-        if (c.reservoir) {
-            L.yn[0] = take(rb);
-            L.yn[1] = take(rb);
-            L.accn = take(rb);
+        L.family = rk4_family(c);
+        if (L.family == PHX_KERNEL_STEP) {
+            L.alt = take(cb);
+            if (c.reservoir) L.alt_n = take(rb);
+        } else {
+            L.y[0] = take(cb);
+            L.y[1] = take(cb);
+            L.acc = take(cb);
+            if (c.reservoir) {
+                L.yn[0] = take(rb);
+                L.yn[1] = take(rb);
+                L.accn = take(rb);
+            }
         }
     }
     if (c.integrator == PHX_RK45) {
@@ -110,6 +118,15 @@ Layout make_layout(const phx_config& c)
     }
     L.total = off;
     return L;
+}
+
+// RK4 kernel family: the whole-step kernel (one launch per step, state read and
+// written once) for one component, the stage-fused kernels otherwise or on request.
+int rk4_family(const phx_config& c)
+{
+    if (c.kernel == PHX_KERNEL_STAGE) return PHX_KERNEL_STAGE;
+    if (c.components == 1) return PHX_KERNEL_STEP;
+    return PHX_KERNEL_STAGE;
 }
 
 // Tile plan for a grid: waves across x chosen from the width; rows per wave halved
@@ -310,7 +327,11 @@ phx_status phx_step(phx_handle* h, int64_t n_steps, phx_info* out)
                     (long long)h->info.steps_accepted);
     }
     if (n_steps > 0) {
-        phx_status s = h->cfg.precision == PHX_C64 ? rk4_steps<float>(h, n_steps) : rk4_steps<double>(h, n_steps);
+        phx_status s;
+        if (h->L.family == PHX_KERNEL_STEP)
+            s = h->cfg.precision == PHX_C64 ? rk4_fused_steps<float>(h, n_steps) : rk4_fused_steps<double>(h, n_steps);
+        else
+            s = h->cfg.precision == PHX_C64 ? rk4_steps<float>(h, n_steps) : rk4_steps<double>(h, n_steps);
         if (s != PHX_OK) return s;
         HIP_OR_FAIL(hipMemcpyAsync(&h->host[OBS_SLOTS], h->ws + h->L.flag, sizeof(unsigned int),
                                    hipMemcpyDeviceToHost, h->stream));

@@ -80,12 +80,20 @@ def good_config(**kw):
 
 
 def test_workspace_bytes_scale_with_precision_and_reservoir():
-    a = phx.phx_workspace_bytes(good_config())
-    b = phx.phx_workspace_bytes(good_config(precision=phx.PHX_C128))
-    c = phx.phx_workspace_bytes(good_config(reservoir=True))
+    a = phx.phx_workspace_bytes(good_config(kernel=phx.PHX_KERNEL_STAGE))
+    b = phx.phx_workspace_bytes(good_config(kernel=phx.PHX_KERNEL_STAGE, precision=phx.PHX_C128))
+    c = phx.phx_workspace_bytes(good_config(kernel=phx.PHX_KERNEL_STAGE, reservoir=True))
     assert 0 < a < b and a < c
-    # three complex stage buffers (two stage arguments and the running sum)
+    # stage kernels: three complex buffers (two stage arguments and the running sum)
     assert a >= 3 * 64 * 48 * 8
+    # whole-step kernel: one second state buffer
+    d = phx.phx_workspace_bytes(good_config(kernel=phx.PHX_KERNEL_STEP))
+    assert 64 * 48 * 8 <= d < a
+    assert phx.phx_workspace_bytes(good_config()) == d  # AUTO picks the whole-step kernel
+    # spinor: the whole-step kernel is not available
+    with pytest.raises(phx.PhxError) as e:
+        phx.phx_workspace_bytes(good_config(kernel=phx.PHX_KERNEL_STEP, components=2))
+    assert e.value.status == phx.PHX_EUNSUPPORTED
 
 
 @pytest.mark.parametrize("field,value", [

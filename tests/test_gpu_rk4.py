@@ -70,14 +70,32 @@ def compare(ph, psi, n, V, P, steps, precision, **cfg_kw):
     return e_psi, e_n
 
 
+FAMILIES = [phx.PHX_KERNEL_STAGE, phx.PHX_KERNEL_AUTO]
+
+
+@pytest.mark.parametrize("family", FAMILIES)
 @pytest.mark.parametrize("precision", PREC)
 @pytest.mark.parametrize("bc", BCS)
 @pytest.mark.parametrize("kind", ["conservative", "driven", "driven_v", "spinor", "spinor_res"])
-def test_rk4_small_parity(kind, bc, precision):
+def test_rk4_small_parity(kind, bc, precision, family):
+    """AUTO selects the whole-step kernel for one component, the stage kernels for two."""
     ph, psi, n, V, P = workload(kind, 300, 70, bc)
-    e_psi, e_n = compare(ph, psi, n, V, P, 40, precision)
-    print(f"{kind} bc={bc} prec={precision}: psi {e_psi:.3e} n {e_n:.3e}")
+    e_psi, e_n = compare(ph, psi, n, V, P, 41, precision, kernel=family)
+    print(f"{kind} bc={bc} prec={precision} family={family}: psi {e_psi:.3e} n {e_n:.3e}")
     assert e_psi <= TOL[precision] and e_n <= TOL[precision]
+
+
+@pytest.mark.parametrize("precision", PREC)
+@pytest.mark.parametrize("bc", BCS)
+@pytest.mark.parametrize("shape", [(57, 200), (113, 57), (500, 301), (56, 56), (55, 25), (2, 3)])
+def test_rk4_step_kernel_region_edges(shape, bc, precision):
+    """Whole-step kernel on grids around multiples of its 56-column / 56- or 24-row
+    output tiles, one or two steps (odd counts start from the workspace copy)."""
+    nx, ny = shape
+    ph, psi, n, V, P = workload("driven_v", nx, ny, bc, seed=13)
+    for steps in (1, 2, 7):
+        e_psi, e_n = compare(ph, psi, n, V, P, steps, precision, kernel=phx.PHX_KERNEL_STEP)
+        assert e_psi <= TOL[precision] and e_n <= TOL[precision], (steps, e_psi, e_n)
 
 
 @pytest.mark.parametrize("precision", PREC)
@@ -85,17 +103,19 @@ def test_rk4_small_parity(kind, bc, precision):
 def test_rk4_tile_shapes_ragged(tile, precision):
     """Forced tile geometries: multi-row marching with ragged tails in both axes."""
     ph, psi, n, V, P = workload("driven_v", 197, 133, (1, 0), seed=3)
-    e_psi, e_n = compare(ph, psi, n, V, P, 25, precision, tile_wx=tile[0], tile_rows=tile[1])
+    e_psi, e_n = compare(ph, psi, n, V, P, 25, precision, tile_wx=tile[0], tile_rows=tile[1],
+                         kernel=phx.PHX_KERNEL_STAGE)
     assert e_psi <= TOL[precision] and e_n <= TOL[precision]
 
 
+@pytest.mark.parametrize("family", FAMILIES)
 @pytest.mark.parametrize("precision", PREC)
 @pytest.mark.parametrize("shape", [(1, 1), (1, 5), (5, 1), (64, 1), (65, 3), (3, 65)])
-def test_rk4_degenerate_grids(shape, precision):
+def test_rk4_degenerate_grids(shape, precision, family):
     """Grids of one cell or one row/column, and widths around one wave."""
     nx, ny = shape
     ph, psi, n, V, P = workload("driven_v", nx, ny, (0, 1), seed=4)
-    e_psi, e_n = compare(ph, psi, n, V, P, 10, precision)
+    e_psi, e_n = compare(ph, psi, n, V, P, 10, precision, kernel=family)
     assert e_psi <= TOL[precision] and e_n <= TOL[precision]
 
 
@@ -107,7 +127,8 @@ def test_tile_shape_invariance_bitwise():
         q = quantize(precision, psi, n, V, P)
         results = []
         for tile in [(0, 0), (1, 1), (2, 7), (4, 3), (4, 64)]:
-            run = GpuRun(ph, *q, precision=precision, tile_wx=tile[0], tile_rows=tile[1])
+            run = GpuRun(ph, *q, precision=precision, tile_wx=tile[0], tile_rows=tile[1],
+                         kernel=phx.PHX_KERNEL_STAGE)
             run.step(12)
             results.append(run.state())
             run.close()
@@ -125,11 +146,12 @@ def test_conservative_256_full_run(precision):
     assert e_psi <= TOL[precision]
 
 
+@pytest.mark.parametrize("family", FAMILIES)
 @pytest.mark.parametrize("precision", PREC)
-def test_driven_1024(precision):
+def test_driven_1024(precision, family):
     """The driven-dissipative workload at 1024^2 (ring pump 2 P_th, noise start)."""
     ph, psi, n0, P = inputs.driven(1024)
-    e_psi, e_n = compare(ph, psi, n0, None, P, 100, precision)
+    e_psi, e_n = compare(ph, psi, n0, None, P, 100, precision, kernel=family)
     print(f"driven 1024^2 100 steps prec={precision}: psi {e_psi:.3e} n {e_n:.3e}")
     assert e_psi <= TOL[precision] and e_n <= TOL[precision]
 
@@ -142,8 +164,9 @@ def _patch(a, j, i, r):
     return a[..., rows[:, None], cols[None, :]]
 
 
+@pytest.mark.parametrize("family", FAMILIES)
 @pytest.mark.parametrize("steps", [1, 3])
-def test_driven_4096_sampled(steps):
+def test_driven_4096_sampled(steps, family):
     """The benchmark workload (driven, 4096^2, complex64, automatic tile plan):
     sampled cells after `steps` steps against the oracle on patches of radius 4*steps
     (zero boundary outside the patch cannot reach the centre in time)."""
@@ -154,7 +177,7 @@ def test_driven_4096_sampled(steps):
     psi = psi + (3.0 * np.exp(-(X * X + Y * Y) / 400.0))[None]
     n0 = n0 + 10.0 * np.exp(-(X * X + Y * Y) / 900.0)[None]
     q = quantize(precision, psi, n0, None, P)
-    run = GpuRun(ph, *q, precision=precision)
+    run = GpuRun(ph, *q, precision=precision, kernel=family)
     run.step(steps)
     g_psi, g_n = run.state()
     run.close()
@@ -209,11 +232,12 @@ def test_observables_deterministic():
     assert a == b
 
 
-def test_nonfinite_detected_and_reported():
+@pytest.mark.parametrize("family", FAMILIES)
+def test_nonfinite_detected_and_reported(family):
     ph, psi, n, V, P = workload("driven", 130, 40, (0, 0))
     psi = psi.copy()
     psi[0, 20, 64] = np.nan
-    run = GpuRun(ph, psi, n, V, P, precision=C64)
+    run = GpuRun(ph, psi, n, V, P, precision=C64, kernel=family)
     run.step(1)
     assert run.observables()["nonfinite"] > 0
     with pytest.raises(phx.PhxError) as e:
@@ -223,18 +247,20 @@ def test_nonfinite_detected_and_reported():
     run.close()
 
 
-def test_checkpoint_resume_bitwise():
+@pytest.mark.parametrize("family", FAMILIES)
+def test_checkpoint_resume_bitwise(family):
     ph, psi, n, V, P = workload("driven_v", 150, 90, (0, 0), seed=8)
-    a = GpuRun(ph, psi, n, V, P, precision=C128)
+    a = GpuRun(ph, psi, n, V, P, precision=C128, kernel=family)
     a.step(20)
     ref = a.state()
     a.close()
-    b = GpuRun(ph, psi, n, V, P, precision=C128)
-    b.step(10)
+    b = GpuRun(ph, psi, n, V, P, precision=C128, kernel=family)
+    b.step(9)
+    b.step(1)
     mid_psi, mid_n = b.state()
     info = b.solver.info()
     b.close()
-    c = GpuRun(ph, mid_psi, mid_n, V, P, precision=C128)
+    c = GpuRun(ph, mid_psi, mid_n, V, P, precision=C128, kernel=family)
     c.solver.set_info(t=info["t"], steps_accepted=info["steps_accepted"])
     c.step(10)
     out = c.state()
@@ -244,9 +270,22 @@ def test_checkpoint_resume_bitwise():
     assert np.array_equal(out[0], ref[0]) and np.array_equal(out[1], ref[1])
 
 
+def test_step_and_stage_families_agree():
+    """Both RK4 kernel families on the same driven grid (different stores and
+    orders of launches, the same per-cell arithmetic) agree to rounding."""
+    ph, psi, n, V, P = workload("driven_v", 400, 300, (0, 0), seed=14)
+    out = []
+    for fam in (phx.PHX_KERNEL_STAGE, phx.PHX_KERNEL_STEP):
+        run = GpuRun(ph, psi, n, V, P, precision=C128, kernel=fam)
+        run.step(30)
+        out.append(run.state())
+        run.close()
+    assert rel_l2(out[0][0], out[1][0]) < 1e-13 and rel_l2(out[0][1], out[1][1]) < 1e-13
+
+
 def test_kernel_timing_api():
     ph, psi, n, V, P = workload("driven", 512, 256, (0, 0))
-    run = GpuRun(ph, psi, n, V, P, precision=C64)
+    run = GpuRun(ph, psi, n, V, P, precision=C64, kernel=phx.PHX_KERNEL_STAGE)
     run.solver.set_timing(True)
     run.step(3)
     run.observables()
