@@ -89,6 +89,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel", choices=["auto", "stage", "step"], default="auto",
                     help="RK4 kernel family (auto: whole-step kernel)")
+    ap.add_argument("--no-tune", action="store_true", help="skip the tile-shape search before timing")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -119,6 +120,7 @@ def main():
     family = {"auto": phx.PHX_KERNEL_AUTO, "stage": phx.PHX_KERNEL_STAGE, "step": phx.PHX_KERNEL_STEP}[args.kernel]
     cfg = phx.config_from_physics(ph, precision=precision, kernel=family)
     solver = phx.Solver(cfg, psi, n, None, Pd)
+    tune = solver.autotune(reps=10, use_cache=False) if not args.no_tune else None
 
     copy_gbps = copy_bandwidth_gbps(torch)
 
@@ -169,7 +171,8 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f32" if real_bytes == 4 else "f64",
         "data": "synthetic",
         "config": {"workload": workload, "grid": [args.n, args.n], "integrator": "rk4",
-                   "kernel_family": family_name},
+                   "kernel_family": family_name,
+                   "tile": None if tune is None else [tune["tile_wx"], tune["tile_rows"]]},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "step_model_bytes_per_point": step_bytes,

@@ -80,8 +80,9 @@ typedef struct phx_config {
     double rtol, atol;      /* RK45 tolerances (>= 0, not both 0)                        */
     double dt_min, dt_max;  /* RK45 step bounds (0 < dt_min <= dt_max; dt_max may be inf) */
     int32_t kernel;         /* PHX_KERNEL_AUTO picks the fastest applicable kernel family */
-    int32_t tile_wx;        /* 0 = automatic, else waves across x per workgroup: 1, 2, 4 */
-    int32_t tile_rows;      /* 0 = automatic, else rows each wave marches: 1..64         */
+    int32_t tile_wx;        /* 0 = automatic; stage-fused kernels: waves across x (1, 2, 4);
+                               whole-step kernel: waves per workgroup (a tuned shape)      */
+    int32_t tile_rows;      /* 0 = automatic; rows per wave (stage-fused: 1..64)         */
     int32_t reserved;       /* must be 0                                                 */
 } phx_config;
 
@@ -187,6 +188,25 @@ phx_status phx_set_timing(phx_handle *h, int32_t enable);
 
 /* Totals since timing was enabled; synchronizes the handle's stream. */
 phx_status phx_kernel_times(phx_handle *h, phx_timing *out);
+
+/* ---------------------------------------------------------------- tuning
+ * Tile-shape search for the handle's RK4 kernel family.  Each candidate shape is
+ * timed with HIP events over `reps` launches on the handle's stream; the trial
+ * launches read the bound state and write only workspace buffers, so the state is
+ * unchanged.  The fastest shape is adopted for later phx_step calls and reported
+ * in the phx_config encoding (stage-fused: tile_wx = waves across x, tile_rows =
+ * rows per wave; whole-step: tile_wx = waves per workgroup, tile_rows = rows per
+ * wave), so that a caller can cache it and pass it to phx_create next time.
+ * Synchronizes the stream.  PHX_EUNSUPPORTED for RK45 handles. */
+typedef struct phx_tune_result {
+    int32_t family;         /* PHX_KERNEL_STAGE or PHX_KERNEL_STEP                         */
+    int32_t tile_wx, tile_rows;  /* adopted shape                                         */
+    int32_t candidates;     /* shapes timed                                               */
+    double best_us;         /* mean launch time of the adopted shape                      */
+    double default_us;      /* mean launch time of the shape in use before the call      */
+} phx_tune_result;
+
+phx_status phx_autotune(phx_handle *h, int32_t reps, phx_tune_result *out);
 
 /* ---------------------------------------------------------------- batches
  * Many independent driven-dissipative scalar instances (Eq. PULSE_psi/res with one

@@ -33,27 +33,28 @@ struct StepArgs {
     unsigned int* flag;
 };
 
-// value held by lane-1 (lane 0 receives 0) and by lane+1 (lane 63 receives 0)
+// value held by lane-1 (lane 0 receives 0) and by lane+1 (lane 63 receives 0):
+// DPP wave shifts by one lane; out-of-range lanes read 0 (bound control).
 __device__ __forceinline__ float lane_prev(float v)
 {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, false));
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x138, 0xf, 0xf, true));
 }
 __device__ __forceinline__ float lane_next(float v)
 {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, false));
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x130, 0xf, 0xf, true));
 }
 __device__ __forceinline__ double lane_prev(double v)
 {
     const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), 0x138, 0xf, 0xf, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x138, 0xf, 0xf, false);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffll), 0x138, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), 0x138, 0xf, 0xf, true);
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 __device__ __forceinline__ double lane_next(double v)
 {
     const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), 0x130, 0xf, 0xf, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x130, 0xf, 0xf, false);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffll), 0x130, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), 0x130, 0xf, 0xf, true);
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
@@ -66,7 +67,7 @@ __device__ __forceinline__ int wrap_any(int g, int n, int bc)
     return m < 0 ? m + n : m;
 }
 
-template <typename R, bool RES, bool HASV, int WAVES, int ROWS>
+template <typename R, bool RES, bool HASV, bool GHOSTS, int WAVES, int ROWS>
 __global__ __launch_bounds__(WAVES * 64) void rk4_step_kernel(const StepArgs<R> a)
 {
     using C = typename cvec<R>::type;
@@ -89,7 +90,7 @@ __global__ __launch_bounds__(WAVES * 64) void rk4_step_kernel(const StepArgs<R> 
 #pragma unroll
     for (int k = 0; k < ROWS; ++k) {
         const int rj = wrap_any(row0 + k, a.ny, a.bcy);
-        const bool g = ci < 0 || rj < 0;
+        const bool g = GHOSTS && (ci < 0 || rj < 0);
         ghost |= (g ? 1u : 0u) << k;
         const int idx = g ? 0 : rj * a.nx + ci;
         const C v = a.psi_in[idx];
@@ -134,7 +135,7 @@ __global__ __launch_bounds__(WAVES * 64) void rk4_step_kernel(const StepArgs<R> 
             rhs_cell<R, 1>(a.c, U, M, D, nn, HASV ? vv[k] : R(0), f, rho);
             R fn = R(0);
             if (RES) fn = pp[k] - (a.c.gamma_r + a.c.R_ * rho[0]) * nn[0];
-            const bool g = (ghost >> k) & 1u;
+            const bool g = GHOSTS && ((ghost >> k) & 1u);
             if (s == 1) {
                 acc[k] = f[0];
                 if (RES) accn[k] = fn;
@@ -151,8 +152,8 @@ __global__ __launch_bounds__(WAVES * 64) void rk4_step_kernel(const StepArgs<R> 
                 nv = C{p0[k].x + a.dt6 * (acc[k].x + f[0].x), p0[k].y + a.dt6 * (acc[k].y + f[0].y)};
                 if (RES) nnv = n0[k] + a.dt6 * (accn[k] + fn);
             }
-            y[k] = g ? czero<C>() : nv;
-            if (RES) yn[k] = g ? R(0) : nnv;
+            y[k] = (GHOSTS && g) ? czero<C>() : nv;
+            if (RES) yn[k] = (GHOSTS && g) ? R(0) : nnv;
             prev = cur;
         }
     }
@@ -178,46 +179,73 @@ __global__ __launch_bounds__(WAVES * 64) void rk4_step_kernel(const StepArgs<R> 
     if (bad) a.flag[0] = 1u;  // benign race: every writer stores 1
 }
 
+// GHOSTS: some boundary is zero, so region cells outside the grid must be held at 0
+// after every stage; with periodic boundaries in both directions there are none.
 template <typename R, bool RES, bool HASV, int WAVES, int ROWS>
 static hipError_t launch_step_t(const StepArgs<R>& a, hipStream_t s)
 {
-    rk4_step_kernel<R, RES, HASV, WAVES, ROWS><<<a.tiles, WAVES * 64, 0, s>>>(a);
+    if (a.bcx == PHX_BC_ZERO || a.bcy == PHX_BC_ZERO)
+        rk4_step_kernel<R, RES, HASV, true, WAVES, ROWS><<<a.tiles, WAVES * 64, 0, s>>>(a);
+    else
+        rk4_step_kernel<R, RES, HASV, false, WAVES, ROWS><<<a.tiles, WAVES * 64, 0, s>>>(a);
     return hipGetLastError();
 }
 
-// Region height per precision: 8 waves of 8 rows (64) for float, 8 waves of 4 rows
-// (32) for double, which keeps the register footprint per lane without spills.
-template <typename R> struct StepShape;
-template <> struct StepShape<float> { static constexpr int WAVES = 8, ROWS = 8; };
-template <> struct StepShape<double> { static constexpr int WAVES = 8, ROWS = 4; };
+// Region shapes (waves per workgroup, rows per wave) instantiated per precision.
+// A region of WAVES*ROWS rows yields WAVES*ROWS - 8 output rows; taller regions
+// recompute less halo, shorter ones need fewer registers per lane (more waves
+// per SIMD).  The first entry is the default; phx_autotune measures them all.
+static const StepShapeId kFloatShapes[] = {{16, 4}, {8, 8}, {8, 4}, {12, 6}, {8, 6}};
+static const StepShapeId kDoubleShapes[] = {{8, 4}, {16, 2}, {8, 2}};
 
-int step_tile_rows(int precision)
+int step_shapes(int precision, const StepShapeId** out)
 {
-    return precision == PHX_C64 ? StepShape<float>::WAVES * StepShape<float>::ROWS - 8
-                                : StepShape<double>::WAVES * StepShape<double>::ROWS - 8;
+    if (precision == PHX_C64) {
+        *out = kFloatShapes;
+        return (int)(sizeof(kFloatShapes) / sizeof(kFloatShapes[0]));
+    }
+    *out = kDoubleShapes;
+    return (int)(sizeof(kDoubleShapes) / sizeof(kDoubleShapes[0]));
+}
+
+template <typename R, bool RES, bool HASV>
+static hipError_t launch_step_shape(const StepShapeId& sh, const StepArgs<R>& a, hipStream_t s)
+{
+    if (sizeof(R) == 4) {
+        if (sh.waves == 16 && sh.rows == 4) return launch_step_t<R, RES, HASV, 16, 4>(a, s);
+        if (sh.waves == 8 && sh.rows == 8) return launch_step_t<R, RES, HASV, 8, 8>(a, s);
+        if (sh.waves == 8 && sh.rows == 4) return launch_step_t<R, RES, HASV, 8, 4>(a, s);
+        if (sh.waves == 12 && sh.rows == 6) return launch_step_t<R, RES, HASV, 12, 6>(a, s);
+        if (sh.waves == 8 && sh.rows == 6) return launch_step_t<R, RES, HASV, 8, 6>(a, s);
+    } else {
+        if (sh.waves == 8 && sh.rows == 4) return launch_step_t<R, RES, HASV, 8, 4>(a, s);
+        if (sh.waves == 16 && sh.rows == 2) return launch_step_t<R, RES, HASV, 16, 2>(a, s);
+        if (sh.waves == 8 && sh.rows == 2) return launch_step_t<R, RES, HASV, 8, 2>(a, s);
+    }
+    return hipErrorInvalidValue;
 }
 
 template <typename R>
-hipError_t launch_rk4_step(bool reservoir, bool has_v, const StepArgs<R>& a, hipStream_t s)
+hipError_t launch_rk4_step(bool reservoir, bool has_v, const StepShapeId& sh, const StepArgs<R>& a,
+                           hipStream_t s)
 {
-    constexpr int W = StepShape<R>::WAVES, K = StepShape<R>::ROWS;
-    if (reservoir) return has_v ? launch_step_t<R, true, true, W, K>(a, s) : launch_step_t<R, true, false, W, K>(a, s);
-    return has_v ? launch_step_t<R, false, true, W, K>(a, s) : launch_step_t<R, false, false, W, K>(a, s);
+    if (reservoir) return has_v ? launch_step_shape<R, true, true>(sh, a, s) : launch_step_shape<R, true, false>(sh, a, s);
+    return has_v ? launch_step_shape<R, false, true>(sh, a, s) : launch_step_shape<R, false, false>(sh, a, s);
 }
 
+// Arguments of one whole step from `src` to `dst` (state buffers) with shape sh.
 template <typename R>
-phx_status rk4_fused_steps(phx_handle* h, int64_t n)
+static StepArgs<R> step_args(const phx_handle* h, const StepShapeId& sh, const void* src, const void* src_n,
+                             void* dst, void* dst_n)
 {
     using C = typename cvec<R>::type;
     const phx_config& c = h->cfg;
-    const size_t rs = sizeof(R);
-    const size_t cells = (size_t)c.nx * c.ny;
     StepArgs<R> a{};
     a.nx = c.nx;
     a.ny = c.ny;
     a.bcx = c.bc_x;
     a.bcy = c.bc_y;
-    const int oh = step_tile_rows(c.precision);
+    const int oh = sh.waves * sh.rows - 8;
     a.tiles_x = (c.nx + 55) / 56;
     a.tiles = a.tiles_x * ((c.ny + oh - 1) / oh);
     a.c = make_coef<R>(c);
@@ -227,8 +255,34 @@ phx_status rk4_fused_steps(phx_handle* h, int64_t n)
     a.V = (const R*)h->f.V;
     a.P = (const R*)h->f.P;
     a.flag = (unsigned int*)(h->ws + h->L.flag);
-    C* S[2] = {(C*)h->f.psi, (C*)(h->ws + h->L.alt)};
-    R* SN[2] = {(R*)h->f.n, c.reservoir ? (R*)(h->ws + h->L.alt_n) : nullptr};
+    a.psi_in = (const C*)src;
+    a.n_in = (const R*)src_n;
+    a.psi_out = (C*)dst;
+    a.n_out = (R*)dst_n;
+    return a;
+}
+
+// One trial launch for the tuner: reads the caller's state, writes the workspace
+// copy, so the state is left unchanged.
+template <typename R>
+hipError_t rk4_step_trial(phx_handle* h, const StepShapeId& sh)
+{
+    const StepArgs<R> a = step_args<R>(h, sh, h->f.psi, h->f.n, h->ws + h->L.alt,
+                                       h->cfg.reservoir ? h->ws + h->L.alt_n : nullptr);
+    return launch_rk4_step<R>(h->cfg.reservoir != 0, h->f.V != nullptr, sh, a, h->stream);
+}
+
+template hipError_t rk4_step_trial<float>(phx_handle*, const StepShapeId&);
+template hipError_t rk4_step_trial<double>(phx_handle*, const StepShapeId&);
+
+template <typename R>
+phx_status rk4_fused_steps(phx_handle* h, int64_t n)
+{
+    const phx_config& c = h->cfg;
+    const size_t rs = sizeof(R);
+    const size_t cells = (size_t)c.nx * c.ny;
+    void* S[2] = {h->f.psi, h->ws + h->L.alt};
+    void* SN[2] = {h->f.n, c.reservoir ? h->ws + h->L.alt_n : nullptr};
     int cur = 0;
     if (n & 1) {
         // odd count: start from the workspace copy so that the last step lands in
@@ -239,14 +293,12 @@ phx_status rk4_fused_steps(phx_handle* h, int64_t n)
         cur = 1;
     }
     const bool res = c.reservoir != 0, hv = h->f.V != nullptr;
+    const StepShapeId sh = h->step_shape;
     for (int64_t k = 0; k < n; ++k) {
-        a.psi_in = S[cur];
-        a.n_in = SN[cur];
-        a.psi_out = S[cur ^ 1];
-        a.n_out = SN[cur ^ 1];
+        const StepArgs<R> a = step_args<R>(h, sh, S[cur], SN[cur], S[cur ^ 1], SN[cur ^ 1]);
         hipEvent_t t0 = nullptr;
         hipError_t e = timing_begin(h, &t0);
-        if (e == hipSuccess) e = launch_rk4_step<R>(res, hv, a, h->stream);
+        if (e == hipSuccess) e = launch_rk4_step<R>(res, hv, sh, a, h->stream);
         if (e == hipSuccess) e = timing_end(h, t0, K_RK4_STEP);
         if (e != hipSuccess) return fail(PHX_EHIP, "RK4 step kernel launch: %s", hipGetErrorString(e));
         cur ^= 1;

@@ -10,6 +10,11 @@
 
 namespace phx {
 
+// Region shape of the whole-step RK4 kernel: waves per workgroup, rows per wave.
+struct StepShapeId {
+    int waves, rows;
+};
+
 struct TilePlan {
     TileShape ts;
     int tiles_x;
@@ -42,6 +47,7 @@ size_t align_up(size_t x);
 phx_status validate_config(const phx_config* c);
 Layout make_layout(const phx_config& c);
 TilePlan plan_tiles(int nx, int ny, int wx, int rows);
+bool valid_step_shape(int precision, int waves, int rows);
 template <typename R> Coef<R> make_coef(const phx_config& c);
 
 }  // namespace phx
@@ -63,6 +69,8 @@ struct phx_handle {
     void* other;
     void* cur_n;
     void* other_n;
+    phx::StepShapeId step_shape;  // whole-step RK4 region shape in use
+    phx::TilePlan stage_tiles;    // stage-fused RK4 tile plan in use
     int fsal;               // index of the buffer that holds K1 of the current state
     bool k1_valid;
     // kernel timing (phx_set_timing / phx_kernel_times)
@@ -91,6 +99,9 @@ const void* state_psi(const phx_handle* h);
 const void* state_n(const phx_handle* h);
 phx_status create_rk45(phx_handle* h);
 template <typename R> phx_status rk4_fused_steps(phx_handle* h, int64_t n);
+template <typename R> hipError_t rk4_step_trial(phx_handle* h, const StepShapeId& sh);
+template <typename R> hipError_t rk4_stage_trial(phx_handle* h, const TileShape& ts);
+int step_shapes(int precision, const StepShapeId** out);
 int rk4_family(const phx_config& c);
 phx_status step_rk45(phx_handle* h, int64_t n, phx_info* out);
 phx_status set_info_rk45(phx_handle* h, const phx_info* in);

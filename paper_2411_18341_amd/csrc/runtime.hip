@@ -56,9 +56,15 @@ phx_status validate_config(const phx_config* c)
     if (c->reserved != 0) return fail(PHX_EINVAL, "reserved field must be 0");
     if (c->kernel == PHX_KERNEL_STEP && (c->integrator != PHX_RK4 || c->components != 1))
         return fail(PHX_EUNSUPPORTED, "the whole-step kernel covers RK4 with one component");
-    if ((c->tile_wx != 0 && c->tile_wx != 1 && c->tile_wx != 2 && c->tile_wx != 4) ||
-        c->tile_rows < 0 || c->tile_rows > 64 || ((c->tile_wx == 0) != (c->tile_rows == 0)))
-        return fail(PHX_EINVAL, "tile_wx must be 0, 1, 2 or 4 and tile_rows 0..64, both 0 or both set");
+    if ((c->tile_wx == 0) != (c->tile_rows == 0)) return fail(PHX_EINVAL, "tile_wx and tile_rows: both 0 or both set");
+    if (c->tile_wx != 0) {
+        if (c->integrator == PHX_RK4 && rk4_family(*c) == PHX_KERNEL_STEP) {
+            if (!valid_step_shape(c->precision, c->tile_wx, c->tile_rows))
+                return fail(PHX_EINVAL, "tile %d x %d is not a whole-step kernel shape", c->tile_wx, c->tile_rows);
+        } else if ((c->tile_wx != 1 && c->tile_wx != 2 && c->tile_wx != 4) || c->tile_rows < 1 || c->tile_rows > 64) {
+            return fail(PHX_EINVAL, "tile_wx must be 1, 2 or 4 and tile_rows 1..64");
+        }
+    }
     if (!finite_pos(c->hbar) || !finite_pos(c->mass)) return fail(PHX_EINVAL, "hbar, mass must be finite and > 0");
     const double coefs[] = {c->g, c->g_x, c->g_r, c->R, c->gamma_c, c->gamma_r, c->delta_lt};
     for (double x : coefs)
@@ -91,7 +97,8 @@ Layout make_layout(const phx_config& c)
     auto take = [&](size_t bytes) { size_t o = off; off += align_up(bytes); return o; };
     L.flag = take(256);
     L.obs = take(OBS_SLOTS * sizeof(double));
-    L.tiles = plan_tiles(c.nx, c.ny, c.tile_wx, c.tile_rows);
+    const bool stage_tiles = c.integrator == PHX_RK4 && rk4_family(c) == PHX_KERNEL_STAGE;
+    L.tiles = plan_tiles(c.nx, c.ny, stage_tiles ? c.tile_wx : 0, stage_tiles ? c.tile_rows : 0);
     L.obs_blocks = L.tiles.tiles < 1024 ? L.tiles.tiles : 1024;
     L.partials = take((size_t)L.obs_blocks * OBS_SLOTS * sizeof(double));
     if (c.integrator == PHX_RK4) {
@@ -118,6 +125,15 @@ Layout make_layout(const phx_config& c)
     }
     L.total = off;
     return L;
+}
+
+bool valid_step_shape(int precision, int waves, int rows)
+{
+    const StepShapeId* sh;
+    const int n = step_shapes(precision, &sh);
+    for (int k = 0; k < n; ++k)
+        if (sh[k].waves == waves && sh[k].rows == rows) return true;
+    return false;
 }
 
 // RK4 kernel family: the whole-step kernel (one launch per step, state read and
@@ -235,6 +251,13 @@ phx_status phx_create(const phx_config* cfg, const phx_fields* f, void* stream,
     }
     memset(h->host, 0, (OBS_SLOTS + 2) * sizeof(double));
     h->cur = f->psi;
+    h->stage_tiles = L.tiles;
+    {
+        const StepShapeId* shapes;
+        step_shapes(cfg->precision, &shapes);
+        h->step_shape = shapes[0];
+        if (cfg->tile_wx != 0 && L.family == PHX_KERNEL_STEP) h->step_shape = StepShapeId{cfg->tile_wx, cfg->tile_rows};
+    }
     if (cfg->integrator == PHX_RK45) {
         s = create_rk45(h);
         if (s != PHX_OK) {
@@ -270,9 +293,9 @@ static phx_status rk4_steps(phx_handle* h, int64_t n)
     a.bcx = c.bc_x;
     a.bcy = c.bc_y;
     a.comps = c.components;
-    a.tiles_x = L.tiles.tiles_x;
-    a.tiles = L.tiles.tiles;
-    a.ts = L.tiles.ts;
+    a.tiles_x = h->stage_tiles.tiles_x;
+    a.tiles = h->stage_tiles.tiles;
+    a.ts = h->stage_tiles.ts;
     a.cstride = (int64_t)c.nx * c.ny;
     a.c = make_coef<R>(c);
     a.V = (const R*)h->f.V;
@@ -313,6 +336,47 @@ static phx_status rk4_steps(phx_handle* h, int64_t n)
     }
     return PHX_OK;
 }
+
+// Trial launches of the stage-fused kernels for the tuner: stage 1 from the state
+// into the workspace, then stage 2 between workspace buffers with shape ts.  The
+// caller's arrays are only read.
+namespace phx {
+template <typename R>
+hipError_t rk4_stage_trial(phx_handle* h, const TileShape& ts)
+{
+    using C = typename cvec<R>::type;
+    const phx_config& c = h->cfg;
+    const Layout& L = h->L;
+    Rk4Args<R> a{};
+    a.nx = c.nx;
+    a.ny = c.ny;
+    a.bcx = c.bc_x;
+    a.bcy = c.bc_y;
+    a.comps = c.components;
+    const TilePlan tp = plan_tiles(c.nx, c.ny, ts.wx, ts.rows);
+    a.tiles_x = tp.tiles_x;
+    a.tiles = tp.tiles;
+    a.ts = tp.ts;
+    a.cstride = (int64_t)c.nx * c.ny;
+    a.c = make_coef<R>(c);
+    a.V = (const R*)h->f.V;
+    a.P = (const R*)h->f.P;
+    a.flag = (unsigned int*)(h->ws + L.flag);
+    a.psi = (const C*)h->f.psi;
+    a.n = (const R*)h->f.n;
+    a.acc = (C*)(h->ws + L.acc);
+    a.accn = c.reservoir ? (R*)(h->ws + L.accn) : nullptr;
+    a.y = (const C*)(h->ws + L.y[0]);
+    a.yn = c.reservoir ? (const R*)(h->ws + L.yn[0]) : nullptr;
+    a.y_out = (C*)(h->ws + L.y[1]);
+    a.yn_out = c.reservoir ? (R*)(h->ws + L.yn[1]) : nullptr;
+    a.a_dt = (R)(0.5 * c.dt);
+    return launch_rk4_stage<R>(2, c.reservoir != 0, h->f.V != nullptr, a, h->stream);
+}
+
+template hipError_t rk4_stage_trial<float>(phx_handle*, const TileShape&);
+template hipError_t rk4_stage_trial<double>(phx_handle*, const TileShape&);
+}  // namespace phx
 
 phx_status phx_step(phx_handle* h, int64_t n_steps, phx_info* out)
 {

@@ -88,6 +88,14 @@ class phx_timing(ctypes.Structure):
                 for k in range(self.count)}
 
 
+class phx_tune_result(ctypes.Structure):
+    _fields_ = [("family", ctypes.c_int32), ("tile_wx", ctypes.c_int32), ("tile_rows", ctypes.c_int32),
+                ("candidates", ctypes.c_int32), ("best_us", ctypes.c_double), ("default_us", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class phx_instance(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("param_index", ctypes.c_int32),
                 ("reserved", ctypes.c_int32), ("offset", ctypes.c_int64)]
@@ -105,7 +113,7 @@ class phx_batch_desc(ctypes.Structure):
 # names of every exported entry point (kept in step with include/phx.h)
 ENTRY_POINTS = ("phx_workspace_bytes", "phx_create", "phx_step", "phx_observables", "phx_get_info",
                 "phx_set_info", "phx_destroy", "phx_last_error", "phx_set_timing", "phx_kernel_times",
-                "phx_batch_workspace_bytes", "phx_batch_step")
+                "phx_autotune", "phx_batch_workspace_bytes", "phx_batch_step")
 
 _lib = None
 
@@ -143,6 +151,8 @@ def load(path: str | None = None):
     lib.phx_set_timing.restype = st
     lib.phx_kernel_times.argtypes = [vp, P(phx_timing)]
     lib.phx_kernel_times.restype = st
+    lib.phx_autotune.argtypes = [vp, ctypes.c_int32, P(phx_tune_result)]
+    lib.phx_autotune.restype = st
     lib.phx_batch_workspace_bytes.argtypes = [P(phx_batch_desc), P(ctypes.c_size_t)]
     lib.phx_batch_workspace_bytes.restype = st
     lib.phx_batch_step.argtypes = [P(phx_batch_desc), ctypes.c_int64, vp]
@@ -217,6 +227,12 @@ def phx_kernel_times(h) -> phx_timing:
     return out
 
 
+def phx_autotune(h, reps: int = 10) -> phx_tune_result:
+    out = phx_tune_result()
+    _check(load().phx_autotune(h, int(reps), ctypes.byref(out)))
+    return out
+
+
 def phx_batch_workspace_bytes(desc: phx_batch_desc) -> int:
     out = ctypes.c_size_t(0)
     _check(load().phx_batch_workspace_bytes(ctypes.byref(desc), ctypes.byref(out)))
@@ -251,6 +267,45 @@ def config_from_physics(ph, **kw) -> phx_config:
     d.update(kw)
     nx, ny, dx = d.pop("nx"), d.pop("ny"), d.pop("dx")
     return make_config(nx, ny, dx, **d)
+
+
+# ------------------------------------------------------------ tuning cache
+
+def tune_cache_path() -> str:
+    """JSON file of tuned tile shapes (PHX_TUNE_CACHE, else ~/.cache/phx_tune.json)."""
+    return os.environ.get("PHX_TUNE_CACHE") or os.path.join(os.path.expanduser("~"), ".cache", "phx_tune.json")
+
+
+def tune_key(cfg: phx_config, has_v: bool, device_name: str = "") -> str:
+    return (f"{device_name}|k{cfg.kernel}|p{cfg.precision}|{cfg.nx}x{cfg.ny}|c{cfg.components}|"
+            f"r{cfg.reservoir}|v{int(has_v)}|bc{cfg.bc_x}{cfg.bc_y}")
+
+
+def _read_cache(path):
+    import json
+    try:
+        with open(path) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def cached_shape(cfg: phx_config, has_v: bool, device_name: str = ""):
+    """(tile_wx, tile_rows) stored for this configuration, or None."""
+    v = _read_cache(tune_cache_path()).get(tune_key(cfg, has_v, device_name))
+    return None if v is None else (int(v["tile_wx"]), int(v["tile_rows"]))
+
+
+def store_shape(cfg: phx_config, has_v: bool, result: phx_tune_result, device_name: str = "") -> None:
+    import json
+    path = tune_cache_path()
+    d = _read_cache(path)
+    d[tune_key(cfg, has_v, device_name)] = result.as_dict()
+    os.makedirs(os.path.dirname(path) or ".", exist_ok=True)
+    tmp = path + f".{os.getpid()}.tmp"
+    with open(tmp, "w") as f:
+        json.dump(d, f, indent=1)
+    os.replace(tmp, path)
 
 
 def torch_dtypes(precision: int):
@@ -303,6 +358,28 @@ class Solver:
 
     def kernel_times(self) -> dict:
         return phx_kernel_times(self.handle).as_dict()
+
+    def autotune(self, reps: int = 10, use_cache: bool = True) -> dict:
+        """Pick the fastest tile shape for this grid (phx_autotune); results are
+        cached per device and configuration in the JSON tuning cache."""
+        import torch
+        dev = torch.cuda.get_device_name(self.psi.device)
+        has_v = self.V is not None
+        if use_cache:
+            shp = cached_shape(self.cfg, has_v, dev)
+            if shp is not None and shp != (self.cfg.tile_wx, self.cfg.tile_rows):
+                cfg = phx_config.from_buffer_copy(self.cfg)
+                cfg.tile_wx, cfg.tile_rows = shp
+                phx_destroy(self.handle)
+                self.cfg = cfg
+                self.handle = phx_create(cfg, self.fields, self.stream.cuda_stream)
+                return {"tile_wx": shp[0], "tile_rows": shp[1], "cached": True}
+        r = phx_autotune(self.handle, reps)
+        if use_cache:
+            store_shape(self.cfg, has_v, r, dev)
+        d = r.as_dict()
+        d["cached"] = False
+        return d
 
     def close(self):
         if getattr(self, "handle", None):

@@ -45,6 +45,7 @@ int main(void) {
   printf("phx_obs %zu\n", sizeof(phx_obs)); F(phx_obs, energy) F(phx_obs, max_density) F(phx_obs, nonfinite)
   printf("phx_info %zu\n", sizeof(phx_info)); F(phx_info, steps_rejected) F(phx_info, nonfinite)
   printf("phx_timing %zu\n", sizeof(phx_timing)); F(phx_timing, launches) F(phx_timing, ms_total)
+  printf("phx_tune_result %zu\n", sizeof(phx_tune_result)); F(phx_tune_result, best_us) F(phx_tune_result, default_us)
   printf("phx_instance %zu\n", sizeof(phx_instance)); F(phx_instance, offset)
   printf("phx_batch_desc %zu\n", sizeof(phx_batch_desc)); F(phx_batch_desc, params) F(phx_batch_desc, psi)
   F(phx_batch_desc, workspace_bytes)
@@ -65,7 +66,8 @@ def test_ctypes_structures_match_c_layout(tmp_path):
     import ctypes
     for cname, cls in (("phx_config", phx.phx_config), ("phx_fields", phx.phx_fields), ("phx_obs", phx.phx_obs),
                        ("phx_info", phx.phx_info), ("phx_timing", phx.phx_timing),
-                       ("phx_instance", phx.phx_instance), ("phx_batch_desc", phx.phx_batch_desc)):
+                       ("phx_tune_result", phx.phx_tune_result), ("phx_instance", phx.phx_instance),
+                       ("phx_batch_desc", phx.phx_batch_desc)):
         assert got[cname] == ctypes.sizeof(cls), cname
         for key, off in got.items():
             if key.startswith(cname + "."):
@@ -163,3 +165,28 @@ def test_stage_fused_byte_model():
     assert bytemodel.rk4_stage_fused(4, True, False)["step"] == 220
     assert bytemodel.rk4_stage_fused(8, True, False)["step"] == 440
     assert bytemodel.state_minimum(4, True, False) == 28
+
+
+def test_tile_shape_validation_per_family():
+    # stage-fused kernels: waves across x in {1, 2, 4}, rows 1..64
+    phx.phx_workspace_bytes(good_config(kernel=phx.PHX_KERNEL_STAGE, tile_wx=2, tile_rows=64))
+    with pytest.raises(phx.PhxError):
+        phx.phx_workspace_bytes(good_config(kernel=phx.PHX_KERNEL_STAGE, tile_wx=8, tile_rows=4))
+    # whole-step kernel: only the instantiated region shapes
+    phx.phx_workspace_bytes(good_config(tile_wx=16, tile_rows=4))
+    phx.phx_workspace_bytes(good_config(tile_wx=8, tile_rows=8))
+    phx.phx_workspace_bytes(good_config(precision=phx.PHX_C128, tile_wx=16, tile_rows=2))
+    for bad in [(4, 4), (16, 8), (2, 3)]:
+        with pytest.raises(phx.PhxError) as e:
+            phx.phx_workspace_bytes(good_config(tile_wx=bad[0], tile_rows=bad[1]))
+        assert e.value.status == phx.PHX_EINVAL
+
+
+def test_tune_cache_roundtrip(tmp_path, monkeypatch):
+    monkeypatch.setenv("PHX_TUNE_CACHE", str(tmp_path / "tune.json"))
+    cfg = good_config()
+    assert phx.cached_shape(cfg, False, "dev") is None
+    r = phx.phx_tune_result(phx.PHX_KERNEL_STEP, 8, 4, 5, 10.0, 12.0)
+    phx.store_shape(cfg, False, r, "dev")
+    assert phx.cached_shape(cfg, False, "dev") == (8, 4)
+    assert phx.cached_shape(cfg, True, "dev") is None

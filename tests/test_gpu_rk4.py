@@ -270,6 +270,46 @@ def test_checkpoint_resume_bitwise(family):
     assert np.array_equal(out[0], ref[0]) and np.array_equal(out[1], ref[1])
 
 
+STEP_SHAPES = {C64: [(16, 4), (8, 8), (8, 4), (12, 6), (8, 6)], C128: [(8, 4), (16, 2), (8, 2)]}
+
+
+@pytest.mark.parametrize("precision", PREC)
+@pytest.mark.parametrize("bc", [(0, 0), (1, 0)])
+def test_step_kernel_every_shape(precision, bc):
+    """Every region shape the tuner may pick gives oracle parity."""
+    ph, psi, n, V, P = workload("driven_v", 170, 131, bc, seed=15)
+    for shape in STEP_SHAPES[precision]:
+        e_psi, e_n = compare(ph, psi, n, V, P, 6, precision, kernel=phx.PHX_KERNEL_STEP,
+                             tile_wx=shape[0], tile_rows=shape[1])
+        assert e_psi <= TOL[precision] and e_n <= TOL[precision], (shape, e_psi, e_n)
+
+
+@pytest.mark.parametrize("family", [phx.PHX_KERNEL_STAGE, phx.PHX_KERNEL_STEP])
+@pytest.mark.parametrize("precision", PREC)
+def test_autotune_keeps_state_and_parity(family, precision, tmp_path, monkeypatch):
+    """phx_autotune times every candidate shape without touching the bound state,
+    and stepping with the adopted shape keeps oracle parity."""
+    monkeypatch.setenv("PHX_TUNE_CACHE", str(tmp_path / "tune.json"))
+    ph, psi, n, V, P = workload("driven_v", 300, 200, (0, 1), seed=16)
+    q = quantize(precision, psi, n, V, P)
+    run = GpuRun(ph, *q, precision=precision, kernel=family)
+    before = run.state()
+    r = run.solver.autotune(reps=2, use_cache=True)
+    after = run.state()
+    assert np.array_equal(before[0], after[0]) and np.array_equal(before[1], after[1])
+    assert r["candidates"] >= 3 and r["best_us"] > 0 and r["best_us"] <= r["default_us"]
+    # a second solver picks the shape from the cache
+    run2 = GpuRun(ph, *q, precision=precision, kernel=family)
+    r2 = run2.solver.autotune(reps=2, use_cache=True)
+    assert r2["cached"] and (r2["tile_wx"], r2["tile_rows"]) == (r["tile_wx"], r["tile_rows"])
+    run2.close()
+    run.step(10)
+    g_psi, g_n = run.state()
+    run.close()
+    o_psi, o_n = oracle_rk4(ph, *q, 10)
+    assert rel_l2(g_psi, o_psi) <= TOL[precision] and rel_l2(g_n, o_n) <= TOL[precision]
+
+
 def test_step_and_stage_families_agree():
     """Both RK4 kernel families on the same driven grid (different stores and
     orders of launches, the same per-cell arithmetic) agree to rounding."""
