@@ -8,6 +8,7 @@
 // halo) and written once; the stage arguments, K sums and reservoir values stay in
 // registers for the whole step.
 //
+// Stage s evaluates only the region rows [s, H-s) that the output depends on.
 // Lane l of every wave owns region column l; wave w owns rows [w*ROWS, (w+1)*ROWS).
 // x-neighbours come from the adjacent lanes by DPP wave shifts, y-neighbours from
 // the lane's own registers except at the wave's first and last row, which are
@@ -122,6 +123,13 @@ __global__ __launch_bounds__(WAVES * 64) void rk4_step_kernel(const StepArgs<R> 
         for (int k = 0; k < ROWS; ++k) {
             const C cur = y[k];
             const C nxt = (k + 1 < ROWS) ? y[k + 1] : below;
+            // Stage s only feeds the rows [s, H-s) of the region that the output
+            // rows depend on; the branch is uniform over the wave.
+            const int r = wave * ROWS + k;
+            if (r < s || r >= H - s) {
+                prev = cur;
+                continue;
+            }
             Row3<C> U[1], M[1], D[1];
             M[0].c = cur;
             M[0].l = C{lane_prev(cur.x), lane_prev(cur.y)};
@@ -195,8 +203,8 @@ static hipError_t launch_step_t(const StepArgs<R>& a, hipStream_t s)
 // A region of WAVES*ROWS rows yields WAVES*ROWS - 8 output rows; taller regions
 // recompute less halo, shorter ones need fewer registers per lane (more waves
 // per SIMD).  The first entry is the default; phx_autotune measures them all.
-static const StepShapeId kFloatShapes[] = {{16, 4}, {8, 8}, {8, 4}, {12, 6}, {8, 6}};
-static const StepShapeId kDoubleShapes[] = {{8, 4}, {16, 2}, {8, 2}};
+static const StepShapeId kFloatShapes[] = {{8, 4}, {16, 4}, {8, 8}, {12, 4}, {12, 6}, {8, 6}, {4, 8}, {16, 6}};
+static const StepShapeId kDoubleShapes[] = {{8, 4}, {16, 2}, {8, 2}, {16, 4}, {12, 4}, {4, 4}};
 
 int step_shapes(int precision, const StepShapeId** out)
 {
@@ -211,17 +219,15 @@ int step_shapes(int precision, const StepShapeId** out)
 template <typename R, bool RES, bool HASV>
 static hipError_t launch_step_shape(const StepShapeId& sh, const StepArgs<R>& a, hipStream_t s)
 {
-    if (sizeof(R) == 4) {
-        if (sh.waves == 16 && sh.rows == 4) return launch_step_t<R, RES, HASV, 16, 4>(a, s);
-        if (sh.waves == 8 && sh.rows == 8) return launch_step_t<R, RES, HASV, 8, 8>(a, s);
-        if (sh.waves == 8 && sh.rows == 4) return launch_step_t<R, RES, HASV, 8, 4>(a, s);
-        if (sh.waves == 12 && sh.rows == 6) return launch_step_t<R, RES, HASV, 12, 6>(a, s);
-        if (sh.waves == 8 && sh.rows == 6) return launch_step_t<R, RES, HASV, 8, 6>(a, s);
+#define PHX_SHAPE(W, K) \
+    if (sh.waves == W && sh.rows == K) return launch_step_t<R, RES, HASV, W, K>(a, s)
+    if constexpr (sizeof(R) == 4) {
+        PHX_SHAPE(8, 4); PHX_SHAPE(16, 4); PHX_SHAPE(8, 8); PHX_SHAPE(12, 4);
+        PHX_SHAPE(12, 6); PHX_SHAPE(8, 6); PHX_SHAPE(4, 8); PHX_SHAPE(16, 6);
     } else {
-        if (sh.waves == 8 && sh.rows == 4) return launch_step_t<R, RES, HASV, 8, 4>(a, s);
-        if (sh.waves == 16 && sh.rows == 2) return launch_step_t<R, RES, HASV, 16, 2>(a, s);
-        if (sh.waves == 8 && sh.rows == 2) return launch_step_t<R, RES, HASV, 8, 2>(a, s);
+        PHX_SHAPE(8, 4); PHX_SHAPE(16, 2); PHX_SHAPE(8, 2); PHX_SHAPE(16, 4); PHX_SHAPE(12, 4); PHX_SHAPE(4, 4);
     }
+#undef PHX_SHAPE
     return hipErrorInvalidValue;
 }
 

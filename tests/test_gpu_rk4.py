@@ -270,7 +270,8 @@ def test_checkpoint_resume_bitwise(family):
     assert np.array_equal(out[0], ref[0]) and np.array_equal(out[1], ref[1])
 
 
-STEP_SHAPES = {C64: [(16, 4), (8, 8), (8, 4), (12, 6), (8, 6)], C128: [(8, 4), (16, 2), (8, 2)]}
+STEP_SHAPES = {C64: [(8, 4), (16, 4), (8, 8), (12, 4), (12, 6), (8, 6), (4, 8), (16, 6)],
+               C128: [(8, 4), (16, 2), (8, 2), (16, 4), (12, 4), (4, 4)]}
 
 
 @pytest.mark.parametrize("precision", PREC)
