@@ -83,7 +83,8 @@ typedef struct phx_config {
     int32_t tile_wx;        /* 0 = automatic; stage-fused kernels: waves across x (1, 2, 4);
                                whole-step kernel: waves per workgroup (a tuned shape)      */
     int32_t tile_rows;      /* 0 = automatic; rows per wave (stage-fused: 1..64)         */
-    int32_t reserved;       /* must be 0                                                 */
+    int32_t graph_steps;    /* RK4 steps per captured hipGraph chunk replayed by phx_step:
+                               0 = default (64), < 0 = launch every kernel directly        */
 } phx_config;
 
 /* Caller-owned device arrays bound to a handle (borrowed until phx_destroy). */
@@ -144,7 +145,9 @@ phx_status phx_create(const phx_config *cfg, const phx_fields *fields, void *hip
                       phx_handle **out);
 
 /* Advance the bound state.  RK4: n_steps steps of Eqs. rk4_K1-rk4_final (Sec. 2),
- * enqueued asynchronously.  RK45: attempts Dormand-Prince steps until n_steps are
+ * enqueued asynchronously; runs of graph_steps steps are captured once into a
+ * hipGraph (on a private stream of default priority) and replayed on the caller's
+ * stream, the rest is launched directly (also while kernel timing is on).  RK45: attempts Dormand-Prince steps until n_steps are
  * accepted; each attempt reads its error norm back to the host, so the call
  * synchronizes the stream once per attempt.  n_steps >= 0.  *out_or_null receives
  * the progress when not NULL (for RK4 without waiting for the device).
@@ -209,40 +212,45 @@ typedef struct phx_tune_result {
 phx_status phx_autotune(phx_handle *h, int32_t reps, phx_tune_result *out);
 
 /* ---------------------------------------------------------------- batches
- * Many independent driven-dissipative scalar instances (Eq. PULSE_psi/res with one
- * component) on grids of different sizes, advanced together by one persistent
- * kernel launch per RK4 stage.  Instance k uses params[instances[k].param_index]
- * (its nx, ny, precision, components, integrator and kernel fields are ignored and
- * taken from the instance record and the descriptor) on its own slice of packed
- * device buffers. */
+ * Many independent one-component instances (Eq. 1, optionally with the pump-fed
+ * reservoir of Eqs. PULSE_psi / PULSE_res) on grids of different sizes, advanced
+ * together by one persistent whole-step RK4 kernel launch per step: workgroups
+ * walk a list of (instance, region) work items.  Instance k uses
+ * params[instances[k].param_index] for its physics, boundaries and dt (the nx,
+ * ny, components, precision, integrator, kernel and tile fields of the params are
+ * ignored), on its own slice of packed caller-owned device arrays. */
 typedef struct phx_instance {
     int32_t nx, ny;         /* grid of this instance, >= 1                              */
     int32_t param_index;    /* index into phx_batch_desc.params                         */
     int32_t reserved;       /* must be 0                                                */
-    int64_t offset;         /* element offset of this instance in psi, n, P (and V)     */
+    int64_t offset;         /* element offset of this instance in psi, n, P and V       */
 } phx_instance;
 
 typedef struct phx_batch_desc {
     int32_t count;          /* number of instances, >= 1                                */
     int32_t precision;      /* PHX_C64 or PHX_C128 for all instances                    */
-    const phx_instance *instances;  /* host array [count]                              */
-    const phx_config *params;       /* host array [n_params]                           */
+    const phx_instance *instances;  /* host array [count]; slices must not overlap     */
+    const phx_config *params;       /* host array [n_params]; all with the same reservoir flag */
     int32_t n_params;
-    int32_t has_V;          /* 1: V holds a potential slice per instance                */
-    void *psi;              /* packed complex, instance k at [offset, offset + nx*ny)   */
-    void *n;                /* packed real, same offsets                                */
-    const void *P;          /* packed real pump, same offsets                           */
-    const void *V;          /* packed real potential or NULL                            */
-    void *workspace;        /* scratch of at least phx_batch_workspace_bytes            */
+    int32_t check_finite;   /* 1: wait for the stream at the end and report non-finite  */
+    int64_t total_cells;    /* length of each packed array in cells                     */
+    void *psi;              /* packed complex [total_cells], read and written           */
+    void *n;                /* packed real [total_cells] (reservoir), read and written  */
+    const void *P;          /* packed real pump [total_cells] (reservoir)               */
+    const void *V;          /* packed real potential [total_cells], or NULL for V = 0   */
+    void *workspace;        /* scratch of at least phx_batch_workspace_bytes, 256-B aligned */
     size_t workspace_bytes;
 } phx_batch_desc;
 
 /* Workspace bytes phx_batch_step needs for this descriptor (host-only). */
 phx_status phx_batch_workspace_bytes(const phx_batch_desc *desc, size_t *out);
 
-/* Advance every instance of the batch by n_steps RK4 steps (Eqs. rk4_K1-rk4_final),
- * enqueued on hip_stream; instances must not overlap in the packed buffers.
- * Errors: PHX_EINVAL, PHX_EWORKSPACE, PHX_EUNSUPPORTED, PHX_EHIP. */
+/* Advance every instance by n_steps RK4 steps (Eqs. rk4_K1-rk4_final), enqueued on
+ * hip_stream.  Uploads the instance table (synchronizing the stream once), then
+ * one persistent launch per step.  With check_finite = 1 it waits for the stream
+ * at the end and returns PHX_ENONFINITE if any stored value was not finite.
+ * Errors: PHX_EINVAL (bad descriptor, slice outside total_cells or overlapping,
+ * unstable dt), PHX_EWORKSPACE, PHX_EUNSUPPORTED, PHX_EHIP, PHX_ENONFINITE. */
 phx_status phx_batch_step(const phx_batch_desc *desc, int64_t n_steps, void *hip_stream);
 
 #ifdef __cplusplus

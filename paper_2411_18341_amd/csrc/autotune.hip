@@ -52,6 +52,7 @@ static phx_status tune_step(phx_handle* h, int reps, phx_tune_result* out)
         }
     }
     h->step_shape = best;
+    h->graph_dirty = true;
     *out = phx_tune_result{PHX_KERNEL_STEP, best.waves, best.rows, n, best_us, before_us};
     return PHX_OK;
 }
@@ -80,6 +81,7 @@ static phx_status tune_stage(phx_handle* h, int reps, phx_tune_result* out)
         }
     }
     h->stage_tiles = plan_tiles(h->cfg.nx, h->cfg.ny, best.wx, best.rows);
+    h->graph_dirty = true;
     *out = phx_tune_result{PHX_KERNEL_STAGE, best.wx, best.rows, count, best_us, before_us};
     return PHX_OK;
 }

@@ -1,16 +1,276 @@
-// Batched RK4 over many independent driven-dissipative instances.
+// Batched whole-step RK4 over many independent one-component instances on grids of
+// different sizes: one persistent launch per step.  The work list is the
+// concatenation of every instance's regions (56 x (H-8) output cells each, H the
+// region height of the step kernel); a workgroup takes items w = blockIdx.x,
+// blockIdx.x + gridDim.x, ..., finds the instance by binary search over the
+// instances' first item, and runs the same device code as the single-grid
+// whole-step kernel on that instance's slice of the packed arrays.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
 #include "runtime.h"
+#include "step_body.h"
+
+namespace phx {
+
+template <typename R>
+struct BatchInst {
+    int nx, ny, bcx, bcy;
+    int tiles_x, tile0;  // regions across x; first work item of this instance
+    int64_t offset;      // element offset in the packed arrays
+    Coef<R> c;
+    R half_dt, dt, dt6;
+};
+
+template <typename R, bool RES, bool HASV, bool GHOSTS, int WAVES, int ROWS>
+__global__ __launch_bounds__(WAVES * 64) void batch_step_kernel(
+    const BatchInst<R>* __restrict__ inst, int count, int total,
+    const typename cvec<R>::type* psi_in, const R* n_in, typename cvec<R>::type* psi_out, R* n_out,
+    const R* V, const R* P, unsigned int* flag)
+{
+    __shared__ typename cvec<R>::type edge[2][WAVES][2][64];
+    bool bad = false;
+    for (int w = blockIdx.x; w < total; w += gridDim.x) {
+        const int t = xcd_tile(w, total);
+        int lo = 0, hi = count - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (inst[mid].tile0 <= t) lo = mid; else hi = mid - 1;
+        }
+        const BatchInst<R>& I = inst[lo];
+        StepArgs<R> a;
+        a.nx = I.nx;
+        a.ny = I.ny;
+        a.bcx = I.bcx;
+        a.bcy = I.bcy;
+        a.tiles_x = I.tiles_x;
+        a.tiles = 0;
+        a.c = I.c;
+        a.half_dt = I.half_dt;
+        a.dt = I.dt;
+        a.dt6 = I.dt6;
+        a.psi_in = psi_in + I.offset;
+        a.n_in = RES ? n_in + I.offset : nullptr;
+        a.psi_out = psi_out + I.offset;
+        a.n_out = RES ? n_out + I.offset : nullptr;
+        a.V = HASV ? V + I.offset : nullptr;
+        a.P = RES ? P + I.offset : nullptr;
+        a.flag = flag;
+        bad = step_region<R, RES, HASV, GHOSTS, WAVES, ROWS>(a, t - I.tile0, edge) || bad;
+    }
+    if (bad) flag[0] = 1u;  // benign race: every writer stores 1
+}
+
+// region shape of the batched kernel per precision (8 waves x 4 rows)
+constexpr int BW = 8, BR = 4;
+
+template <typename R, bool RES, bool HASV, bool GHOSTS>
+static hipError_t launch_batch_t(int grid, const BatchInst<R>* inst, int count, int total, const void* pi,
+                                 const void* ni, void* po, void* no, const void* V, const void* P,
+                                 unsigned int* flag, hipStream_t s)
+{
+    using C = typename cvec<R>::type;
+    batch_step_kernel<R, RES, HASV, GHOSTS, BW, BR><<<grid, BW * 64, 0, s>>>(
+        inst, count, total, (const C*)pi, (const R*)ni, (C*)po, (R*)no, (const R*)V, (const R*)P, flag);
+    return hipGetLastError();
+}
+
+template <typename R>
+static hipError_t launch_batch(bool res, bool hv, bool ghosts, int grid, const BatchInst<R>* inst, int count,
+                               int total, const void* pi, const void* ni, void* po, void* no, const void* V,
+                               const void* P, unsigned int* flag, hipStream_t s)
+{
+#define PHX_B(RS, HV, G) \
+    if (res == RS && hv == HV && ghosts == G) \
+        return launch_batch_t<R, RS, HV, G>(grid, inst, count, total, pi, ni, po, no, V, P, flag, s)
+    PHX_B(true, false, false); PHX_B(true, true, false); PHX_B(false, false, false); PHX_B(false, true, false);
+    PHX_B(true, false, true); PHX_B(true, true, true); PHX_B(false, false, true); PHX_B(false, true, true);
+#undef PHX_B
+    return hipErrorInvalidValue;
+}
+
+struct BatchLayout {
+    size_t table, alt, alt_n, flag, total;
+};
+
+static BatchLayout batch_layout(const phx_batch_desc& d)
+{
+    const size_t rs = d.precision == PHX_C64 ? 4 : 8;
+    const size_t inst_bytes = d.precision == PHX_C64 ? sizeof(BatchInst<float>) : sizeof(BatchInst<double>);
+    BatchLayout L{};
+    size_t off = 0;
+    auto take = [&](size_t b) { size_t o = off; off += align_up(b); return o; };
+    L.flag = take(256);
+    L.table = take((size_t)d.count * inst_bytes);
+    L.alt = take((size_t)d.total_cells * 2 * rs);
+    const bool res = d.params && d.n_params > 0 && d.params[0].reservoir;
+    L.alt_n = res ? take((size_t)d.total_cells * rs) : 0;
+    L.total = off;
+    return L;
+}
+
+static phx_status validate_batch(const phx_batch_desc* d)
+{
+    if (!d) return fail(PHX_EINVAL, "descriptor is NULL");
+    if (d->count < 1) return fail(PHX_EINVAL, "count must be >= 1");
+    if (d->precision != PHX_C64 && d->precision != PHX_C128) return fail(PHX_EINVAL, "bad precision");
+    if (!d->instances || !d->params || d->n_params < 1) return fail(PHX_EINVAL, "instances and params required");
+    if (d->check_finite != 0 && d->check_finite != 1) return fail(PHX_EINVAL, "check_finite must be 0 or 1");
+    if (d->total_cells < 1 || d->total_cells >= ((int64_t)1 << 40)) return fail(PHX_EINVAL, "bad total_cells");
+    const int res = d->params[0].reservoir;
+    for (int k = 0; k < d->n_params; ++k) {
+        phx_config c = d->params[k];
+        c.nx = c.ny = 1;
+        c.components = 1;
+        c.precision = d->precision;
+        c.integrator = PHX_RK4;
+        c.kernel = PHX_KERNEL_AUTO;
+        c.tile_wx = c.tile_rows = 0;
+        phx_status s = validate_config(&c);
+        if (s != PHX_OK) return s;
+        if (c.reservoir != res) return fail(PHX_EINVAL, "all params must share the reservoir flag");
+    }
+    std::vector<std::pair<int64_t, int64_t>> spans;
+    spans.reserve(d->count);
+    int64_t tiles = 0;
+    for (int k = 0; k < d->count; ++k) {
+        const phx_instance& I = d->instances[k];
+        if (I.nx < 1 || I.ny < 1 || (int64_t)I.nx * I.ny >= ((int64_t)1 << 31))
+            return fail(PHX_EINVAL, "instance %d: bad grid %d x %d", k, I.nx, I.ny);
+        if (I.param_index < 0 || I.param_index >= d->n_params || I.reserved != 0)
+            return fail(PHX_EINVAL, "instance %d: bad param_index or reserved field", k);
+        if (I.offset < 0 || I.offset + (int64_t)I.nx * I.ny > d->total_cells)
+            return fail(PHX_EINVAL, "instance %d: slice outside the packed arrays", k);
+        phx_config c = d->params[I.param_index];
+        c.nx = I.nx;
+        c.ny = I.ny;
+        c.components = 1;
+        c.precision = d->precision;
+        c.integrator = PHX_RK4;
+        c.kernel = PHX_KERNEL_AUTO;
+        c.tile_wx = c.tile_rows = 0;
+        phx_status s = validate_config(&c);  // stability of dt on this grid
+        if (s != PHX_OK) return s;
+        spans.push_back({I.offset, I.offset + (int64_t)I.nx * I.ny});
+        tiles += (int64_t)((I.nx + 55) / 56) * ((I.ny + BW * BR - 9) / (BW * BR - 8));
+    }
+    if (tiles >= ((int64_t)1 << 31)) return fail(PHX_EINVAL, "too many work items");
+    std::sort(spans.begin(), spans.end());
+    for (size_t k = 1; k < spans.size(); ++k)
+        if (spans[k].first < spans[k - 1].second) return fail(PHX_EINVAL, "instance slices overlap");
+    if (!d->psi || (res && (!d->n || !d->P))) return fail(PHX_EINVAL, "psi (and n, P with the reservoir) required");
+    const void* ptrs[] = {d->psi, d->n, d->P, d->V, d->workspace};
+    for (const void* p : ptrs)
+        if (p && ((uintptr_t)p & 255u)) return fail(PHX_EINVAL, "device pointers must be 256-byte aligned");
+    return PHX_OK;
+}
+
+template <typename R>
+static phx_status batch_run(const phx_batch_desc* d, int64_t n, hipStream_t stream)
+{
+    const BatchLayout L = batch_layout(*d);
+    char* ws = (char*)d->workspace;
+    const int res = d->params[0].reservoir;
+    std::vector<BatchInst<R>> table(d->count);
+    int tile0 = 0;
+    bool ghosts = false;
+    for (int k = 0; k < d->count; ++k) {
+        const phx_instance& I = d->instances[k];
+        phx_config c = d->params[I.param_index];
+        c.nx = I.nx;
+        c.ny = I.ny;
+        BatchInst<R>& b = table[k];
+        b.nx = I.nx;
+        b.ny = I.ny;
+        b.bcx = c.bc_x;
+        b.bcy = c.bc_y;
+        b.tiles_x = (I.nx + 55) / 56;
+        b.tile0 = tile0;
+        b.offset = I.offset;
+        b.c = make_coef<R>(c);
+        b.half_dt = (R)(0.5 * c.dt);
+        b.dt = (R)c.dt;
+        b.dt6 = (R)(c.dt / 6.0);
+        tile0 += b.tiles_x * ((I.ny + BW * BR - 9) / (BW * BR - 8));
+        ghosts = ghosts || c.bc_x == PHX_BC_ZERO || c.bc_y == PHX_BC_ZERO;
+    }
+    const int total = tile0;
+    hipError_t e = hipMemcpyAsync(ws + L.table, table.data(), table.size() * sizeof(BatchInst<R>),
+                                  hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipMemsetAsync(ws + L.flag, 0, 256, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);  // the host table may go out of scope
+    if (e != hipSuccess) return fail(PHX_EHIP, "batch table upload: %s", hipGetErrorString(e));
+
+    // persistent grid: as many workgroups as fit on the device at once, a multiple
+    // of 8 so that every workgroup stays on one XCD's share of the work list
+    int dev = 0, cus = 256, per_cu = 1;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, dev) == hipSuccess) cus = prop.multiProcessorCount;
+    }
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_step_kernel<R, true, false, false, BW, BR>,
+                                                     BW * 64, 0) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    int grid = cus * per_cu;
+    grid = std::min(grid, (total + 7) / 8 * 8);
+    grid = (grid + 7) / 8 * 8;
+
+    const size_t rs = sizeof(R);
+    void* S[2] = {d->psi, ws + L.alt};
+    void* SN[2] = {d->n, res ? ws + L.alt_n : nullptr};
+    int cur = 0;
+    if (n & 1) {
+        e = hipMemcpyAsync(S[1], S[0], (size_t)d->total_cells * 2 * rs, hipMemcpyDeviceToDevice, stream);
+        if (e == hipSuccess && res)
+            e = hipMemcpyAsync(SN[1], SN[0], (size_t)d->total_cells * rs, hipMemcpyDeviceToDevice, stream);
+        if (e != hipSuccess) return fail(PHX_EHIP, "batch state copy: %s", hipGetErrorString(e));
+        cur = 1;
+    }
+    const BatchInst<R>* dtab = (const BatchInst<R>*)(ws + L.table);
+    unsigned int* flag = (unsigned int*)(ws + L.flag);
+    for (int64_t k = 0; k < n; ++k) {
+        e = launch_batch<R>(res != 0, d->V != nullptr, ghosts, grid, dtab, d->count, total, S[cur], SN[cur],
+                            S[cur ^ 1], SN[cur ^ 1], d->V, d->P, flag, stream);
+        if (e != hipSuccess) return fail(PHX_EHIP, "batch step launch: %s", hipGetErrorString(e));
+        cur ^= 1;
+    }
+    if (d->check_finite) {
+        unsigned int v = 0;
+        e = hipMemcpyAsync(&v, flag, sizeof(v), hipMemcpyDeviceToHost, stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);
+        if (e != hipSuccess) return fail(PHX_EHIP, "batch flag read: %s", hipGetErrorString(e));
+        if (v) return fail(PHX_ENONFINITE, "a non-finite value appeared in the batch");
+    }
+    return PHX_OK;
+}
+
+}  // namespace phx
 
 using namespace phx;
 
-phx_status phx_batch_workspace_bytes(const phx_batch_desc*, size_t*)
+phx_status phx_batch_workspace_bytes(const phx_batch_desc* desc, size_t* out)
 {
     clear_error();
-    return fail(PHX_EUNSUPPORTED, "batches are not available in this build");
+    if (!out) return fail(PHX_EINVAL, "out is NULL");
+    phx_status s = validate_batch(desc);
+    if (s != PHX_OK) return s;
+    *out = batch_layout(*desc).total;
+    return PHX_OK;
 }
 
-phx_status phx_batch_step(const phx_batch_desc*, int64_t, void*)
+phx_status phx_batch_step(const phx_batch_desc* desc, int64_t n_steps, void* hip_stream)
 {
     clear_error();
-    return fail(PHX_EUNSUPPORTED, "batches are not available in this build");
+    phx_status s = validate_batch(desc);
+    if (s != PHX_OK) return s;
+    if (n_steps < 0) return fail(PHX_EINVAL, "n_steps must be >= 0");
+    const BatchLayout L = batch_layout(*desc);
+    if (!desc->workspace || desc->workspace_bytes < L.total)
+        return fail(PHX_EWORKSPACE, "workspace of %zu bytes needed", L.total);
+    if (n_steps == 0) return PHX_OK;
+    hipStream_t st = (hipStream_t)hip_stream;
+    return desc->precision == PHX_C64 ? batch_run<float>(desc, n_steps, st) : batch_run<double>(desc, n_steps, st);
 }

@@ -71,8 +71,13 @@ struct phx_handle {
     void* other_n;
     phx::StepShapeId step_shape;  // whole-step RK4 region shape in use
     phx::TilePlan stage_tiles;    // stage-fused RK4 tile plan in use
+    int step_parity;              // whole-step family: buffer holding the state (0 = caller's)
     int fsal;               // index of the buffer that holds K1 of the current state
     bool k1_valid;
+    // hipGraph of graph_steps RK4 steps, captured on cap_stream, replayed on stream
+    hipStream_t cap_stream;
+    hipGraphExec_t graph;
+    bool graph_dirty;
     // kernel timing (phx_set_timing / phx_kernel_times)
     struct TimedLaunch {
         hipEvent_t start, stop;
@@ -99,6 +104,10 @@ const void* state_psi(const phx_handle* h);
 const void* state_n(const phx_handle* h);
 phx_status create_rk45(phx_handle* h);
 template <typename R> phx_status rk4_fused_steps(phx_handle* h, int64_t n);
+template <typename R> phx_status rk4_fused_launches(phx_handle* h, int64_t n, hipStream_t s);
+template <typename R> phx_status rk4_stage_launches(phx_handle* h, int64_t n, hipStream_t s);
+int graph_chunk(const phx_config& c);
+template <typename R> phx_status rk4_run_graph(phx_handle* h, int64_t n);
 template <typename R> hipError_t rk4_step_trial(phx_handle* h, const StepShapeId& sh);
 template <typename R> hipError_t rk4_stage_trial(phx_handle* h, const TileShape& ts);
 int step_shapes(int precision, const StepShapeId** out);

@@ -53,7 +53,6 @@ phx_status validate_config(const phx_config* c)
         return fail(PHX_EINVAL, "integrator=%d must be PHX_RK4 or PHX_RK45", c->integrator);
     if (c->kernel < PHX_KERNEL_AUTO || c->kernel > PHX_KERNEL_STEP)
         return fail(PHX_EINVAL, "kernel=%d is not a PHX_KERNEL_* value", c->kernel);
-    if (c->reserved != 0) return fail(PHX_EINVAL, "reserved field must be 0");
     if (c->kernel == PHX_KERNEL_STEP && (c->integrator != PHX_RK4 || c->components != 1))
         return fail(PHX_EUNSUPPORTED, "the whole-step kernel covers RK4 with one component");
     if ((c->tile_wx == 0) != (c->tile_rows == 0)) return fail(PHX_EINVAL, "tile_wx and tile_rows: both 0 or both set");
@@ -281,8 +280,9 @@ static void poll_flag(phx_handle* h)
     if (v) h->info.nonfinite = 1;
 }
 
+namespace phx {
 template <typename R>
-static phx_status rk4_steps(phx_handle* h, int64_t n)
+phx_status rk4_stage_launches(phx_handle* h, int64_t n, hipStream_t stream)
 {
     const phx_config& c = h->cfg;
     const Layout& L = h->L;
@@ -329,13 +329,15 @@ static phx_status rk4_steps(phx_handle* h, int64_t n)
             a.a_dt = adt[s];
             hipEvent_t t0 = nullptr;
             hipError_t e = timing_begin(h, &t0);
-            if (e == hipSuccess) e = launch_rk4_stage<R>(s + 1, res, hv, a, h->stream);
+            if (e == hipSuccess) e = launch_rk4_stage<R>(s + 1, res, hv, a, stream);
             if (e == hipSuccess) e = timing_end(h, t0, K_RK4_S1 + s);
             if (e != hipSuccess) return fail(PHX_EHIP, "RK4 stage %d launch: %s", s + 1, hipGetErrorString(e));
         }
     }
     return PHX_OK;
 }
+
+}  // namespace phx
 
 // Trial launches of the stage-fused kernels for the tuner: stage 1 from the state
 // into the workspace, then stage 2 between workspace buffers with shape ts.  The
@@ -378,6 +380,65 @@ template hipError_t rk4_stage_trial<float>(phx_handle*, const TileShape&);
 template hipError_t rk4_stage_trial<double>(phx_handle*, const TileShape&);
 }  // namespace phx
 
+namespace phx {
+int graph_chunk(const phx_config& c)
+{
+    if (c.graph_steps < 0) return 0;
+    const int g = c.graph_steps == 0 ? 64 : c.graph_steps;
+    return (g + 1) & ~1;  // even, so that a replay of the whole-step family ends in the same buffer
+}
+
+// Enqueues n RK4 steps on the handle's stream: whole chunks as replays of one
+// captured graph, the remainder directly.  With kernel timing on, everything is
+// launched directly so that each kernel is bracketed by events.
+template <typename R>
+static phx_status rk4_run(phx_handle* h, int64_t n)
+{
+    const bool step = h->L.family == PHX_KERNEL_STEP;
+    auto direct = [&](hipStream_t s, int64_t k) {
+        return step ? rk4_fused_launches<R>(h, k, s) : rk4_stage_launches<R>(h, k, s);
+    };
+    const int G = graph_chunk(h->cfg);
+    if (h->timing || G == 0 || n < G) return direct(h->stream, n);
+    if (!h->graph || h->graph_dirty) {
+        if (h->graph) {
+            (void)hipGraphExecDestroy(h->graph);
+            h->graph = nullptr;
+        }
+        if (!h->cap_stream && hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking) != hipSuccess)
+            return fail(PHX_EHIP, "capture stream creation failed");
+        // the capture stream must not run ahead of work already queued on the caller's stream
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return fail(PHX_EHIP, "graph capture: %s", hipGetErrorString(e));
+        phx_status st = direct(h->cap_stream, G);
+        e = hipStreamEndCapture(h->cap_stream, &g);
+        if (st != PHX_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return st;
+        }
+        if (e == hipSuccess) e = hipGraphInstantiate(&h->graph, g, nullptr, nullptr, 0);
+        if (g) (void)hipGraphDestroy(g);
+        if (e != hipSuccess) return fail(PHX_EHIP, "graph instantiation: %s", hipGetErrorString(e));
+        h->graph_dirty = false;
+    }
+    for (int64_t k = 0; k < n / G; ++k) {
+        hipError_t e = hipGraphLaunch(h->graph, h->stream);
+        if (e != hipSuccess) return fail(PHX_EHIP, "graph launch: %s", hipGetErrorString(e));
+    }
+    return direct(h->stream, n % G);
+}
+
+}  // namespace phx
+
+namespace phx {
+template <typename R> phx_status rk4_run_graph(phx_handle* h, int64_t n) { return rk4_run<R>(h, n); }
+template phx_status rk4_run_graph<float>(phx_handle*, int64_t);
+template phx_status rk4_run_graph<double>(phx_handle*, int64_t);
+template phx_status rk4_stage_launches<float>(phx_handle*, int64_t, hipStream_t);
+template phx_status rk4_stage_launches<double>(phx_handle*, int64_t, hipStream_t);
+}  // namespace phx
+
 phx_status phx_step(phx_handle* h, int64_t n_steps, phx_info* out)
 {
     clear_error();
@@ -395,7 +456,7 @@ phx_status phx_step(phx_handle* h, int64_t n_steps, phx_info* out)
         if (h->L.family == PHX_KERNEL_STEP)
             s = h->cfg.precision == PHX_C64 ? rk4_fused_steps<float>(h, n_steps) : rk4_fused_steps<double>(h, n_steps);
         else
-            s = h->cfg.precision == PHX_C64 ? rk4_steps<float>(h, n_steps) : rk4_steps<double>(h, n_steps);
+            s = h->cfg.precision == PHX_C64 ? rk4_run<float>(h, n_steps) : rk4_run<double>(h, n_steps);
         if (s != PHX_OK) return s;
         HIP_OR_FAIL(hipMemcpyAsync(&h->host[OBS_SLOTS], h->ws + h->L.flag, sizeof(unsigned int),
                                    hipMemcpyDeviceToHost, h->stream));
@@ -596,6 +657,8 @@ void phx_destroy(phx_handle* h)
         (void)hipEventDestroy(t.stop);
     }
     for (hipEvent_t e : h->free_events) (void)hipEventDestroy(e);
+    if (h->graph) (void)hipGraphExecDestroy(h->graph);
+    if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
     if (h->host) (void)hipHostFree(h->host);
     (void)hipEventDestroy(h->flag_ready);
     delete h;

@@ -41,7 +41,7 @@ class phx_config(ctypes.Structure):
         ("dt", ctypes.c_double), ("rtol", ctypes.c_double), ("atol", ctypes.c_double),
         ("dt_min", ctypes.c_double), ("dt_max", ctypes.c_double),
         ("kernel", ctypes.c_int32), ("tile_wx", ctypes.c_int32), ("tile_rows", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("graph_steps", ctypes.c_int32),
     ]
 
 
@@ -104,7 +104,8 @@ class phx_instance(ctypes.Structure):
 class phx_batch_desc(ctypes.Structure):
     _fields_ = [("count", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("instances", ctypes.POINTER(phx_instance)), ("params", ctypes.POINTER(phx_config)),
-                ("n_params", ctypes.c_int32), ("has_V", ctypes.c_int32),
+                ("n_params", ctypes.c_int32), ("check_finite", ctypes.c_int32),
+                ("total_cells", ctypes.c_int64),
                 ("psi", ctypes.c_void_p), ("n", ctypes.c_void_p), ("P", ctypes.c_void_p),
                 ("V", ctypes.c_void_p), ("workspace", ctypes.c_void_p),
                 ("workspace_bytes", ctypes.c_size_t)]
@@ -249,13 +250,13 @@ def make_config(nx, ny, dx, dy=None, *, bc_x=PHX_BC_PERIODIC, bc_y=PHX_BC_PERIOD
                 reservoir=False, precision=PHX_C64, integrator=PHX_RK4, hbar=1.0, mass=1.0, g=0.0,
                 g_x=0.0, g_r=0.0, R=0.0, gamma_c=0.0, gamma_r=0.0, delta_lt=0.0, dt=1e-3,
                 rtol=1e-6, atol=1e-6, dt_min=1e-12, dt_max=float("inf"),
-                kernel=PHX_KERNEL_AUTO, tile_wx=0, tile_rows=0) -> phx_config:
+                kernel=PHX_KERNEL_AUTO, tile_wx=0, tile_rows=0, graph_steps=0) -> phx_config:
     return phx_config(int(nx), int(ny), float(dx), float(dx if dy is None else dy), int(bc_x), int(bc_y),
                       int(components), int(bool(reservoir)), int(precision), int(integrator),
                       float(hbar), float(mass), float(g), float(g_x), float(g_r), float(R),
                       float(gamma_c), float(gamma_r), float(delta_lt), float(dt), float(rtol),
                       float(atol), float(dt_min), float(dt_max), int(kernel), int(tile_wx),
-                      int(tile_rows), 0)
+                      int(tile_rows), int(graph_steps))
 
 
 def config_from_physics(ph, **kw) -> phx_config:
@@ -391,3 +392,52 @@ class Solver:
             self.close()
         except Exception:
             pass
+
+
+class Batch:
+    """Packed torch buffers for many one-component instances and a persistent
+    batched stepper (phx_batch_step).
+
+    grids: list of (nx, ny); params: list of phx_config (physics, boundaries, dt);
+    param_index: per-instance index into params.  Instance k's cells are
+    psi[offsets[k] : offsets[k] + nx*ny] (row-major), likewise n, P, V."""
+
+    def __init__(self, grids, params, param_index=None, precision=PHX_C64, device="cuda:0",
+                 with_v=False, check_finite=False):
+        import torch
+        self.torch = torch
+        self.grids = [(int(a), int(b)) for a, b in grids]
+        self.precision = precision
+        cdt, rdt = torch_dtypes(precision)
+        align = 64  # keep every slice 256-byte aligned for the complex array
+        offs, o = [], 0
+        for nx, ny in self.grids:
+            offs.append(o)
+            o += (nx * ny + align - 1) // align * align
+        self.offsets = offs
+        self.total = o
+        res = bool(params[0].reservoir)
+        self.psi = torch.zeros(o, dtype=cdt, device=device)
+        self.n = torch.zeros(o, dtype=rdt, device=device) if res else None
+        self.P = torch.zeros(o, dtype=rdt, device=device) if res else None
+        self.V = torch.zeros(o, dtype=rdt, device=device) if with_v else None
+        pidx = param_index if param_index is not None else [0] * len(self.grids)
+        self._inst = (phx_instance * len(self.grids))(*[
+            phx_instance(nx, ny, int(p), 0, off) for (nx, ny), p, off in zip(self.grids, pidx, offs)])
+        self._params = (phx_config * len(params))(*params)
+        ptr = lambda t: None if t is None else t.data_ptr()
+        self.desc = phx_batch_desc(len(self.grids), precision, self._inst, self._params, len(params),
+                                   int(check_finite), o, ptr(self.psi), ptr(self.n), ptr(self.P), ptr(self.V),
+                                   None, 0)
+        nbytes = phx_batch_workspace_bytes(self.desc)
+        self.workspace = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+        self.desc.workspace = self.workspace.data_ptr()
+        self.desc.workspace_bytes = nbytes
+
+    def view(self, t, k):
+        nx, ny = self.grids[k]
+        return t[self.offsets[k]:self.offsets[k] + nx * ny].view(ny, nx)
+
+    def step(self, n_steps: int, stream=None):
+        s = stream if stream is not None else self.torch.cuda.current_stream(self.psi.device)
+        phx_batch_step(self.desc, n_steps, s.cuda_stream)

@@ -40,7 +40,7 @@ def _c_layout():
 #define F(T, m) printf(#T "." #m " %zu\n", offsetof(T, m));
 int main(void) {
   printf("phx_config %zu\n", sizeof(phx_config)); F(phx_config, dx) F(phx_config, bc_x) F(phx_config, hbar)
-  F(phx_config, delta_lt) F(phx_config, dt) F(phx_config, dt_max) F(phx_config, kernel) F(phx_config, tile_rows) F(phx_config, reserved)
+  F(phx_config, delta_lt) F(phx_config, dt) F(phx_config, dt_max) F(phx_config, kernel) F(phx_config, tile_rows) F(phx_config, graph_steps)
   printf("phx_fields %zu\n", sizeof(phx_fields)); F(phx_fields, workspace_bytes)
   printf("phx_obs %zu\n", sizeof(phx_obs)); F(phx_obs, energy) F(phx_obs, max_density) F(phx_obs, nonfinite)
   printf("phx_info %zu\n", sizeof(phx_info)); F(phx_info, steps_rejected) F(phx_info, nonfinite)
@@ -101,7 +101,7 @@ def test_workspace_bytes_scale_with_precision_and_reservoir():
 @pytest.mark.parametrize("field,value", [
     ("nx", 0), ("ny", -3), ("dx", 0.0), ("dy", float("nan")), ("bc_x", 2), ("components", 3),
     ("reservoir", 2), ("precision", 5), ("integrator", 9), ("hbar", 0.0), ("mass", -1.0),
-    ("g", float("inf")), ("dt", 0.0), ("dt", 1.0), ("kernel", 7), ("reserved", 1),
+    ("g", float("inf")), ("dt", 0.0), ("dt", 1.0), ("kernel", 7),
     ("tile_wx", 3), ("tile_rows", 5), ("tile_rows", 65),
 ])
 def test_invalid_config_rejected(field, value):
@@ -190,3 +190,41 @@ def test_tune_cache_roundtrip(tmp_path, monkeypatch):
     phx.store_shape(cfg, False, r, "dev")
     assert phx.cached_shape(cfg, False, "dev") == (8, 4)
     assert phx.cached_shape(cfg, True, "dev") is None
+
+
+def _desc(grids, offsets, total, params=None, ws=1 << 30):
+    params = params or [phx.make_config(8, 8, 0.2, reservoir=True, g=0.01, R=0.01, gamma_c=0.15,
+                                        gamma_r=0.225, dt=0.02)]
+    inst = (phx.phx_instance * len(grids))(*[phx.phx_instance(nx, ny, 0, 0, o)
+                                             for (nx, ny), o in zip(grids, offsets)])
+    pa = (phx.phx_config * len(params))(*params)
+    d = phx.phx_batch_desc(len(grids), phx.PHX_C64, inst, pa, len(params), 0, total, 256, 512, 768,
+                           None, 1024, ws)
+    d._keep = (inst, pa)
+    return d
+
+
+def test_batch_descriptor_validation():
+    ok = _desc([(10, 10), (20, 5)], [0, 100], 200)
+    assert phx.phx_batch_workspace_bytes(ok) > 200 * 8
+    bad_cases = [
+        _desc([(10, 10), (20, 5)], [0, 50], 200),        # overlap
+        _desc([(10, 10), (20, 5)], [0, 150], 200),       # past total_cells
+        _desc([(0, 10)], [0], 200),                      # empty grid
+        _desc([(10, 10)], [-1], 200),                    # negative offset
+    ]
+    for d in bad_cases:
+        with pytest.raises(phx.PhxError) as e:
+            phx.phx_batch_workspace_bytes(d)
+        assert e.value.status == phx.PHX_EINVAL
+    d = _desc([(10, 10)], [0], 200)
+    d.instances[0].param_index = 3
+    with pytest.raises(phx.PhxError):
+        phx.phx_batch_workspace_bytes(d)
+    unstable = _desc([(10, 10)], [0], 200, params=[phx.make_config(8, 8, 0.2, dt=1.0)])
+    with pytest.raises(phx.PhxError):
+        phx.phx_batch_workspace_bytes(unstable)
+    small = _desc([(10, 10)], [0], 200, ws=16)
+    with pytest.raises(phx.PhxError) as e:
+        phx.phx_batch_step(small, 1, None)
+    assert e.value.status == phx.PHX_EWORKSPACE
