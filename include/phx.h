@@ -253,6 +253,81 @@ phx_status phx_batch_workspace_bytes(const phx_batch_desc *desc, size_t *out);
  * unstable dt), PHX_EWORKSPACE, PHX_EUNSUPPORTED, PHX_EHIP, PHX_ENONFINITE. */
 phx_status phx_batch_step(const phx_batch_desc *desc, int64_t n_steps, void *hip_stream);
 
+/* ---------------------------------------------------------------- learned corrector
+ * A coarse grid (block means of a fine grid, larger time step) stands in for the
+ * fine grid when a small convolutional network adds a learned correction after
+ * every coarse step.  The network: four 3x3 convolutions with circular padding,
+ * in_channels -> hidden -> hidden -> hidden -> out_channels, ReLU between them.  It
+ * runs on BF16 MFMA with FP32 accumulation; master parameters and Adam moments are
+ * FP32.  Inputs and outputs are FP32 NHWC: x[batch][height][width][in_channels],
+ * y[batch][height][width][out_channels].
+ *
+ * Parameter layout (FP32, n_params entries, padded entries must be 0): for each
+ * layer l, weights W_l[c_out_pad][K_pad] at w_off[l] with K index
+ * k = tap * c_in_pad + c_in, tap = (dy + 1) * 3 + (dx + 1) for the input pixel
+ * (y + dy, x + dx), then biases b_l[c_out_pad] at b_off[l]
+ * (phx_cnn_param_offsets gives the offsets and padded sizes). */
+typedef struct phx_cnn_config {
+    int32_t in_channels;    /* 4                                                       */
+    int32_t hidden;         /* 32                                                      */
+    int32_t out_channels;   /* 3                                                       */
+    int32_t height, width;  /* grid of every sample; width a multiple of 32             */
+    int32_t max_batch;      /* samples per call, >= 1                                  */
+} phx_cnn_config;
+
+typedef struct phx_cnn_buffers {
+    float *params;          /* [n_params] FP32 master parameters (caller-owned)        */
+    float *adam_m, *adam_v; /* [n_params] Adam moments, zero before the first update   */
+    void *workspace;        /* at least the workspace_bytes of phx_cnn_sizes            */
+    size_t workspace_bytes;
+} phx_cnn_buffers;
+
+typedef struct phx_cnn phx_cnn;
+
+phx_status phx_cnn_sizes(const phx_cnn_config *cfg, int64_t *n_params, size_t *workspace_bytes);
+phx_status phx_cnn_param_offsets(const phx_cnn_config *cfg, int64_t *w_off /*[4]*/, int64_t *b_off /*[4]*/,
+                                 int32_t *k_pad /*[4]*/, int32_t *c_in_pad /*[4]*/, int32_t *c_out_pad /*[4]*/);
+phx_status phx_cnn_create(const phx_cnn_config *cfg, const phx_cnn_buffers *buf, void *hip_stream, phx_cnn **out);
+void phx_cnn_destroy(phx_cnn *h);
+
+/* y = network(x) for `batch` samples (enqueued on the handle's stream). */
+phx_status phx_cnn_forward(phx_cnn *h, const float *x, int32_t batch, float *y);
+
+/* Mean-squared-error loss of network(x) against target ([batch][height][width]
+ * [out_channels]) and its gradient with respect to every parameter, written to
+ * grads[n_params] (same layout as the parameters); *loss (device double) receives
+ * the loss.  Backward passes: data gradients through the flipped weights times
+ * the ReLU masks, weight gradients reduced over pixels in a fixed order. */
+phx_status phx_cnn_gradients(phx_cnn *h, const float *x, const float *target, int32_t batch, float *grads,
+                             double *loss);
+
+/* One Adam step (Kingma & Ba 2015, Algorithm 1) at step t >= 1 on the master
+ * parameters with moment buffers adam_m / adam_v. */
+phx_status phx_cnn_adam(phx_cnn *h, const float *grads, int32_t t, float lr, float beta1, float beta2, float eps);
+
+/* phx_cnn_gradients followed by phx_cnn_adam (beta1 0.9, beta2 0.999, eps 1e-8). */
+phx_status phx_cnn_train_step(phx_cnn *h, const float *x, const float *target, int32_t batch, int32_t t, float lr,
+                              double *loss);
+
+/* Block means over factor x factor cells of a fine grid (nx_f, ny_f multiples of
+ * factor): psi_c, n_c, P_c on the (nx_f/factor) x (ny_f/factor) grid.  n_f, P_f may
+ * be NULL. */
+phx_status phx_coarsen(int32_t precision, const void *psi_f, const void *n_f, const void *P_f, int32_t nx_f,
+                       int32_t ny_f, int32_t factor, void *psi_c, void *n_c, void *P_c, void *hip_stream);
+
+/* Network input x[cell] = (Re psi/s_psi, Im psi/s_psi, n/s_n, P/s_p) (n, P may be NULL: 0). */
+phx_status phx_corrector_features(int32_t precision, const void *psi, const void *n, const void *P, int32_t nx,
+                                  int32_t ny, double s_psi, double s_n, double s_p, float *x, void *hip_stream);
+
+/* Training target r[cell] = ((psi_ref - psi)/s_psi as re, im, (n_ref - n)/s_n). */
+phx_status phx_corrector_residual(int32_t precision, const void *psi_ref, const void *n_ref, const void *psi,
+                                  const void *n, int32_t nx, int32_t ny, double s_psi, double s_n, float *r,
+                                  void *hip_stream);
+
+/* Correction: psi += s_psi (y0 + i y1), n += s_n y2 (n may be NULL). */
+phx_status phx_corrector_apply(int32_t precision, void *psi, void *n, const float *y, int32_t nx, int32_t ny,
+                               double s_psi, double s_n, void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

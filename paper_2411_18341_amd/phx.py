@@ -111,10 +111,23 @@ class phx_batch_desc(ctypes.Structure):
                 ("workspace_bytes", ctypes.c_size_t)]
 
 
+class phx_cnn_config(ctypes.Structure):
+    _fields_ = [("in_channels", ctypes.c_int32), ("hidden", ctypes.c_int32), ("out_channels", ctypes.c_int32),
+                ("height", ctypes.c_int32), ("width", ctypes.c_int32), ("max_batch", ctypes.c_int32)]
+
+
+class phx_cnn_buffers(ctypes.Structure):
+    _fields_ = [("params", ctypes.c_void_p), ("adam_m", ctypes.c_void_p), ("adam_v", ctypes.c_void_p),
+                ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t)]
+
+
 # names of every exported entry point (kept in step with include/phx.h)
 ENTRY_POINTS = ("phx_workspace_bytes", "phx_create", "phx_step", "phx_observables", "phx_get_info",
                 "phx_set_info", "phx_destroy", "phx_last_error", "phx_set_timing", "phx_kernel_times",
-                "phx_autotune", "phx_batch_workspace_bytes", "phx_batch_step")
+                "phx_autotune", "phx_batch_workspace_bytes", "phx_batch_step", "phx_cnn_sizes",
+                "phx_cnn_param_offsets", "phx_cnn_create", "phx_cnn_destroy", "phx_cnn_forward",
+                "phx_cnn_gradients", "phx_cnn_adam", "phx_cnn_train_step", "phx_coarsen",
+                "phx_corrector_features", "phx_corrector_residual", "phx_corrector_apply")
 
 _lib = None
 
@@ -158,6 +171,24 @@ def load(path: str | None = None):
     lib.phx_batch_workspace_bytes.restype = st
     lib.phx_batch_step.argtypes = [P(phx_batch_desc), ctypes.c_int64, vp]
     lib.phx_batch_step.restype = st
+    i32, i64, dbl, flt = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_float
+    lib.phx_cnn_sizes.argtypes = [P(phx_cnn_config), P(i64), P(ctypes.c_size_t)]
+    lib.phx_cnn_param_offsets.argtypes = [P(phx_cnn_config), P(i64), P(i64), P(i32), P(i32), P(i32)]
+    lib.phx_cnn_create.argtypes = [P(phx_cnn_config), P(phx_cnn_buffers), vp, P(vp)]
+    lib.phx_cnn_destroy.argtypes = [vp]
+    lib.phx_cnn_destroy.restype = None
+    lib.phx_cnn_forward.argtypes = [vp, vp, i32, vp]
+    lib.phx_cnn_gradients.argtypes = [vp, vp, vp, i32, vp, vp]
+    lib.phx_cnn_adam.argtypes = [vp, vp, i32, flt, flt, flt, flt]
+    lib.phx_cnn_train_step.argtypes = [vp, vp, vp, i32, i32, flt, vp]
+    lib.phx_coarsen.argtypes = [i32, vp, vp, vp, i32, i32, i32, vp, vp, vp, vp]
+    lib.phx_corrector_features.argtypes = [i32, vp, vp, vp, i32, i32, dbl, dbl, dbl, vp, vp]
+    lib.phx_corrector_residual.argtypes = [i32, vp, vp, vp, vp, i32, i32, dbl, dbl, vp, vp]
+    lib.phx_corrector_apply.argtypes = [i32, vp, vp, vp, i32, i32, dbl, dbl, vp]
+    for name in ("phx_cnn_sizes", "phx_cnn_param_offsets", "phx_cnn_create", "phx_cnn_forward",
+                 "phx_cnn_gradients", "phx_cnn_adam", "phx_cnn_train_step", "phx_coarsen",
+                 "phx_corrector_features", "phx_corrector_residual", "phx_corrector_apply"):
+        getattr(lib, name).restype = st
     if path is None:
         _lib = lib
     return lib
@@ -441,3 +472,158 @@ class Batch:
     def step(self, n_steps: int, stream=None):
         s = stream if stream is not None else self.torch.cuda.current_stream(self.psi.device)
         phx_batch_step(self.desc, n_steps, s.cuda_stream)
+
+
+# ------------------------------------------------------------ learned corrector
+
+def _p(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream_handle(stream, device=None):
+    import torch
+    return (stream if stream is not None else torch.cuda.current_stream(device)).cuda_stream
+
+
+def phx_cnn_sizes(cfg: phx_cnn_config):
+    n = ctypes.c_int64(0)
+    ws = ctypes.c_size_t(0)
+    _check(load().phx_cnn_sizes(ctypes.byref(cfg), ctypes.byref(n), ctypes.byref(ws)))
+    return n.value, ws.value
+
+
+def phx_cnn_param_offsets(cfg: phx_cnn_config):
+    w = (ctypes.c_int64 * 4)()
+    b = (ctypes.c_int64 * 4)()
+    kp = (ctypes.c_int32 * 4)()
+    ci = (ctypes.c_int32 * 4)()
+    co = (ctypes.c_int32 * 4)()
+    _check(load().phx_cnn_param_offsets(ctypes.byref(cfg), w, b, kp, ci, co))
+    return list(w), list(b), list(kp), list(ci), list(co)
+
+
+def phx_coarsen(precision, psi_f, n_f, P_f, nx_f, ny_f, factor, psi_c, n_c, P_c, stream=None):
+    _check(load().phx_coarsen(precision, _p(psi_f), _p(n_f), _p(P_f), nx_f, ny_f, factor, _p(psi_c), _p(n_c),
+                              _p(P_c), _stream_handle(stream)))
+
+
+def phx_corrector_features(precision, psi, n, P, nx, ny, s_psi, s_n, s_p, x, stream=None):
+    _check(load().phx_corrector_features(precision, _p(psi), _p(n), _p(P), nx, ny, float(s_psi), float(s_n),
+                                         float(s_p), _p(x), _stream_handle(stream)))
+
+
+def phx_corrector_residual(precision, psi_ref, n_ref, psi, n, nx, ny, s_psi, s_n, r, stream=None):
+    _check(load().phx_corrector_residual(precision, _p(psi_ref), _p(n_ref), _p(psi), _p(n), nx, ny, float(s_psi),
+                                         float(s_n), _p(r), _stream_handle(stream)))
+
+
+def phx_corrector_apply(precision, psi, n, y, nx, ny, s_psi, s_n, stream=None):
+    _check(load().phx_corrector_apply(precision, _p(psi), _p(n), _p(y), nx, ny, float(s_psi), float(s_n),
+                                      _stream_handle(stream)))
+
+
+class Corrector:
+    """The corrector network on the current GPU: FP32 master parameters and Adam
+    moments as torch tensors, BF16 MFMA kernels in libphx."""
+
+    def __init__(self, height, width, max_batch, in_channels=4, hidden=32, out_channels=3, device="cuda:0",
+                 stream=None):
+        import torch
+        self.torch = torch
+        self.cfg = phx_cnn_config(in_channels, hidden, out_channels, height, width, max_batch)
+        self.n_params, ws = phx_cnn_sizes(self.cfg)
+        self.w_off, self.b_off, self.kp, self.cinp, self.coutp = phx_cnn_param_offsets(self.cfg)
+        self.channels = [in_channels, hidden, hidden, hidden, out_channels]
+        self.params = torch.zeros(self.n_params, dtype=torch.float32, device=device)
+        self.adam_m = torch.zeros_like(self.params)
+        self.adam_v = torch.zeros_like(self.params)
+        self.grads = torch.zeros_like(self.params)
+        self.loss = torch.zeros(1, dtype=torch.float64, device=device)
+        self.workspace = torch.empty(max(ws, 256), dtype=torch.uint8, device=device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(torch.device(device))
+        self.buf = phx_cnn_buffers(self.params.data_ptr(), self.adam_m.data_ptr(), self.adam_v.data_ptr(),
+                                   self.workspace.data_ptr(), ws)
+        h = ctypes.c_void_p()
+        _check(load().phx_cnn_create(ctypes.byref(self.cfg), ctypes.byref(self.buf), self.stream.cuda_stream,
+                                     ctypes.byref(h)))
+        self.handle = h
+        self.step_count = 0
+
+    # parameters as lists of (w [c_out][c_in][3][3], b [c_out]) numpy arrays
+    def set_weights(self, layers):
+        import numpy as np
+        flat = np.zeros(self.n_params, np.float32)
+        for l, (w, b) in enumerate(layers):
+            co, ci = w.shape[:2]
+            W = np.zeros((self.coutp[l], self.kp[l]), np.float32)
+            for t in range(9):
+                W[:co, t * self.cinp[l]:t * self.cinp[l] + ci] = w[:, :, t // 3, t % 3]
+            flat[self.w_off[l]:self.w_off[l] + W.size] = W.ravel()
+            flat[self.b_off[l]:self.b_off[l] + co] = b
+        self.params.copy_(self.torch.from_numpy(flat))
+
+    def unpack(self, flat):
+        import numpy as np
+        flat = np.asarray(flat, np.float64)
+        out = []
+        for l in range(4):
+            co, ci = self.channels[l + 1], self.channels[l]
+            W = flat[self.w_off[l]:self.w_off[l] + self.coutp[l] * self.kp[l]].reshape(self.coutp[l], self.kp[l])
+            w = np.zeros((co, ci, 3, 3))
+            for t in range(9):
+                w[:, :, t // 3, t % 3] = W[:co, t * self.cinp[l]:t * self.cinp[l] + ci]
+            out.append((w, flat[self.b_off[l]:self.b_off[l] + co].copy()))
+        return out
+
+    def get_weights(self):
+        return self.unpack(self.params.cpu().numpy())
+
+    def init_random(self, seed=0, scale=1.0):
+        """He-style initialization, seeded on the host."""
+        import numpy as np
+        rng = np.random.default_rng(seed)
+        layers = []
+        for l in range(4):
+            ci, co = self.channels[l], self.channels[l + 1]
+            std = scale * np.sqrt(2.0 / (9 * ci))
+            if l == 3:
+                std *= 0.1  # start close to "no correction"
+            layers.append((rng.standard_normal((co, ci, 3, 3)) * std, np.zeros(co)))
+        self.set_weights(layers)
+        self.adam_m.zero_()
+        self.adam_v.zero_()
+        self.step_count = 0
+
+    def forward(self, x, y=None):
+        b = x.shape[0]
+        if y is None:
+            y = self.torch.empty((b, self.cfg.height, self.cfg.width, self.cfg.out_channels), dtype=self.torch.float32,
+                                 device=x.device)
+        _check(load().phx_cnn_forward(self.handle, _p(x), b, _p(y)))
+        return y
+
+    def gradients(self, x, target):
+        _check(load().phx_cnn_gradients(self.handle, _p(x), _p(target), x.shape[0], _p(self.grads), _p(self.loss)))
+        return self.grads
+
+    def adam(self, lr, beta1=0.9, beta2=0.999, eps=1e-8, grads=None):
+        self.step_count += 1
+        g = self.grads if grads is None else grads
+        _check(load().phx_cnn_adam(self.handle, _p(g), self.step_count, lr, beta1, beta2, eps))
+
+    def train_step(self, x, target, lr):
+        self.step_count += 1
+        _check(load().phx_cnn_train_step(self.handle, _p(x), _p(target), x.shape[0], self.step_count, lr,
+                                         _p(self.loss)))
+        return self.loss
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load().phx_cnn_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
