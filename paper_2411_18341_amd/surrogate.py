@@ -1,0 +1,266 @@
+"""Coarse grid + learned corrector standing in for the fine grid (driven workload).
+
+Fine grid: the driven-dissipative workload at 1024^2 (dx 0.2, RK4 dt 0.02).
+Coarse grid: 256^2 over the same domain (dx 0.8) with RK4 dt 0.08 = 4 fine steps.
+D is the 4x4 block mean.  Network input: features of a coarse state (Re psi,
+Im psi scaled by sqrt(rho_s), n by n_s, P by P_th, rho_s = 22.5 and n_s = 15 the
+homogeneous steady state at P = 2 P_th).  Target: the residual
+    r = D(fine state after 4 fine steps) - coarse RK4 step of D(fine state)
+scaled the same way, so the corrected coarse step is
+    coarse_step(D u) + correction(features(D u)).
+Everything runs in libphx kernels: the fine and coarse trajectories (batched
+whole-step RK4), coarse-graining, features, residuals, the network's forward and
+backward passes and Adam; this module only sequences the calls.
+
+    python -m paper_2411_18341_amd.surrogate --train-traj 500 --eval-traj 50 --out report.json
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import time
+
+import numpy as np
+
+from . import inputs, phx
+
+RHO_S = 22.5   # (P - P_th)/gamma_c at P = 2 P_th
+N_S = 15.0     # gamma_c / R
+
+
+def fine_physics(n=1024):
+    ph, _, _, P = inputs.driven(n, seed=0)
+    return ph, P
+
+
+def coarse_config(ph, n_coarse, dt):
+    c = phx.config_from_physics(ph, precision=phx.PHX_C64, dt=dt)
+    c.nx = c.ny = n_coarse
+    c.dx = c.dy = ph.dx * ph.nx / n_coarse
+    return c
+
+
+class Pipeline:
+    def __init__(self, n_fine=1024, factor=4, device="cuda:0"):
+        import torch
+        self.torch = torch
+        self.dev = device
+        self.nf = n_fine
+        self.f = factor
+        self.nc = n_fine // factor
+        self.ph, self.P = fine_physics(n_fine)
+        self.pth = inputs.pump_threshold(self.ph.gamma_c, self.ph.gamma_r, self.ph.R)
+        self.cfg_f = phx.config_from_physics(self.ph, precision=phx.PHX_C64)
+        self.cfg_c = coarse_config(self.ph, self.nc, self.ph.dt * factor)
+
+    # -------------------------------------------------------------- batches
+    def fine_batch(self, seeds):
+        torch = self.torch
+        b = phx.Batch([(self.nf, self.nf)] * len(seeds), [self.cfg_f], precision=phx.PHX_C64, device=self.dev)
+        P = torch.from_numpy(self.P[0]).to(self.dev, torch.float32)
+        for k, s in enumerate(seeds):
+            psi = inputs.random_state((self.nf, self.nf), int(s), 1e-3)
+            b.view(b.psi, k).copy_(torch.from_numpy(psi).to(torch.complex64))
+            b.view(b.P, k).copy_(P)
+        return b
+
+    def coarse_batch(self, count, cfg=None):
+        return phx.Batch([(self.nc, self.nc)] * count, [cfg or self.cfg_c], precision=phx.PHX_C64, device=self.dev)
+
+    def coarsen_into(self, fine, coarse, k_f, k_c=None):
+        k_c = k_f if k_c is None else k_c
+        phx.phx_coarsen(phx.PHX_C64, fine.view(fine.psi, k_f), fine.view(fine.n, k_f), fine.view(fine.P, k_f),
+                        self.nf, self.nf, self.f, coarse.view(coarse.psi, k_c), coarse.view(coarse.n, k_c),
+                        coarse.view(coarse.P, k_c))
+
+    def features(self, coarse, k, out):
+        phx.phx_corrector_features(phx.PHX_C64, coarse.view(coarse.psi, k), coarse.view(coarse.n, k),
+                                   coarse.view(coarse.P, k), self.nc, self.nc, math.sqrt(RHO_S), N_S, self.pth, out)
+
+    # -------------------------------------------------------------- data
+    def generate(self, seeds, snapshots=20, every=500, log=print):
+        """Training pairs from fine trajectories: (features, residual) tensors of
+        shape [len(seeds)*snapshots, nc, nc, 4] and [..., 3]."""
+        torch = self.torch
+        n = len(seeds)
+        fine = self.fine_batch(seeds)
+        coarse = self.coarse_batch(n)
+        ref = self.coarse_batch(n)
+        X = torch.empty((n * snapshots, self.nc, self.nc, 4), dtype=torch.float32, device=self.dev)
+        R = torch.empty((n * snapshots, self.nc, self.nc, 3), dtype=torch.float32, device=self.dev)
+        t0 = time.time()
+        for s in range(snapshots):
+            fine.step(every - self.f)
+            for k in range(n):
+                self.coarsen_into(fine, coarse, k)
+                self.features(coarse, k, X[s * n + k])
+            coarse.step(1)
+            fine.step(self.f)
+            for k in range(n):
+                self.coarsen_into(fine, ref, k)
+                phx.phx_corrector_residual(phx.PHX_C64, ref.view(ref.psi, k), ref.view(ref.n, k),
+                                           coarse.view(coarse.psi, k), coarse.view(coarse.n, k), self.nc, self.nc,
+                                           math.sqrt(RHO_S), N_S, R[s * n + k])
+            torch.cuda.synchronize()
+            log(f"snapshot {s + 1}/{snapshots} t={(s + 1) * every * self.ph.dt:.1f} ({time.time() - t0:.1f}s)")
+        return X, R
+
+    # -------------------------------------------------------------- training
+    def train(self, X, R, epochs=10, batch=16, lr=1e-3, seed=0, log=print):
+        torch = self.torch
+        net = phx.Corrector(self.nc, self.nc, batch, device=self.dev)
+        net.init_random(seed)
+        rng = np.random.default_rng(seed)
+        n = X.shape[0]
+        steps = 0
+        history = []
+        t0 = time.time()
+        total = epochs * (n // batch)
+        for ep in range(epochs):
+            perm = torch.from_numpy(rng.permutation(n)).to(self.dev)
+            run = 0.0
+            for b in range(n // batch):
+                idx = perm[b * batch:(b + 1) * batch]
+                xb = X.index_select(0, idx).contiguous()
+                rb = R.index_select(0, idx).contiguous()
+                frac = steps / max(1, total)
+                cur_lr = lr * 0.5 * (1 + math.cos(math.pi * frac))  # cosine decay
+                net.train_step(xb, rb, cur_lr)
+                steps += 1
+                if b % 50 == 0:
+                    run = net.loss.item()
+            history.append(run)
+            log(f"epoch {ep + 1}/{epochs} loss {run:.4e} ({time.time() - t0:.1f}s)")
+        torch.cuda.synchronize()
+        return net, history, time.time() - t0
+
+    # -------------------------------------------------------------- evaluation
+    def evaluate(self, net, seeds, t_start=5000, horizons=(8, 64, 512), log=print):
+        """Relative L2 errors (density |psi|^2 and reservoir n on the coarse grid)
+        of coarse+corrector, plain coarse (256^2) and plain 512^2 against the fine
+        1024^2 reference, from shared starts D(fine state at t_start), plus the
+        GPU time of each run."""
+        torch = self.torch
+        n = len(seeds)
+        fine0 = self.fine_batch(seeds)
+        fine0.step(t_start)
+        nm = self.nf // 2
+        cfg_m = coarse_config(self.ph, nm, self.ph.dt * 2)
+        results = {}
+        for H in horizons:
+            assert H % self.f == 0
+            fine = self.fine_batch(seeds)
+            fine.psi.copy_(fine0.psi)
+            fine.n.copy_(fine0.n)
+            plain = self.coarse_batch(n)
+            corr = self.coarse_batch(n)
+            mid = phx.Batch([(nm, nm)] * n, [cfg_m], precision=phx.PHX_C64, device=self.dev)
+            for k in range(n):
+                self.coarsen_into(fine, plain, k)
+                self.coarsen_into(fine, corr, k)
+                phx.phx_coarsen(phx.PHX_C64, fine.view(fine.psi, k), fine.view(fine.n, k), fine.view(fine.P, k),
+                                self.nf, self.nf, 2, mid.view(mid.psi, k), mid.view(mid.n, k), mid.view(mid.P, k))
+            torch.cuda.synchronize()
+            timings = {}
+
+            def timed(name, fn):
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                fn()
+                torch.cuda.synchronize()
+                timings[name] = time.perf_counter() - t
+
+            timed("fine_1024", lambda: fine.step(H))
+            timed("plain_256", lambda: plain.step(H // self.f))
+            timed("plain_512", lambda: mid.step(H // 2))
+            x = torch.empty((n, self.nc, self.nc, 4), dtype=torch.float32, device=self.dev)
+            y = torch.empty((n, self.nc, self.nc, 3), dtype=torch.float32, device=self.dev)
+            big = phx.Corrector(self.nc, self.nc, n, device=self.dev)
+            big.params.copy_(net.params)
+
+            def corrected():
+                for _ in range(H // self.f):
+                    for k in range(n):
+                        self.features(corr, k, x[k])
+                    big.forward(x, y)
+                    corr.step(1)
+                    for k in range(n):
+                        phx.phx_corrector_apply(phx.PHX_C64, corr.view(corr.psi, k), corr.view(corr.n, k), y[k],
+                                                self.nc, self.nc, math.sqrt(RHO_S), N_S)
+
+            timed("corrected_256", corrected)
+            big.close()
+            ref = self.coarse_batch(n)
+            mid_c = self.coarse_batch(n)
+            for k in range(n):
+                self.coarsen_into(fine, ref, k)
+                phx.phx_coarsen(phx.PHX_C64, mid.view(mid.psi, k), mid.view(mid.n, k), mid.view(mid.P, k), nm, nm,
+                                2, mid_c.view(mid_c.psi, k), mid_c.view(mid_c.n, k), mid_c.view(mid_c.P, k))
+            torch.cuda.synchronize()
+
+            def err(b):
+                rho = (b.psi.abs() ** 2).double()
+                rho_r = (ref.psi.abs() ** 2).double()
+                e_rho = float(torch.linalg.norm(rho - rho_r) / torch.linalg.norm(rho_r))
+                e_n = float(torch.linalg.norm(b.n.double() - ref.n.double()) / torch.linalg.norm(ref.n.double()))
+                return e_rho, e_n
+
+            res = {"fine_steps": H, "gpu_seconds": timings}
+            for name, b in (("plain_256", plain), ("plain_512", mid_c), ("corrected_256", corr)):
+                e = err(b)
+                res[name] = {"rel_l2_density": e[0], "rel_l2_reservoir": e[1]}
+            results[str(H)] = res
+            log(json.dumps({str(H): res}))
+        return results
+
+
+def speedup_at(results, target=1e-3, key="rel_l2_density"):
+    """Speedup of the corrected coarse run over the cheapest plain run that reaches
+    `target` at each horizon (the fine 1024^2 run is the reference, error 0)."""
+    out = {}
+    for H, r in results.items():
+        t = r["gpu_seconds"]
+        plain = [(t["plain_256"], r["plain_256"][key]), (t["plain_512"], r["plain_512"][key]),
+                 (t["fine_1024"], 0.0)]
+        cheapest = min(c for c, e in plain if e <= target)
+        e_c = r["corrected_256"][key]
+        out[H] = {"corrected_error": e_c, "meets_target": e_c <= target,
+                  "plain_cost_at_target_s": cheapest, "corrected_cost_s": t["corrected_256"],
+                  "speedup": cheapest / t["corrected_256"] if e_c <= target else None,
+                  "gain_over_plain_256": r["plain_256"][key] / max(e_c, 1e-300)}
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--train-traj", type=int, default=500)
+    ap.add_argument("--eval-traj", type=int, default=50)
+    ap.add_argument("--snapshots", type=int, default=20)
+    ap.add_argument("--every", type=int, default=500)
+    ap.add_argument("--epochs", type=int, default=10)
+    ap.add_argument("--batch", type=int, default=16)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--t-start", type=int, default=5000)
+    ap.add_argument("--n-fine", type=int, default=1024)
+    ap.add_argument("--out", default=None)
+    args = ap.parse_args()
+    pl = Pipeline(n_fine=args.n_fine)
+    log = lambda s: print(s, flush=True)
+    t0 = time.time()
+    X, R = pl.generate(list(range(10000, 10000 + args.train_traj)), args.snapshots, args.every, log)
+    t_gen = time.time() - t0
+    net, hist, t_train = pl.train(X, R, args.epochs, args.batch, args.lr, log=log)
+    del X, R
+    res = pl.evaluate(net, list(range(20000, 20000 + args.eval_traj)), args.t_start, log=log)
+    rep = {"train_trajectories": args.train_traj, "snapshots": args.snapshots, "every": args.every,
+           "epochs": args.epochs, "batch": args.batch, "lr": args.lr, "loss_history": hist,
+           "generate_seconds": t_gen, "train_seconds": t_train, "eval": res, "speedup_1e-3": speedup_at(res)}
+    print(json.dumps(rep), flush=True)
+    if args.out:
+        with open(args.out, "w") as f:
+            json.dump(rep, f, indent=1)
+
+
+if __name__ == "__main__":
+    main()
