@@ -1,6 +1,8 @@
 """Coarse grid + learned corrector standing in for the fine grid (driven workload).
 
-Fine grid: the driven-dissipative workload at 1024^2 (dx 0.2, RK4 dt 0.02).
+Fine grid: the driven-dissipative workload at 1024^2 (dx 0.2, RK4 dt 0.02), every
+trajectory started from a condensate seeded on the ring pump (the pump alone does
+not condense within the run from noise), snapshots every 250 steps.
 Coarse grid: 256^2 over the same domain (dx 0.8) with RK4 dt 0.08 = 4 fine steps.
 D is the 4x4 block mean.  Network input: features of a coarse state (Re psi,
 Im psi scaled by sqrt(rho_s), n by n_s, P by P_th, rho_s = 22.5 and n_s = 15 the
@@ -56,12 +58,14 @@ class Pipeline:
 
     # -------------------------------------------------------------- batches
     def fine_batch(self, seeds):
+        """Fine trajectories started from seeded ring condensates (inputs.ring_condensate)."""
         torch = self.torch
         b = phx.Batch([(self.nf, self.nf)] * len(seeds), [self.cfg_f], precision=phx.PHX_C64, device=self.dev)
         P = torch.from_numpy(self.P[0]).to(self.dev, torch.float32)
         for k, s in enumerate(seeds):
-            psi = inputs.random_state((self.nf, self.nf), int(s), 1e-3)
-            b.view(b.psi, k).copy_(torch.from_numpy(psi).to(torch.complex64))
+            _, psi, n0, _ = inputs.ring_condensate(self.nf, int(s), self.ph.dx)
+            b.view(b.psi, k).copy_(torch.from_numpy(psi[0]).to(torch.complex64))
+            b.view(b.n, k).copy_(torch.from_numpy(n0[0]).to(torch.float32))
             b.view(b.P, k).copy_(P)
         return b
 
@@ -79,7 +83,7 @@ class Pipeline:
                                    coarse.view(coarse.P, k), self.nc, self.nc, math.sqrt(RHO_S), N_S, self.pth, out)
 
     # -------------------------------------------------------------- data
-    def generate(self, seeds, snapshots=20, every=500, log=print):
+    def generate(self, seeds, snapshots=20, every=250, log=print):
         """Training pairs from fine trajectories: (features, residual) tensors of
         shape [len(seeds)*snapshots, nc, nc, 4] and [..., 3]."""
         torch = self.torch
@@ -107,8 +111,20 @@ class Pipeline:
         return X, R
 
     # -------------------------------------------------------------- training
+    def target_scales(self, R):
+        """RMS of the psi channels (together) and of the n channel of the residuals;
+        the network is trained on the residual divided by these."""
+        sp = float(R[..., :2].double().pow(2).mean().sqrt())
+        sn = float(R[..., 2].double().pow(2).mean().sqrt())
+        return max(sp, 1e-12), max(sn, 1e-12)
+
     def train(self, X, R, epochs=10, batch=16, lr=1e-3, seed=0, log=print):
         torch = self.torch
+        sp, sn = self.target_scales(R)
+        self.r_scale = (sp, sn)
+        R[..., :2] /= sp
+        R[..., 2] /= sn
+        log(f"residual rms: psi {sp:.3e}, n {sn:.3e} (targets normalized)")
         net = phx.Corrector(self.nc, self.nc, batch, device=self.dev)
         net.init_random(seed)
         rng = np.random.default_rng(seed)
@@ -136,7 +152,7 @@ class Pipeline:
         return net, history, time.time() - t0
 
     # -------------------------------------------------------------- evaluation
-    def evaluate(self, net, seeds, t_start=5000, horizons=(8, 64, 512), log=print):
+    def evaluate(self, net, seeds, t_start=2500, horizons=(8, 64, 512), log=print):
         """Relative L2 errors (density |psi|^2 and reservoir n on the coarse grid)
         of coarse+corrector, plain coarse (256^2) and plain 512^2 against the fine
         1024^2 reference, from shared starts D(fine state at t_start), plus the
@@ -187,7 +203,8 @@ class Pipeline:
                     corr.step(1)
                     for k in range(n):
                         phx.phx_corrector_apply(phx.PHX_C64, corr.view(corr.psi, k), corr.view(corr.n, k), y[k],
-                                                self.nc, self.nc, math.sqrt(RHO_S), N_S)
+                                                self.nc, self.nc, math.sqrt(RHO_S) * self.r_scale[0],
+                                                N_S * self.r_scale[1])
 
             timed("corrected_256", corrected)
             big.close()
@@ -237,11 +254,11 @@ def main():
     ap.add_argument("--train-traj", type=int, default=500)
     ap.add_argument("--eval-traj", type=int, default=50)
     ap.add_argument("--snapshots", type=int, default=20)
-    ap.add_argument("--every", type=int, default=500)
+    ap.add_argument("--every", type=int, default=250)
     ap.add_argument("--epochs", type=int, default=10)
     ap.add_argument("--batch", type=int, default=16)
     ap.add_argument("--lr", type=float, default=1e-3)
-    ap.add_argument("--t-start", type=int, default=5000)
+    ap.add_argument("--t-start", type=int, default=2500)
     ap.add_argument("--n-fine", type=int, default=1024)
     ap.add_argument("--out", default=None)
     args = ap.parse_args()
