@@ -29,7 +29,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "grid-point RK4 updates/s + HBM GB/s at 4096² c64; surrogate vs plain at L2 1e-3"
 HBM_PEAK_GBPS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "rk4_stage_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "rk4_traffic.json")
 COPY_BYTES = 1 << 30
 
 

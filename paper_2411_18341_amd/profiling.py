@@ -23,7 +23,8 @@ from collections import defaultdict
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 # sources whose change invalidates a stored counter measurement of the RK4 kernels
 KERNEL_SOURCES = ["paper_2411_18341_amd/csrc/rk4.hip", "paper_2411_18341_amd/csrc/stencil.h",
-                  "paper_2411_18341_amd/csrc/phx_kernels.h", "paper_2411_18341_amd/csrc/rk4_step.hip"]
+                  "paper_2411_18341_amd/csrc/phx_kernels.h", "paper_2411_18341_amd/csrc/rk4_step.hip",
+                  "paper_2411_18341_amd/csrc/step_body.h"]
 
 
 def kernel_source_hash() -> str:
@@ -42,10 +43,12 @@ def kernel_kind(name: str) -> str:
     m = re.search(r"(rk4_stage_kernel|dp_stage_kernel)<[^>]*?(\d+)>", name)
     if m:
         return ("rk4_stage" if m.group(1).startswith("rk4") else "dp_stage") + m.group(2)
-    for k in ("rk4_step_kernel", "batch_stage_kernel", "dp_restart_kernel", "dp_err_sum_kernel",
-              "obs_pass1", "obs_pass2"):
+    named = {"rk4_step_kernel": "rk4_step", "batch_step_kernel": "batch_step", "dp_restart_kernel": "dp_restart",
+             "dp_err_sum_kernel": "dp_error", "obs_pass1": "obs_pass1", "obs_pass2": "obs_pass2",
+             "conv_fwd_kernel": "conv_fwd", "conv_bwd_weight_kernel": "conv_bwd_weight"}
+    for k, v in named.items():
         if k in name:
-            return k
+            return v
     return name[:60]
 
 

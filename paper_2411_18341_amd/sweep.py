@@ -1,0 +1,98 @@
+"""Throughput against grid size, the analogue of the paper's Fig. 4 (Sec. 4.2), and
+the per-kernel time split, the analogue of its Fig. 5 (Sec. 4.4).
+
+For each side N the driven-dissipative workload (complex64 psi, float32 n, ring
+pump, RK4 dt 0.02, periodic) runs on one GPU with each RK4 kernel family:
+  stage  four stage-fused launches per step (220 B/pt of algorithmic traffic)
+  step   one whole-step launch per step (28 B/pt)
+after a tile-shape search for that size.  Reported per (N, family): grid-point
+updates per second, the algorithmic GB/s of the step, and the mean time of every
+kernel launched (HIP events on the solver's stream).  Small grids fit the 256 MB
+Infinity Cache and launch overhead dominates the smallest; large ones stream
+from HBM.
+
+    python -m paper_2411_18341_amd.sweep --sizes 128 256 512 1024 2048 4096 8192 --out sweep.md
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import time
+
+from . import bytemodel, inputs, phx
+
+
+def steps_for(n: int) -> int:
+    """Timed step count: about 4e9 point updates per measurement, within [50, 5000]."""
+    return max(50, min(5000, int(4e9 / (n * n))))
+
+
+def measure(n: int, family: str, precision=phx.PHX_C64, warmup: int = 20, tune_reps: int = 5):
+    import torch
+    ph, psi0, n0, P = inputs.driven(n)
+    cdt, rdt = phx.torch_dtypes(precision)
+    dev = torch.device("cuda:0")
+    psi = torch.from_numpy(psi0).to(dtype=cdt, device=dev).contiguous()
+    nn = torch.from_numpy(n0).to(dtype=rdt, device=dev).contiguous()
+    Pd = torch.from_numpy(P).to(dtype=rdt, device=dev).contiguous()
+    del psi0, n0, P
+    kernel = {"stage": phx.PHX_KERNEL_STAGE, "step": phx.PHX_KERNEL_STEP}[family]
+    cfg = phx.config_from_physics(ph, precision=precision, kernel=kernel)
+    solver = phx.Solver(cfg, psi, nn, None, Pd)
+    try:
+        tune = solver.autotune(reps=tune_reps, use_cache=False)
+        steps = steps_for(n)
+        solver.step(warmup)
+        torch.cuda.synchronize()
+        solver.set_timing(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        solver.step(steps)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        times = solver.kernel_times()
+    finally:
+        solver.close()
+    real_bytes = 4 if precision == phx.PHX_C64 else 8
+    model = (bytemodel.rk4_whole_step if family == "step" else bytemodel.rk4_stage_fused)(
+        real_bytes, reservoir=True, has_v=False)
+    cells = n * n
+    return {
+        "n": n, "family": family, "steps": steps, "tile": [tune["tile_wx"], tune["tile_rows"]],
+        "UPs": cells * steps / wall, "us_per_step": wall / steps * 1e6,
+        "algorithmic_GBps": model["step"] * cells * steps / wall / 1e9,
+        "kernels_us": {k: v["ms_total"] / v["launches"] * 1e3 for k, v in times.items()},
+    }
+
+
+def table(rows) -> str:
+    out = ["| N | family | tile | steps | µs/step | G UP/s | algorithmic GB/s | mean launch µs per kernel |",
+           "|---|---|---|---|---|---|---|---|"]
+    for r in rows:
+        ks = ", ".join(f"{k} {v:.2f}" for k, v in sorted(r["kernels_us"].items()))
+        out.append(f"| {r['n']} | {r['family']} | {r['tile'][0]}x{r['tile'][1]} | {r['steps']} | "
+                   f"{r['us_per_step']:.2f} | {r['UPs'] / 1e9:.2f} | {r['algorithmic_GBps']:.0f} | {ks} |")
+    return "\n".join(out)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--sizes", type=int, nargs="+", default=[128, 256, 512, 1024, 2048, 4096, 8192])
+    ap.add_argument("--families", nargs="+", default=["stage", "step"], choices=["stage", "step"])
+    ap.add_argument("--out", default=None, help="write the markdown table here")
+    args = ap.parse_args()
+    rows = []
+    for n in args.sizes:
+        for fam in args.families:
+            r = measure(n, fam)
+            rows.append(r)
+            print(json.dumps(r), flush=True)
+    md = table(rows)
+    print(md, flush=True)
+    if args.out:
+        with open(args.out, "w") as f:
+            f.write(md + "\n")
+
+
+if __name__ == "__main__":
+    main()
