@@ -90,6 +90,8 @@ def main():
     ap.add_argument("--kernel", choices=["auto", "stage", "step"], default="auto",
                     help="RK4 kernel family (auto: whole-step kernel)")
     ap.add_argument("--no-tune", action="store_true", help="skip the tile-shape search before timing")
+    ap.add_argument("--tile", type=int, nargs=2, metavar=("WX", "ROWS"), default=None,
+                    help="force this tile shape (no search)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -119,8 +121,13 @@ def main():
     Pd = torch.from_numpy(P).to(dtype=rdt, device=dev).contiguous()
     family = {"auto": phx.PHX_KERNEL_AUTO, "stage": phx.PHX_KERNEL_STAGE, "step": phx.PHX_KERNEL_STEP}[args.kernel]
     cfg = phx.config_from_physics(ph, precision=precision, kernel=family)
+    if args.tile:
+        cfg.tile_wx, cfg.tile_rows = args.tile
     solver = phx.Solver(cfg, psi, n, None, Pd)
-    tune = solver.autotune(reps=10, use_cache=False) if not args.no_tune else None
+    if args.tile:
+        tune = {"tile_wx": args.tile[0], "tile_rows": args.tile[1]}
+    else:
+        tune = solver.autotune(reps=10, use_cache=False) if not args.no_tune else None
 
     copy_gbps = copy_bandwidth_gbps(torch)
 

@@ -97,7 +97,7 @@ __global__ __launch_bounds__(256) void dp_stage_kernel(const DpArgs<R> a)
             const R v = HASV ? a.V[idx] : R(0);
             C f[COMPS];
             R rho[COMPS];
-            rhs_cell<R, COMPS>(a.c, U, M, D, nn, v, f, rho);
+            rhs_cell<R, COMPS, HASV>(a.c, U, M, D, nn, v, f, rho);
 #pragma unroll
             for (int s = 0; s < COMPS; ++s) {
                 const int o = s * cs + idx;

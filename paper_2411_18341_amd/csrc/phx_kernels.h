@@ -17,7 +17,7 @@ template <> struct cvec<double> { using type = double2; };
 
 // Right-hand-side coefficients, formed in double on the host and rounded once.
 //   d psi_s/dt = i T - sgn bxy X + (u - i w) psi_s,   u = (R n - gamma_c)/2,
-//   w = (V + g rho_s + g_x rho_o + g_r n)/hbar,
+//   w = (V + g rho_s + g_x rho_o + g_r n)/hbar (1/hbar folded into the coefficients),
 //   T = ax Dxx' psi_s + ay Dyy' psi_s - bx Dxx' psi_o + by Dyy' psi_o,
 //   X = psi_o[i+1,j+1] - psi_o[i+1,j-1] - psi_o[i-1,j+1] + psi_o[i-1,j-1],
 // where Dxx' f = f[i+1] + f[i-1] - 2 f[i] (undivided second difference),
@@ -28,7 +28,7 @@ template <typename R>
 struct Coef {
     R ax, ay;
     R inv_hbar;
-    R g, g_x, g_r;
+    R gh, gxh, grh;           // g/hbar, g_x/hbar, g_r/hbar: w = V/hbar + gh rho_s + gxh rho_o + grh n
     R half_R, half_gamma;
     R R_, gamma_r;
     R bx, by, bxy;

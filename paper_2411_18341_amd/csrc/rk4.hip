@@ -54,7 +54,7 @@ __global__ __launch_bounds__(256) void rk4_stage_kernel(const Rk4Args<R> a)
         const R v = HASV ? a.V[idx] : R(0);
         C f[COMPS];
         R rho[COMPS];
-        rhs_cell<R, COMPS>(a.c, U, M, D, nn, v, f, rho);
+        rhs_cell<R, COMPS, HASV>(a.c, U, M, D, nn, v, f, rho);
 #pragma unroll
         for (int s = 0; s < COMPS; ++s) {
             const int o = s * cs + idx;

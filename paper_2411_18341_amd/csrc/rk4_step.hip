@@ -46,7 +46,7 @@ static hipError_t launch_step_t(const StepArgs<R>& a, hipStream_t s)
 // recompute less halo, shorter ones need fewer registers per lane (more waves
 // per SIMD).  The first entry is the default; phx_autotune measures them all.
 static const StepShapeId kFloatShapes[] = {{8, 4}, {16, 4}, {8, 8}, {12, 4}, {12, 6}, {8, 6}, {4, 8}, {16, 6}};
-static const StepShapeId kDoubleShapes[] = {{8, 4}, {16, 2}, {8, 2}, {16, 4}, {12, 4}, {4, 4}};
+static const StepShapeId kDoubleShapes[] = {{8, 4}, {16, 2}, {8, 2}, {12, 4}, {4, 4}};
 
 int step_shapes(int precision, const StepShapeId** out)
 {
@@ -67,7 +67,7 @@ static hipError_t launch_step_shape(const StepShapeId& sh, const StepArgs<R>& a,
         PHX_SHAPE(8, 4); PHX_SHAPE(16, 4); PHX_SHAPE(8, 8); PHX_SHAPE(12, 4);
         PHX_SHAPE(12, 6); PHX_SHAPE(8, 6); PHX_SHAPE(4, 8); PHX_SHAPE(16, 6);
     } else {
-        PHX_SHAPE(8, 4); PHX_SHAPE(16, 2); PHX_SHAPE(8, 2); PHX_SHAPE(16, 4); PHX_SHAPE(12, 4); PHX_SHAPE(4, 4);
+        PHX_SHAPE(8, 4); PHX_SHAPE(16, 2); PHX_SHAPE(8, 2); PHX_SHAPE(12, 4); PHX_SHAPE(4, 4);
     }
 #undef PHX_SHAPE
     return hipErrorInvalidValue;

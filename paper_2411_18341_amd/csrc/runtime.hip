@@ -176,9 +176,9 @@ Coef<R> make_coef(const phx_config& c)
     k.ax = (R)(c.hbar / (2.0 * c.mass * c.dx * c.dx));
     k.ay = (R)(c.hbar / (2.0 * c.mass * c.dy * c.dy));
     k.inv_hbar = (R)(1.0 / c.hbar);
-    k.g = (R)c.g;
-    k.g_x = (R)c.g_x;
-    k.g_r = (R)c.g_r;
+    k.gh = (R)(c.g / c.hbar);
+    k.gxh = (R)(c.g_x / c.hbar);
+    k.grh = (R)(c.g_r / c.hbar);
     k.half_R = (R)(0.5 * c.R);
     k.half_gamma = (R)(0.5 * c.gamma_c);
     k.R_ = (R)c.R;

@@ -65,9 +65,10 @@ __device__ __forceinline__ Row3<C> load_row(const C* __restrict__ f, int j, int 
 }
 
 // Right-hand side at the centre of the windows (U: row j-1, M: row j, D: row j+1)
-// for every component.  nn are the reservoir values, v the potential.  Writes
-// f_psi and rho = |psi|^2 per component.  See Coef for the formula.
-template <typename R, int COMPS>
+// for every component.  nn are the reservoir values, v the potential (ignored
+// without HASV).  Writes f_psi and rho = |psi|^2 per component.  See Coef for the
+// formula; the one-component form skips the coupling terms altogether.
+template <typename R, int COMPS, bool HASV = true>
 __device__ __forceinline__ void rhs_cell(const Coef<R>& k,
                                          const Row3<typename cvec<R>::type> (&U)[COMPS],
                                          const Row3<typename cvec<R>::type> (&M)[COMPS],
@@ -92,8 +93,10 @@ __device__ __forceinline__ void rhs_cell(const Coef<R>& k,
         const R syy_y = U[s].c.y + D[s].c.y - R(2) * p.y;
         R tx = k.ax * sxx_x + k.ay * syy_x;
         R ty = k.ax * sxx_y + k.ay * syy_y;
-        R w = v + k.g * rho[s] + k.g_r * nn[s];
-        R fx = R(0), fy = R(0);
+        // w / hbar (the potential enters only when present)
+        R om = k.gh * rho[s] + k.grh * nn[s];
+        if (HASV) om += k.inv_hbar * v;
+        const R u = k.half_R * nn[s] - k.half_gamma;
         if (COMPS == 2) {
             const C q = M[o].c;
             const R oxx_x = M[o].l.x + M[o].r.x - R(2) * q.x;
@@ -102,19 +105,19 @@ __device__ __forceinline__ void rhs_cell(const Coef<R>& k,
             const R oyy_y = U[o].c.y + D[o].c.y - R(2) * q.y;
             tx += -k.bx * oxx_x + k.by * oyy_x;
             ty += -k.bx * oxx_y + k.by * oyy_y;
-            w += k.g_x * rho[o];
+            om += k.gxh * rho[o];
             // X = o[i+1,j+1] - o[i+1,j-1] - o[i-1,j+1] + o[i-1,j-1]
             const R xx = (D[o].r.x - U[o].r.x) - (D[o].l.x - U[o].l.x);
             const R xy = (D[o].r.y - U[o].r.y) - (D[o].l.y - U[o].l.y);
             const R sb = (s == 0) ? -k.bxy : k.bxy;  // -sgn * bxy
-            fx = sb * xx;
-            fy = sb * xy;
+            // i T + (u - i om) p - sgn bxy X
+            f[s].x = sb * xx - ty + u * p.x + om * p.y;
+            f[s].y = sb * xy + tx + u * p.y - om * p.x;
+        } else {
+            // i T + (u - i om) p
+            f[s].x = u * p.x + om * p.y - ty;
+            f[s].y = u * p.y - om * p.x + tx;
         }
-        const R om = w * k.inv_hbar;
-        const R u = k.half_R * nn[s] - k.half_gamma;
-        // i T + (u - i om) p
-        f[s].x = fx - ty + u * p.x + om * p.y;
-        f[s].y = fy + tx + u * p.y - om * p.x;
     }
 }
 

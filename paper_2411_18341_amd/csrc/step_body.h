@@ -70,51 +70,32 @@ __device__ __forceinline__ int wrap_any(int g, int n, int bc)
     return m < 0 ? m + n : m;
 }
 
-// One whole RK4 step of the region `tile` of the grid described by `a`, computed
-// by the WAVES waves of the calling workgroup; `edge` is the workgroup's LDS
-// exchange buffer.  Returns true (in every lane that stored a cell) when a stored
-// value is not finite.  Every thread of the workgroup must call it (barriers).
-template <typename R, bool RES, bool HASV, bool GHOSTS, int WAVES, int ROWS>
-__device__ __forceinline__ bool step_region(const StepArgs<R>& a, int tile,
+// The four stages of one region, run by one wave over its ROWS rows.  EDGE waves
+// hold region rows that some stage skips (the first and last 4 rows of the region);
+// the other waves run every row of every stage with no per-row test, so that the
+// unrolled code has no branch joins (and no register copies at them).
+//
+// Per cell, with p = the stage argument, lr / ud the sums of its left+right and
+// up+down neighbours, and kv = V/hbar + 2 (ax + ay) held for the whole step:
+//   om = kv + g_r/hbar n + g/hbar |p|^2,   u = (R n - gamma_c)/2,
+//   f.x = u p.x + om p.y - (ax lr.y + ay ud.y)
+//   f.y = u p.y - om p.x + (ax lr.x + ay ud.x)
+// which is i (hbar/2m) Lap p + (u - i w) p of Eq. (1) / Eq. (PULSE_psi) with the
+// -2(ax+ay) p centre term of the five-point Laplacian folded into om.
+template <typename R, bool RES, bool HASV, bool GHOSTS, int WAVES, int ROWS, bool EDGE>
+__device__ __forceinline__ void step_stages(const StepArgs<R>& a, int lane, int wave,
+                                            unsigned int ghost,
+                                            const typename cvec<R>::type (&p0)[ROWS],
+                                            typename cvec<R>::type (&y)[ROWS],
+                                            const R (&n0)[ROWS], R (&yn)[ROWS],
+                                            const R (&pp)[ROWS], const R (&kv)[ROWS],
                                             typename cvec<R>::type (&edge)[2][WAVES][2][64])
 {
     using C = typename cvec<R>::type;
     constexpr int H = WAVES * ROWS;
-    constexpr int OW = 56, OH = H - 8;
-
-    const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
-    const int tx = tile % a.tiles_x;
-    const int ty = tile / a.tiles_x;
-    const int gi = tx * OW - 4 + lane;
-    const int ci = wrap_any(gi, a.nx, a.bcx);
-    const int row0 = ty * OH - 4 + wave * ROWS;
-
-    C p0[ROWS], y[ROWS], acc[ROWS];
-    R n0[ROWS], yn[ROWS], accn[ROWS], pp[ROWS], vv[ROWS];
-    unsigned int ghost = 0;  // bit k: row k of this lane is a ghost cell
-#pragma unroll
-    for (int k = 0; k < ROWS; ++k) {
-        const int rj = wrap_any(row0 + k, a.ny, a.bcy);
-        const bool g = GHOSTS && (ci < 0 || rj < 0);
-        ghost |= (g ? 1u : 0u) << k;
-        const int idx = g ? 0 : rj * a.nx + ci;
-        const C v = a.psi_in[idx];
-        p0[k] = g ? czero<C>() : v;
-        if (RES) {
-            const R nv = a.n_in[idx];
-            const R pv = a.P[idx];
-            n0[k] = g ? R(0) : nv;
-            pp[k] = g ? R(0) : pv;
-        }
-        if (HASV) {
-            const R vv_ = a.V[idx];
-            vv[k] = g ? R(0) : vv_;
-        }
-        y[k] = p0[k];
-        if (RES) yn[k] = n0[k];
-    }
-
+    const Coef<R>& c = a.c;
+    C acc[ROWS];
+    R accn[ROWS];
 #pragma unroll
     for (int s = 1; s <= 4; ++s) {
         const int par = s & 1;
@@ -128,48 +109,134 @@ __device__ __forceinline__ bool step_region(const StepArgs<R>& a, int tile,
         for (int k = 0; k < ROWS; ++k) {
             const C cur = y[k];
             const C nxt = (k + 1 < ROWS) ? y[k + 1] : below;
-            // Stage s only feeds the rows [s, H-s) of the region that the output
-            // rows depend on; the branch is uniform over the wave.
-            const int r = wave * ROWS + k;
-            if (r < s || r >= H - s) {
-                prev = cur;
-                continue;
+            if (EDGE) {
+                // stage s only feeds the region rows [s, H-s) that the output depends on
+                const int r = wave * ROWS + k;
+                if (r < s || r >= H - s) {
+                    prev = cur;
+                    continue;
+                }
             }
-            Row3<C> U[1], M[1], D[1];
-            M[0].c = cur;
-            M[0].l = C{lane_prev(cur.x), lane_prev(cur.y)};
-            M[0].r = C{lane_next(cur.x), lane_next(cur.y)};
-            U[0].c = prev;
-            D[0].c = nxt;
-            U[0].l = U[0].r = D[0].l = D[0].r = czero<C>();  // corners unused by the scalar stencil
-            R nn[1] = {RES ? yn[k] : R(0)};
-            C f[1];
-            R rho[1];
-            rhs_cell<R, 1>(a.c, U, M, D, nn, HASV ? vv[k] : R(0), f, rho);
+            const R lrx = lane_prev(cur.x) + lane_next(cur.x);
+            const R lry = lane_prev(cur.y) + lane_next(cur.y);
+            const R udx = prev.x + nxt.x;
+            const R udy = prev.y + nxt.y;
+            const R rho = fma(cur.x, cur.x, cur.y * cur.y);
+            R om = kv[k];
+            if (RES) om = fma(c.grh, yn[k], om);
+            om = fma(c.gh, rho, om);
+            const R u = RES ? fma(c.half_R, yn[k], -c.half_gamma) : -c.half_gamma;
+            const R tx = fma(c.ax, lrx, c.ay * udx);
+            const R ty = fma(c.ax, lry, c.ay * udy);
+            const R fx = fma(u, cur.x, fma(om, cur.y, -ty));
+            const R fy = fma(u, cur.y, fma(-om, cur.x, tx));
             R fn = R(0);
-            if (RES) fn = pp[k] - (a.c.gamma_r + a.c.R_ * rho[0]) * nn[0];
-            const bool g = GHOSTS && ((ghost >> k) & 1u);
-            if (s == 1) {
-                acc[k] = f[0];
-                if (RES) accn[k] = fn;
-            } else if (s < 4) {
-                acc[k] = C{acc[k].x + R(2) * f[0].x, acc[k].y + R(2) * f[0].y};
-                if (RES) accn[k] = accn[k] + R(2) * fn;
-            }
+            if (RES) fn = fma(-fma(c.R_, rho, c.gamma_r), yn[k], pp[k]);
             C nv;
             R nnv = R(0);
-            if (s < 4) {
-                nv = C{p0[k].x + adt * f[0].x, p0[k].y + adt * f[0].y};
-                if (RES) nnv = n0[k] + adt * fn;
-            } else {
-                nv = C{p0[k].x + a.dt6 * (acc[k].x + f[0].x), p0[k].y + a.dt6 * (acc[k].y + f[0].y)};
-                if (RES) nnv = n0[k] + a.dt6 * (accn[k] + fn);
+            if (s == 1) {
+                acc[k] = C{fx, fy};
+                if (RES) accn[k] = fn;
+            } else if (s < 4) {
+                acc[k] = C{fma(R(2), fx, acc[k].x), fma(R(2), fy, acc[k].y)};
+                if (RES) accn[k] = fma(R(2), fn, accn[k]);
             }
-            y[k] = (GHOSTS && g) ? czero<C>() : nv;
-            if (RES) yn[k] = (GHOSTS && g) ? R(0) : nnv;
+            if (s < 4) {
+                nv = C{fma(adt, fx, p0[k].x), fma(adt, fy, p0[k].y)};
+                if (RES) nnv = fma(adt, fn, n0[k]);
+            } else {
+                nv = C{fma(a.dt6, acc[k].x + fx, p0[k].x), fma(a.dt6, acc[k].y + fy, p0[k].y)};
+                if (RES) nnv = fma(a.dt6, accn[k] + fn, n0[k]);
+            }
+            const bool g = GHOSTS && ((ghost >> k) & 1u);
+            y[k] = g ? czero<C>() : nv;
+            if (RES) yn[k] = g ? R(0) : nnv;
             prev = cur;
         }
     }
+}
+
+// What a region's step reads from HBM, per lane and row of the calling wave: the
+// state, the pump, the per-cell part of om (kv) and the ghost mask.  Loading it is
+// separate from computing so that a persistent workgroup can fetch the next region
+// while it computes the current one.
+template <typename R, int ROWS>
+struct RegionIn {
+    typename cvec<R>::type p0[ROWS];
+    R n0[ROWS], pp[ROWS], kv[ROWS];
+    unsigned int ghost;  // bit k: row k of this lane is a ghost cell
+};
+
+// Issues the loads of region `tile` for the calling wave (no barrier, no LDS).
+template <typename R, bool RES, bool HASV, bool GHOSTS, int WAVES, int ROWS>
+__device__ __forceinline__ void load_region(const StepArgs<R>& a, int tile, RegionIn<R, ROWS>& in)
+{
+    using C = typename cvec<R>::type;
+    constexpr int OW = 56, OH = WAVES * ROWS - 8;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int tx = tile % a.tiles_x;
+    const int ty = tile / a.tiles_x;
+    const int ci = wrap_any(tx * OW - 4 + lane, a.nx, a.bcx);
+    const int row0 = ty * OH - 4 + wave * ROWS;
+    const R kdiag = R(2) * (a.c.ax + a.c.ay);
+    in.ghost = 0;
+#pragma unroll
+    for (int k = 0; k < ROWS; ++k) {
+        const int rj = wrap_any(row0 + k, a.ny, a.bcy);
+        const bool g = GHOSTS && (ci < 0 || rj < 0);
+        in.ghost |= (g ? 1u : 0u) << k;
+        const int idx = g ? 0 : rj * a.nx + ci;
+        const C v = a.psi_in[idx];
+        in.p0[k] = g ? czero<C>() : v;
+        if (RES) {
+            const R nv = a.n_in[idx];
+            const R pv = a.P[idx];
+            in.n0[k] = g ? R(0) : nv;
+            in.pp[k] = g ? R(0) : pv;
+        }
+        in.kv[k] = kdiag;
+        if (HASV) {
+            const R vv_ = a.V[idx];
+            in.kv[k] = g ? kdiag : fma(a.c.inv_hbar, vv_, kdiag);
+        }
+    }
+}
+
+// The four stages of region `tile` from its loaded inputs, then the store of its
+// interior.  Returns true (in every lane that stored a cell) when a stored value is
+// not finite.  Every thread of the workgroup must call it (barriers).
+template <typename R, bool RES, bool HASV, bool GHOSTS, int WAVES, int ROWS>
+__device__ __forceinline__ bool run_region(const StepArgs<R>& a, int tile, const RegionIn<R, ROWS>& in,
+                                           typename cvec<R>::type (&edge)[2][WAVES][2][64])
+{
+    using C = typename cvec<R>::type;
+    constexpr int H = WAVES * ROWS;
+    constexpr int OW = 56, OH = H - 8;
+    const int lane = threadIdx.x & 63;
+    // the wave index is the same in every lane: keep it in a scalar register so that
+    // the branches on it below are scalar branches, not lane masks
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int tx = tile % a.tiles_x;
+    const int ty = tile / a.tiles_x;
+    const int gi = tx * OW - 4 + lane;
+    const int row0 = ty * OH - 4 + wave * ROWS;
+
+    C y[ROWS];
+    R yn[ROWS];
+#pragma unroll
+    for (int k = 0; k < ROWS; ++k) {
+        y[k] = in.p0[k];
+        yn[k] = RES ? in.n0[k] : R(0);
+    }
+
+    // waves whose rows all lie in [4, H-4) run every row of every stage
+    if (wave * ROWS >= 4 && (wave + 1) * ROWS <= H - 4)
+        step_stages<R, RES, HASV, GHOSTS, WAVES, ROWS, false>(a, lane, wave, in.ghost, in.p0, y, in.n0, yn,
+                                                              in.pp, in.kv, edge);
+    else
+        step_stages<R, RES, HASV, GHOSTS, WAVES, ROWS, true>(a, lane, wave, in.ghost, in.p0, y, in.n0, yn,
+                                                             in.pp, in.kv, edge);
 
     // interior of the region: lanes 4..59, region rows 4..H-5, inside the grid
     bool bad = false;
@@ -190,6 +257,18 @@ __device__ __forceinline__ bool step_region(const StepArgs<R>& a, int tile,
         }
     }
     return bad;
+}
+
+// One whole RK4 step of the region `tile` of the grid described by `a`, computed
+// by the WAVES waves of the calling workgroup; `edge` is the workgroup's LDS
+// exchange buffer.  Every thread of the workgroup must call it (barriers).
+template <typename R, bool RES, bool HASV, bool GHOSTS, int WAVES, int ROWS>
+__device__ __forceinline__ bool step_region(const StepArgs<R>& a, int tile,
+                                            typename cvec<R>::type (&edge)[2][WAVES][2][64])
+{
+    RegionIn<R, ROWS> in;
+    load_region<R, RES, HASV, GHOSTS, WAVES, ROWS>(a, tile, in);
+    return run_region<R, RES, HASV, GHOSTS, WAVES, ROWS>(a, tile, in, edge);
 }
 
 }  // namespace phx

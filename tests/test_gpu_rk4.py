@@ -271,7 +271,7 @@ def test_checkpoint_resume_bitwise(family):
 
 
 STEP_SHAPES = {C64: [(8, 4), (16, 4), (8, 8), (12, 4), (12, 6), (8, 6), (4, 8), (16, 6)],
-               C128: [(8, 4), (16, 2), (8, 2), (16, 4), (12, 4), (4, 4)]}
+               C128: [(8, 4), (16, 2), (8, 2), (12, 4), (4, 4)]}
 
 
 @pytest.mark.parametrize("precision", PREC)

@@ -76,9 +76,23 @@ def test_dopri5_small_parity(case, precision):
     tol = TOL[precision]
     assert abs(info["t"] - ctrl.t) <= tol * ctrl.t
     assert abs(info["dt"] - ctrl.dt) <= 10 * tol * ctrl.dt
-    assert rel_l2(g_psi, o_psi) <= tol
+    # The controller sizes each step from an error estimate formed from kernel-precision
+    # stage values, so the two time grids differ by that estimate's rounding (1e-6 of t
+    # in complex64, checked above).  Compare the states at the same time: move the
+    # oracle's state to the GPU's final time along its derivative (first order; the
+    # second-order term is below 1e-9 here).
+    shift = info["t"] - ctrl.t
+    _, _, qV, qP = quantize(precision, *args[1:5])
+    f_psi, f_n = oracle.rhs(oracle_physics(ph), o_psi, o_n, qV, qP)
+    o_psi_t = o_psi + shift * f_psi
+    e_psi = rel_l2(g_psi, o_psi_t)
+    print(f"rel L2 psi {rel_l2(g_psi, o_psi):.3e} at the oracle's t, {e_psi:.3e} at the GPU's t "
+          f"(t shift {shift:.3e})")
+    assert e_psi <= tol
     if ph.reservoir:
-        assert rel_l2(g_n, o_n) <= tol
+        e_n = rel_l2(g_n, o_n + shift * f_n)
+        print(f"rel L2 n {rel_l2(g_n, o_n):.3e} at the oracle's t, {e_n:.3e} at the GPU's t")
+        assert e_n <= tol
 
 
 def test_dopri5_rejections_match():
