@@ -159,10 +159,12 @@ def main():
                          "GBps": nbytes / (avg_ms * 1e-3) / 1e9}
     dom = max(kernels, key=lambda k: kernels[k]["avg_us"] * kernels[k]["launches"])
     d = kernels[dom]
-    traffic = measured_traffic(dom, workload)
+    # counter measurements of the whole-step kernel are kept per region shape
+    shape_key = dom if dom != "rk4_step" or tune is None else f"rk4_step_{tune['tile_wx']}x{tune['tile_rows']}"
+    traffic = measured_traffic(shape_key, workload)
     roofline = {"bound": "hbm", "achieved": round(d["GBps"], 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                 "frac": round(d["GBps"] / HBM_PEAK_GBPS, 4), "traffic": traffic,
-                "kernel": dom, "bytes_per_launch": d["bytes_per_launch"],
+                "kernel": shape_key, "bytes_per_launch": d["bytes_per_launch"],
                 "avg_launch_us": round(d["avg_us"], 2)}
     family_name = "whole-step (1 launch per step)" if dom == "rk4_step" else "stage-fused (4 launches per step)"
     step_bytes = step_model["step"] if dom == "rk4_step" else stage_model["step"]

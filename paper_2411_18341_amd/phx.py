@@ -469,6 +469,15 @@ class Batch:
         nx, ny = self.grids[k]
         return t[self.offsets[k]:self.offsets[k] + nx * ny].view(ny, nx)
 
+    def stacked(self, t):
+        """All instances as one grid of count*ny rows (instances of one size whose
+        slices are contiguous, i.e. nx*ny a multiple of 64); for pointwise and
+        block-local kernels."""
+        nx, ny = self.grids[0]
+        if any(g != (nx, ny) for g in self.grids) or (nx * ny) % 64:
+            raise ValueError("stacked view needs equal grids with nx*ny a multiple of 64")
+        return t[:len(self.grids) * nx * ny].view(len(self.grids) * ny, nx)
+
     def step(self, n_steps: int, stream=None):
         s = stream if stream is not None else self.torch.cuda.current_stream(self.psi.device)
         phx_batch_step(self.desc, n_steps, s.cuda_stream)

@@ -8,6 +8,9 @@ for a plain device copy of known size that ran in the same process.
 
     python -m paper_2411_18341_amd.profiling stats <kernel_stats.csv> <command...>
     python -m paper_2411_18341_amd.profiling traffic <fetch.csv> <write.csv> <copy_bytes> <out.json> <workload>
+
+(`traffic` adds its kernels to <out.json> when that file holds a measurement of the
+same kernel sources and workload, else replaces it.)
 """
 from __future__ import annotations
 
@@ -39,10 +42,14 @@ def kernel_source_hash() -> str:
 
 def kernel_kind(name: str) -> str:
     """Kernel kind as the solver's timing API names it (rk4_stage2, dp_stage7, ...),
-    or a shortened name for other kernels."""
+    the whole-step kernel with its region shape (rk4_step_8x6: 8 waves x 6 rows), or
+    a shortened name for other kernels."""
     m = re.search(r"(rk4_stage_kernel|dp_stage_kernel)<[^>]*?(\d+)>", name)
     if m:
         return ("rk4_stage" if m.group(1).startswith("rk4") else "dp_stage") + m.group(2)
+    m = re.search(r"rk4_step_kernel<[^>]*?(\d+), (\d+)>", name)
+    if m:
+        return f"rk4_step_{m.group(1)}x{m.group(2)}"
     named = {"rk4_step_kernel": "rk4_step", "batch_step_kernel": "batch_step", "dp_restart_kernel": "dp_restart",
              "dp_err_sum_kernel": "dp_error", "obs_pass1": "obs_pass1", "obs_pass2": "obs_pass2",
              "conv_fwd_kernel": "conv_fwd", "conv_bwd_weight_kernel": "conv_bwd_weight"}
@@ -120,7 +127,14 @@ def main(argv):
     if argv[0] == "stats":
         sys.stdout.write(stats_summary(argv[1], " ".join(argv[2:])))
     elif argv[0] == "traffic":
+        # merges into an existing file taken on the same sources and workload
         t = traffic_summary(argv[1], argv[2], float(argv[3]), argv[5])
+        if os.path.exists(argv[4]):
+            with open(argv[4]) as f:
+                old = json.load(f)
+            if old.get("source_hash") == t["source_hash"] and old.get("workload") == t["workload"]:
+                old["kernels"].update(t["kernels"])
+                t["kernels"] = old["kernels"]
         with open(argv[4], "w") as f:
             json.dump(t, f, indent=1)
         print(json.dumps(t, indent=1))

@@ -72,15 +72,22 @@ class Pipeline:
     def coarse_batch(self, count, cfg=None):
         return phx.Batch([(self.nc, self.nc)] * count, [cfg or self.cfg_c], precision=phx.PHX_C64, device=self.dev)
 
-    def coarsen_into(self, fine, coarse, k_f, k_c=None):
-        k_c = k_f if k_c is None else k_c
-        phx.phx_coarsen(phx.PHX_C64, fine.view(fine.psi, k_f), fine.view(fine.n, k_f), fine.view(fine.P, k_f),
-                        self.nf, self.nf, self.f, coarse.view(coarse.psi, k_c), coarse.view(coarse.n, k_c),
-                        coarse.view(coarse.P, k_c))
+    # Whole batches go through one launch each: equal instances are contiguous in the
+    # packed buffers, so they form one grid of count*n rows for the pointwise kernels
+    # and the 4x4 block mean (a block never straddles two instances).
+    def coarsen_all(self, fine, coarse, factor=None, n_src=None):
+        f = self.f if factor is None else factor
+        nsrc = self.nf if n_src is None else n_src
+        count = len(fine.grids)
+        phx.phx_coarsen(phx.PHX_C64, fine.stacked(fine.psi), fine.stacked(fine.n), fine.stacked(fine.P),
+                        nsrc, nsrc * count, f, coarse.stacked(coarse.psi), coarse.stacked(coarse.n),
+                        coarse.stacked(coarse.P))
 
-    def features(self, coarse, k, out):
-        phx.phx_corrector_features(phx.PHX_C64, coarse.view(coarse.psi, k), coarse.view(coarse.n, k),
-                                   coarse.view(coarse.P, k), self.nc, self.nc, math.sqrt(RHO_S), N_S, self.pth, out)
+    def features_all(self, coarse, out):
+        count = len(coarse.grids)
+        phx.phx_corrector_features(phx.PHX_C64, coarse.stacked(coarse.psi), coarse.stacked(coarse.n),
+                                   coarse.stacked(coarse.P), self.nc, self.nc * count, math.sqrt(RHO_S), N_S,
+                                   self.pth, out)
 
     # -------------------------------------------------------------- data
     def generate(self, seeds, snapshots=20, every=250, log=print):
@@ -96,16 +103,14 @@ class Pipeline:
         t0 = time.time()
         for s in range(snapshots):
             fine.step(every - self.f)
-            for k in range(n):
-                self.coarsen_into(fine, coarse, k)
-                self.features(coarse, k, X[s * n + k])
+            self.coarsen_all(fine, coarse)
+            self.features_all(coarse, X[s * n:(s + 1) * n])
             coarse.step(1)
             fine.step(self.f)
-            for k in range(n):
-                self.coarsen_into(fine, ref, k)
-                phx.phx_corrector_residual(phx.PHX_C64, ref.view(ref.psi, k), ref.view(ref.n, k),
-                                           coarse.view(coarse.psi, k), coarse.view(coarse.n, k), self.nc, self.nc,
-                                           math.sqrt(RHO_S), N_S, R[s * n + k])
+            self.coarsen_all(fine, ref)
+            phx.phx_corrector_residual(phx.PHX_C64, ref.stacked(ref.psi), ref.stacked(ref.n),
+                                       coarse.stacked(coarse.psi), coarse.stacked(coarse.n), self.nc,
+                                       self.nc * n, math.sqrt(RHO_S), N_S, R[s * n:(s + 1) * n])
             torch.cuda.synchronize()
             log(f"snapshot {s + 1}/{snapshots} t={(s + 1) * every * self.ph.dt:.1f} ({time.time() - t0:.1f}s)")
         return X, R
@@ -172,11 +177,9 @@ class Pipeline:
             plain = self.coarse_batch(n)
             corr = self.coarse_batch(n)
             mid = phx.Batch([(nm, nm)] * n, [cfg_m], precision=phx.PHX_C64, device=self.dev)
-            for k in range(n):
-                self.coarsen_into(fine, plain, k)
-                self.coarsen_into(fine, corr, k)
-                phx.phx_coarsen(phx.PHX_C64, fine.view(fine.psi, k), fine.view(fine.n, k), fine.view(fine.P, k),
-                                self.nf, self.nf, 2, mid.view(mid.psi, k), mid.view(mid.n, k), mid.view(mid.P, k))
+            self.coarsen_all(fine, plain)
+            self.coarsen_all(fine, corr)
+            self.coarsen_all(fine, mid, factor=2)
             torch.cuda.synchronize()
             timings = {}
 
@@ -197,23 +200,19 @@ class Pipeline:
 
             def corrected():
                 for _ in range(H // self.f):
-                    for k in range(n):
-                        self.features(corr, k, x[k])
+                    self.features_all(corr, x)
                     big.forward(x, y)
                     corr.step(1)
-                    for k in range(n):
-                        phx.phx_corrector_apply(phx.PHX_C64, corr.view(corr.psi, k), corr.view(corr.n, k), y[k],
-                                                self.nc, self.nc, math.sqrt(RHO_S) * self.r_scale[0],
-                                                N_S * self.r_scale[1])
+                    phx.phx_corrector_apply(phx.PHX_C64, corr.stacked(corr.psi), corr.stacked(corr.n), y,
+                                            self.nc, self.nc * n, math.sqrt(RHO_S) * self.r_scale[0],
+                                            N_S * self.r_scale[1])
 
             timed("corrected_256", corrected)
             big.close()
             ref = self.coarse_batch(n)
             mid_c = self.coarse_batch(n)
-            for k in range(n):
-                self.coarsen_into(fine, ref, k)
-                phx.phx_coarsen(phx.PHX_C64, mid.view(mid.psi, k), mid.view(mid.n, k), mid.view(mid.P, k), nm, nm,
-                                2, mid_c.view(mid_c.psi, k), mid_c.view(mid_c.n, k), mid_c.view(mid_c.P, k))
+            self.coarsen_all(fine, ref)
+            self.coarsen_all(mid, mid_c, factor=2, n_src=nm)
             torch.cuda.synchronize()
 
             def err(b):

@@ -285,6 +285,23 @@ def test_step_kernel_every_shape(precision, bc):
         assert e_psi <= TOL[precision] and e_n <= TOL[precision], (shape, e_psi, e_n)
 
 
+@pytest.mark.parametrize("bc", [(0, 0), (1, 1)])
+def test_step_kernel_large_grid_every_shape(bc):
+    """A 2048 x 1536 grid (thousands of regions, ragged in y for every shape, more
+    workgroups than fit on the device at once): every region shape gives oracle
+    parity on every cell."""
+    ph, psi, n, V, P = workload("driven_v", 2048, 1536, bc, seed=17)
+    q = quantize(C64, psi, n, V, P)
+    o_psi, o_n = oracle_rk4(ph, *q, 3)
+    for shape in STEP_SHAPES[C64]:
+        run = GpuRun(ph, *q, precision=C64, kernel=phx.PHX_KERNEL_STEP, tile_wx=shape[0], tile_rows=shape[1])
+        run.step(3)
+        g_psi, g_n = run.state()
+        run.close()
+        e_psi, e_n = rel_l2(g_psi, o_psi), rel_l2(g_n, o_n)
+        assert e_psi <= TOL[C64] and e_n <= TOL[C64], (shape, e_psi, e_n)
+
+
 @pytest.mark.parametrize("family", [phx.PHX_KERNEL_STAGE, phx.PHX_KERNEL_STEP])
 @pytest.mark.parametrize("precision", PREC)
 def test_autotune_keeps_state_and_parity(family, precision, tmp_path, monkeypatch):
