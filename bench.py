@@ -85,7 +85,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--n", type=int, default=4096, help="grid side (default 4096)")
     ap.add_argument("--precision", choices=["c64", "c128"], default="c64")
-    ap.add_argument("--cpu-steps", type=int, default=10, help="oracle steps for the CPU baseline")
+    ap.add_argument("--cpu-steps", type=int, default=50, help="oracle steps for the CPU baseline (about 10-30 s)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel", choices=["auto", "stage", "step"], default="auto",
                     help="RK4 kernel family (auto: whole-step kernel)")
