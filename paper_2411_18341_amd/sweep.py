@@ -12,6 +12,10 @@ Infinity Cache and launch overhead dominates the smallest; large ones stream
 from HBM.
 
     python -m paper_2411_18341_amd.sweep --sizes 128 256 512 1024 2048 4096 8192 --out sweep.md
+
+With --batch it first measures the batched workload of 256 driven instances on
+grids of 128..1024 (one persistent launch per step) against stepping the same
+instances with one solver each.
 """
 from __future__ import annotations
 
@@ -65,6 +69,55 @@ def measure(n: int, family: str, precision=phx.PHX_C64, warmup: int = 20, tune_r
     }
 
 
+def measure_batch(steps: int = 500, warmup: int = 20, count: int = 256, seed: int = 4, loop_steps: int = 50):
+    """The batched sweep workload (inputs.batch_sizes / batch_pumps / batch_instance:
+    `count` driven instances on square grids drawn log-uniformly in [128, 1024],
+    complex64) stepped by one persistent launch per step, against the same instances
+    stepped one solver at a time (each with its own whole-step launches, graph
+    chunks and default region shape)."""
+    import torch
+    sizes = inputs.batch_sizes(count, seed)
+    pumps = inputs.batch_pumps(count, seed)
+    ph0, _, _, _ = inputs.batch_instance(int(sizes[0]), 1.0, 0)
+    cfg = phx.config_from_physics(ph0, precision=phx.PHX_C64)
+    b = phx.Batch([(int(n), int(n)) for n in sizes], [cfg], [0] * count, precision=phx.PHX_C64)
+    solvers = []
+    for k, (n, p) in enumerate(zip(sizes, pumps)):
+        ph, psi, n0, P = inputs.batch_instance(int(n), float(p), 1000 + k)
+        b.view(b.psi, k).copy_(torch.from_numpy(psi[0]).to(torch.complex64))
+        b.view(b.n, k).copy_(torch.from_numpy(n0[0]).to(torch.float32))
+        b.view(b.P, k).copy_(torch.from_numpy(P[0]).to(torch.float32))
+    cells = int(sum(int(n) * int(n) for n in sizes))
+    b.step(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step(steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    # the same instances as separate solvers (copies of the batch's current states)
+    for k, n in enumerate(sizes):
+        n = int(n)
+        ph, _, _, P = inputs.batch_instance(n, float(pumps[k]), 1000 + k)
+        psi = b.view(b.psi, k).clone().view(1, n, n)
+        nn = b.view(b.n, k).clone().view(1, n, n)
+        Pd = b.view(b.P, k).clone().view(1, n, n)
+        c = phx.config_from_physics(ph, precision=phx.PHX_C64, kernel=phx.PHX_KERNEL_STEP)
+        solvers.append(phx.Solver(c, psi, nn, None, Pd))
+    for s in solvers:
+        s.step(2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in solvers:
+        s.step(loop_steps)
+    torch.cuda.synchronize()
+    wall_loop = time.perf_counter() - t0
+    for s in solvers:
+        s.close()
+    return {"instances": count, "cells": cells, "steps": steps, "UPs": cells * steps / wall,
+            "us_per_step": wall / steps * 1e6, "one_solver_per_instance_UPs": cells * loop_steps / wall_loop,
+            "one_solver_per_instance_steps": loop_steps}
+
+
 def table(rows) -> str:
     out = ["| N | family | tile | steps | µs/step | G UP/s | algorithmic GB/s | mean launch µs per kernel |",
            "|---|---|---|---|---|---|---|---|"]
@@ -80,7 +133,14 @@ def main():
     ap.add_argument("--sizes", type=int, nargs="+", default=[128, 256, 512, 1024, 2048, 4096, 8192])
     ap.add_argument("--families", nargs="+", default=["stage", "step"], choices=["stage", "step"])
     ap.add_argument("--out", default=None, help="write the markdown table here")
+    ap.add_argument("--batch", action="store_true", help="also measure the 256-instance batched workload")
     args = ap.parse_args()
+    if args.batch:
+        r = measure_batch()
+        print(json.dumps({"batch": r}), flush=True)
+        if args.out:
+            with open(args.out + ".batch.json", "w") as f:
+                json.dump(r, f, indent=1)
     rows = []
     for n in args.sizes:
         for fam in args.families:
