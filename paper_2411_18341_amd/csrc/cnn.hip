@@ -4,14 +4,16 @@
 // coarsening of a fine state, input features, training residuals, and adding the
 // predicted correction to a coarse state).
 //
-// Convolutions are implicit GEMMs on v_mfma_f32_16x16x32_bf16:
-//   forward        M = 16 pixels of one row, N = output channels, K = 9 taps x C_in
+// Convolutions are implicit GEMMs on v_mfma_f32_16x16x32_bf16, in persistent
+// workgroups that walk tiles of a few rows x 64 (or 32) pixels staged in LDS:
+//   forward        M = 16 output channels, N = 16 pixels of one row, K = 9 taps x C_in;
+//                  the weights stay in LDS for all tiles of a workgroup
 //   backward-data  the forward kernel on dY with the weights flipped in the taps and
 //                  transposed in the channels, times the ReLU mask of the layer input
-//   backward-weight M = output channels, N = 9 taps x C_in, K = pixels: each
-//                  workgroup stages 32-pixel chunks of dY and of the three shifted
-//                  copies of X in LDS and accumulates; per-workgroup partials are
-//                  summed in a fixed order.
+//   backward-weight M = output channels, N = 9 taps x C_in, K = pixels: dY^T and three
+//                  x-shifted copies of X^T per tile in LDS; each workgroup accumulates
+//                  over its tiles and writes one set of partial sums, summed in a
+//                  fixed order.
 // Activations are NHWC bf16 with channels padded to a multiple of 8 (input) or 16
 // (output); weights are [c_out][K] with k = tap * C_in + c_in, tap = (dy+1)*3 + (dx+1),
 // K padded with zeros to a multiple of 32.
@@ -58,67 +60,112 @@ static LayerDims layer_dims(int cin, int cout)
 
 enum ConvMode { CONV_RELU_BF16 = 0, CONV_LINEAR_F32 = 1, CONV_MASK_BF16 = 2 };
 
-// One wave computes 16 consecutive pixels of a row times all COUTP output
-// channels.  in: [P][CINP] bf16, w: [COUTP][KP] bf16, bias: [COUTP] f32.
+// Tiled forward convolution, persistent over tiles.  A workgroup of 4 waves keeps the
+// bf16 weights in LDS for all its tiles; a tile is 4 rows x TW = 16*MT pixels of one
+// image, staged in LDS with a one-pixel circular halo.  Wave w computes row w of the
+// tile as MT x NT MFMA blocks with the weights as operand A (16 output channels x 32
+// k) and the input as operand B (32 k x 16 pixels), so each lane's accumulator holds
+// 4 consecutive output channels of one pixel and stores them with one write.
+// in: [P][CINP] bf16, w: [COUTP][KP] bf16 (zero beyond 9*CINP), bias: [COUTP] f32.
 // MODE: CONV_RELU_BF16 -> out_bf16[P][COUTP] = relu(acc + bias)
 //       CONV_LINEAR_F32 -> out_f32[P][out_stride], channels < out_stride, acc + bias
 //       CONV_MASK_BF16 -> out_bf16[P][COUTP] = acc if mask[P][COUTP] > 0 else 0
-template <int CINP, int COUTP, int MODE>
+// Requires W % TW == 0.
+template <int CINP, int COUTP, int MODE, int MT>
 __global__ __launch_bounds__(256) void conv_fwd_kernel(const u16* __restrict__ in, const u16* __restrict__ w,
-                                                       const float* __restrict__ bias, int H, int W, int P,
+                                                       const float* __restrict__ bias, int H, int W, int images,
                                                        u16* __restrict__ out_bf16, float* __restrict__ out_f32,
                                                        int out_stride, const u16* __restrict__ mask)
 {
     constexpr int KP = (9 * CINP + 31) / 32 * 32;
     constexpr int NT = COUTP / 16;
-    const int lane = threadIdx.x & 63;
-    const int wv = blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int p0 = wv * 16;
-    if (p0 >= P) return;  // whole wave leaves together (P is a multiple of 16)
+    constexpr int TW = 16 * MT, TR = 4;
+    constexpr int CS = CINP + 8;  // LDS elements per staged pixel (padded against bank conflicts)
+    constexpr int WS = KP + 8;    // LDS elements per weight row
+    constexpr int C8 = CINP / 8;  // 16-byte chunks per pixel
+    __shared__ __attribute__((aligned(16))) u16 sw[COUTP * WS];
+    __shared__ __attribute__((aligned(16))) u16 sx[(TR + 2) * (TW + 2) * CS];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int m = lane & 15, g = lane >> 4;
-    const int p = p0 + m;  // pixel of this lane's A row
-    const int img = p / (H * W);
-    const int rem = p - img * H * W;
-    const int y = rem / W, x = rem - (rem / W) * W;
-    f32x4 acc[NT];
-#pragma unroll
-    for (int t = 0; t < NT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int c = 0; c < KP / 32; ++c) {
-        const int k0 = 32 * c + 8 * g;
-        const int tap = k0 / CINP, ci = k0 - (k0 / CINP) * CINP;
-        bf16x8 a;
-        if (tap < 9) {
-            const int dy = tap / 3 - 1, dx = tap - (tap / 3) * 3 - 1;
-            int yy = y + dy, xx = x + dx;
-            yy += (yy < 0) ? H : (yy >= H ? -H : 0);
-            xx += (xx < 0) ? W : (xx >= W ? -W : 0);
-            a = *(const bf16x8*)(in + ((size_t)(img * H + yy) * W + xx) * CINP + ci);
-        } else {
-            a = bf16x8{0, 0, 0, 0, 0, 0, 0, 0};
-        }
-#pragma unroll
-        for (int t = 0; t < NT; ++t) {
-            const bf16x8 b = *(const bf16x8*)(w + (size_t)(t * 16 + m) * KP + k0);
-            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[t], 0, 0, 0);
-        }
+    for (int e = threadIdx.x; e < COUTP * (KP / 8); e += 256) {
+        const int o = e / (KP / 8), k8 = e - o * (KP / 8);
+        *(uint4*)&sw[o * WS + 8 * k8] = *(const uint4*)&w[(size_t)o * KP + 8 * k8];
     }
-    // lane holds C[4g + i][m]: pixel p0 + 4g + i, channel t*16 + m
+    const int tx_n = W / TW, ty_n = (H + TR - 1) / TR;
+    const int tiles = images * ty_n * tx_n;
+    for (int v = blockIdx.x; v < tiles; v += gridDim.x) {
+        // XCD-aware order: each XCD walks a contiguous band of tiles, so the halo rows
+        // shared by vertically adjacent tiles are read through one L2
+        const int t = xcd_tile(v, tiles);
+        const int img = t / (ty_n * tx_n);
+        const int rt = t - img * (ty_n * tx_n);
+        const int y0 = (rt / tx_n) * TR, x0 = (rt - (rt / tx_n) * tx_n) * TW;
+        __syncthreads();  // the previous tile's reads of sx are done
+        for (int e = threadIdx.x; e < (TR + 2) * (TW + 2) * C8; e += 256) {
+            const int c8 = e % C8, pix = e / C8;
+            const int r = pix / (TW + 2), c = pix - (pix / (TW + 2)) * (TW + 2);
+            int yy = y0 - 1 + r, xx = x0 - 1 + c;
+            if (yy < 0) yy += H;
+            if (yy >= H) yy %= H;
+            xx += (xx < 0) ? W : (xx >= W ? -W : 0);
+            *(uint4*)&sx[(r * (TW + 2) + c) * CS + 8 * c8] =
+                *(const uint4*)&in[((size_t)(img * H + yy) * W + xx) * CINP + 8 * c8];
+        }
+        __syncthreads();
+        f32x4 acc[MT][NT];
 #pragma unroll
-    for (int t = 0; t < NT; ++t) {
-        const int co = t * 16 + m;
+        for (int i = 0; i < MT; ++i)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int q = p0 + 4 * g + i;
-            float v = acc[t][i];
-            if (MODE == CONV_RELU_BF16) {
-                v += bias[co];
-                out_bf16[(size_t)q * COUTP + co] = bf16_bits(v > 0.f ? v : 0.f);
-            } else if (MODE == CONV_LINEAR_F32) {
-                if (co < out_stride) out_f32[(size_t)q * out_stride + co] = v + bias[co];
-            } else {
-                const float mk = bf16_value(mask[(size_t)q * COUTP + co]);
-                out_bf16[(size_t)q * COUTP + co] = bf16_bits(mk > 0.f ? v : 0.f);
+            for (int j = 0; j < NT; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int c = 0; c < KP / 32; ++c) {
+            const int k0 = 32 * c + 8 * g;
+            const int tap = k0 / CINP, ci = k0 - (k0 / CINP) * CINP;
+            bf16x8 a[NT];
+#pragma unroll
+            for (int j = 0; j < NT; ++j) a[j] = *(const bf16x8*)&sw[(j * 16 + m) * WS + k0];
+            const int dy = tap / 3, dx = tap - (tap / 3) * 3;  // offsets into the halo tile
+#pragma unroll
+            for (int i = 0; i < MT; ++i) {
+                bf16x8 b = bf16x8{0, 0, 0, 0, 0, 0, 0, 0};
+                if (tap < 9) b = *(const bf16x8*)&sx[((wave + dy) * (TW + 2) + i * 16 + m + dx) * CS + ci];
+#pragma unroll
+                for (int j = 0; j < NT; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[j], b, acc[i][j], 0, 0, 0);
+            }
+        }
+        // lane holds C[4g + r][m]: channel j*16 + 4g + r of pixel (y0 + wave, x0 + i*16 + m)
+        const int yrow = y0 + wave;
+        if (yrow < H) {
+#pragma unroll
+            for (int i = 0; i < MT; ++i) {
+                const size_t q = (size_t)(img * H + yrow) * W + x0 + i * 16 + m;
+#pragma unroll
+                for (int j = 0; j < NT; ++j) {
+                    const int c0 = j * 16 + 4 * g;
+                    if (MODE == CONV_RELU_BF16) {
+                        u16 o[4];
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            const float v = acc[i][j][r] + bias[c0 + r];
+                            o[r] = bf16_bits(v > 0.f ? v : 0.f);
+                        }
+                        *(uint2*)&out_bf16[q * COUTP + c0] =
+                            uint2{o[0] | ((unsigned int)o[1] << 16), o[2] | ((unsigned int)o[3] << 16)};
+                    } else if (MODE == CONV_LINEAR_F32) {
+#pragma unroll
+                        for (int r = 0; r < 4; ++r)
+                            if (c0 + r < out_stride) out_f32[q * out_stride + c0 + r] = acc[i][j][r] + bias[c0 + r];
+                    } else {
+                        const uint2 mk = *(const uint2*)&mask[q * COUTP + c0];
+                        const u16 mv[4] = {(u16)(mk.x & 0xffffu), (u16)(mk.x >> 16), (u16)(mk.y & 0xffffu),
+                                           (u16)(mk.y >> 16)};
+                        u16 o[4];
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) o[r] = bf16_bits(bf16_value(mv[r]) > 0.f ? acc[i][j][r] : 0.f);
+                        *(uint2*)&out_bf16[q * COUTP + c0] =
+                            uint2{o[0] | ((unsigned int)o[1] << 16), o[2] | ((unsigned int)o[3] << 16)};
+                    }
+                }
             }
         }
     }
@@ -126,98 +173,138 @@ __global__ __launch_bounds__(256) void conv_fwd_kernel(const u16* __restrict__ i
 
 // ----------------------------------------------------------- backward weights
 
-// dW[o][k] += sum_p dY[p][o] X[p + off(tap(k))][cin(k)], db[o] += sum_p dY[p][o] over
-// the pixel chunks of this workgroup (32 consecutive pixels of one row each);
-// writes COUTP*KP + COUTP partial sums per workgroup.
-template <int CINP, int COUTP>
+// dW[o][k] = sum_p dY[p][o] X[p + off(tap(k))][cin(k)] and db[o] = sum_p dY[p][o],
+// persistent over tiles of TR = 2 rows x TW = 16*MT pixels of one image.  Per tile the
+// workgroup stages dY^T [COUTP][TR*TW] and, for each x shift s = dx in {0, 1, 2}, X^T
+// [s][TR+2 rows][CINP][TW] with X at column x0 + c + s - 1, both written as pixel
+// pairs, so that both MFMA operands are 8 consecutive pixels per lane (K = pixels).
+// Wave w owns the N-tiles nt = w, w+4, ... of dW (16 columns of K each) for all
+// output channels and accumulates them over all tiles of the workgroup; at the end
+// the workgroup writes one set of COUTP*KP + COUTP partial sums.  Requires W % TW == 0.
+template <int CINP, int COUTP, int MT>
 __global__ __launch_bounds__(256) void conv_bwd_weight_kernel(const u16* __restrict__ x, const u16* __restrict__ dy,
-                                                              int H, int W, int P, float* __restrict__ partials)
+                                                              int H, int W, int images, float* __restrict__ partials)
 {
     constexpr int KP = (9 * CINP + 31) / 32 * 32;
-    constexpr int MT = COUTP / 16, NTILES = KP / 16;
-    constexpr int BLOCKS = MT * NTILES;                 // 16x16 output blocks
-    constexpr int PER_WAVE = (BLOCKS + 3) / 4;
-    // LDS: dY^T [COUTP][32] and X shifted by dx in {-1,0,1}: [3 dx][3 dy][CINP][32]
-    __shared__ __attribute__((aligned(16))) u16 sdy[COUTP][32];
-    __shared__ __attribute__((aligned(16))) u16 sx[3][3][CINP][32];
+    constexpr int MTN = COUTP / 16, NTILES = KP / 16, NPW = (NTILES + 3) / 4;
+    constexpr int TW = 16 * MT, TR = 2, NPX = TR * TW;
+    constexpr int XS = TW + 8, DS = NPX + 8;  // padded LDS row strides (16-byte multiples)
+    __shared__ __attribute__((aligned(16))) u16 sxt[3][TR + 2][CINP][XS];
+    __shared__ __attribute__((aligned(16))) u16 sdt[COUTP][DS];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int m = lane & 15, g = lane >> 4;
-    f32x4 acc[PER_WAVE];
+    f32x4 acc[MTN][NPW];
 #pragma unroll
-    for (int b = 0; b < PER_WAVE; ++b) acc[b] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int i = 0; i < MTN; ++i)
+#pragma unroll
+        for (int j = 0; j < NPW; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
     float dbias = 0.f;  // thread t < COUTP accumulates channel t
-    const int chunks = P / 32;
-    for (int ch = blockIdx.x; ch < chunks; ch += gridDim.x) {
-        const int p0 = ch * 32;
-        const int img = p0 / (H * W);
-        const int rem = p0 - img * H * W;
-        const int y = rem / W, x0 = rem - (rem / W) * W;
-        // stage dY^T
-        for (int e = threadIdx.x; e < 32 * COUTP; e += 256) {
-            const int px = e / COUTP, o = e - (e / COUTP) * COUTP;
-            sdy[o][px] = dy[(size_t)(p0 + px) * COUTP + o];
+    const int tx_n = W / TW, ty_n = (H + TR - 1) / TR;
+    const int tiles = images * ty_n * tx_n;
+    for (int v = blockIdx.x; v < tiles; v += gridDim.x) {
+        const int t = xcd_tile(v, tiles);  // XCD-aware order, as in the forward kernel
+        const int img = t / (ty_n * tx_n);
+        const int rt = t - img * (ty_n * tx_n);
+        const int y0 = (rt / tx_n) * TR, x0 = (rt - (rt / tx_n) * tx_n) * TW;
+        __syncthreads();  // the previous tile's reads of the staging areas are done
+        for (int e = threadIdx.x; e < 3 * (TR + 2) * (TW / 2) * (CINP / 8); e += 256) {
+            const int c8 = e % (CINP / 8);
+            int rest = e / (CINP / 8);
+            const int c2 = rest % (TW / 2);
+            rest /= TW / 2;
+            const int r = rest % (TR + 2), sh = rest / (TR + 2);
+            int yy = y0 - 1 + r;
+            if (yy < 0) yy += H;
+            if (yy >= H) yy %= H;
+            int xa = x0 + 2 * c2 + sh - 1;
+            xa += (xa < 0) ? W : (xa >= W ? -W : 0);
+            const int xb = (xa + 1 == W) ? 0 : xa + 1;
+            const size_t row = (size_t)(img * H + yy) * W;
+            const uint4 va = *(const uint4*)&x[(row + xa) * CINP + 8 * c8];
+            const uint4 vb = *(const uint4*)&x[(row + xb) * CINP + 8 * c8];
+            const unsigned int aw[4] = {va.x, va.y, va.z, va.w}, bw[4] = {vb.x, vb.y, vb.z, vb.w};
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                *(unsigned int*)&sxt[sh][r][8 * c8 + 2 * j][2 * c2] = (aw[j] & 0xffffu) | (bw[j] << 16);
+                *(unsigned int*)&sxt[sh][r][8 * c8 + 2 * j + 1][2 * c2] = (aw[j] >> 16) | (bw[j] & 0xffff0000u);
+            }
         }
-        // stage X rows y-1..y+1, columns x0-1+dx .. for the three dx shifts
-        for (int e = threadIdx.x; e < 3 * 3 * 32 * CINP; e += 256) {
-            const int ci = e % CINP;
-            const int px = (e / CINP) % 32;
-            const int r = (e / (CINP * 32)) % 3;
-            const int s = e / (CINP * 32 * 3);
-            int yy = y + r - 1, xx = x0 + px + s - 1;
-            yy += (yy < 0) ? H : (yy >= H ? -H : 0);
-            xx += (xx < 0) ? W : (xx >= W ? -W : 0);
-            sx[s][r][ci][px] = x[((size_t)(img * H + yy) * W + xx) * CINP + ci];
+        for (int e = threadIdx.x; e < (NPX / 2) * (COUTP / 8); e += 256) {
+            const int c8 = e % (COUTP / 8), q = 2 * (e / (COUTP / 8));
+            const int rr = q / TW, cc = q - (q / TW) * TW;
+            uint4 va = uint4{0u, 0u, 0u, 0u}, vb = uint4{0u, 0u, 0u, 0u};
+            if (y0 + rr < H) {  // rows past the image bottom contribute nothing
+                const size_t base = ((size_t)(img * H + y0 + rr) * W + x0 + cc) * COUTP + 8 * c8;
+                va = *(const uint4*)&dy[base];
+                vb = *(const uint4*)&dy[base + COUTP];
+            }
+            const unsigned int aw[4] = {va.x, va.y, va.z, va.w}, bw[4] = {vb.x, vb.y, vb.z, vb.w};
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                *(unsigned int*)&sdt[8 * c8 + 2 * j][q] = (aw[j] & 0xffffu) | (bw[j] << 16);
+                *(unsigned int*)&sdt[8 * c8 + 2 * j + 1][q] = (aw[j] >> 16) | (bw[j] & 0xffff0000u);
+            }
         }
         __syncthreads();
         if (threadIdx.x < COUTP) {
             float sacc = 0.f;
-            for (int px = 0; px < 32; ++px) sacc += bf16_value(sdy[threadIdx.x][px]);
+            for (int q = 0; q < NPX; q += 8) {
+                const uint4 v = *(const uint4*)&sdt[threadIdx.x][q];
+                const unsigned int vw[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                for (int j = 0; j < 4; ++j) sacc += bf16_value((u16)(vw[j] & 0xffffu)) + bf16_value((u16)(vw[j] >> 16));
+            }
             dbias += sacc;
         }
 #pragma unroll
-        for (int b = 0; b < PER_WAVE; ++b) {
-            const int blk = wave + 4 * b;
-            if (blk < BLOCKS) {
-                const int mt = blk / NTILES, nt = blk - (blk / NTILES) * NTILES;
-                // A[m][kr] = dY[p0 + kr][mt*16 + m], kr = 8g + j
-                const bf16x8 a = *(const bf16x8*)&sdy[mt * 16 + m][8 * g];
-                // B[kr][n] = X[p0 + kr + off(tap)][cin], column n -> k = nt*16 + m
-                const int k = nt * 16 + m;
-                const int tap = k / CINP, ci = k - (k / CINP) * CINP;
-                bf16x8 bv;
-                if (tap < 9) {
-                    const int r = tap / 3, s = tap - (tap / 3) * 3;
-                    bv = *(const bf16x8*)&sx[s][r][ci][8 * g];
-                } else {
-                    bv = bf16x8{0, 0, 0, 0, 0, 0, 0, 0};
+        for (int kc = 0; kc < NPX / 32; ++kc) {
+            const int rr = (kc * 32) / TW, cb = (kc * 32) % TW;
+            bf16x8 a[MTN];
+#pragma unroll
+            for (int i = 0; i < MTN; ++i) a[i] = *(const bf16x8*)&sdt[i * 16 + m][kc * 32 + 8 * g];
+#pragma unroll
+            for (int j = 0; j < NPW; ++j) {
+                const int nt = wave + 4 * j;
+                if (nt < NTILES) {
+                    const int k = nt * 16 + m;
+                    const int tap = k / CINP, ci = k - (k / CINP) * CINP;
+                    bf16x8 b = bf16x8{0, 0, 0, 0, 0, 0, 0, 0};
+                    if (tap < 9) b = *(const bf16x8*)&sxt[tap % 3][rr + tap / 3][ci][cb + 8 * g];
+#pragma unroll
+                    for (int i = 0; i < MTN; ++i) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b, acc[i][j], 0, 0, 0);
                 }
-                acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bv, acc[b], 0, 0, 0);
             }
         }
-        __syncthreads();
     }
+    // lane holds C[4g + r][m]: dW[i*16 + 4g + r][nt*16 + m]
     float* part = partials + (size_t)blockIdx.x * (COUTP * KP + COUTP);
 #pragma unroll
-    for (int b = 0; b < PER_WAVE; ++b) {
-        const int blk = wave + 4 * b;
-        if (blk < BLOCKS) {
-            const int mt = blk / NTILES, nt = blk - (blk / NTILES) * NTILES;
+    for (int j = 0; j < NPW; ++j) {
+        const int nt = wave + 4 * j;
+        if (nt < NTILES) {
 #pragma unroll
-            for (int i = 0; i < 4; ++i) part[(size_t)(mt * 16 + 4 * g + i) * KP + nt * 16 + m] = acc[b][i];
+            for (int i = 0; i < MTN; ++i)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) part[(size_t)(i * 16 + 4 * g + r) * KP + nt * 16 + m] = acc[i][j][r];
         }
     }
     if (threadIdx.x < COUTP) part[COUTP * KP + threadIdx.x] = dbias;
 }
 
-// grads[e] = sum over workgroups of partials[wg][e] (fixed order)
-__global__ __launch_bounds__(256) void sum_partials_kernel(const float* __restrict__ partials, int n, int groups,
-                                                          float* __restrict__ out)
+// grads[e] = sum over workgroups of partials[wg][e]: eight interleaved running sums
+// (groups g = 8i + r go to sum r), combined in a fixed order.
+__global__ __launch_bounds__(64) void sum_partials_kernel(const float* __restrict__ partials, int n, int groups,
+                                                         float* __restrict__ out)
 {
-    const int e = blockIdx.x * 256 + threadIdx.x;
+    const int e = blockIdx.x * 64 + threadIdx.x;
     if (e >= n) return;
-    float s = 0.f;
-    for (int gidx = 0; gidx < groups; ++gidx) s += partials[(size_t)gidx * n + e];
-    out[e] = s;
+    float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    int gidx = 0;
+    for (; gidx + 8 <= groups; gidx += 8)
+#pragma unroll
+        for (int r = 0; r < 8; ++r) s[r] += partials[(size_t)(gidx + r) * n + e];
+    for (int r = 0; gidx + r < groups; ++r) s[r] += partials[(size_t)(gidx + r) * n + e];
+    out[e] = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
 }
 
 // ------------------------------------------------------------ small kernels
@@ -252,23 +339,36 @@ __global__ __launch_bounds__(256) void pack_input_kernel(const float* __restrict
     out[e] = c < cin ? bf16_bits(x[(size_t)p * cin + c]) : (u16)0;
 }
 
-// loss partial sums and dL/dy = 2 (y - t) / (P cout) in bf16 [P][coutp]
+// loss partial sums (one per workgroup; each thread takes pixels p, p + G, ... with G
+// the grid's thread count, a fixed order for a given P) and dL/dy = scale (y - t) in
+// bf16 [P][coutp], padded channels 0 (coutp is a multiple of 8)
 __global__ __launch_bounds__(256) void mse_grad_kernel(const float* __restrict__ y, const float* __restrict__ t,
                                                        int cout, int coutp, int P, float scale,
                                                        u16* __restrict__ dy, double* __restrict__ loss_part)
 {
     __shared__ double red[4];
-    const int e = blockIdx.x * 256 + threadIdx.x;
     double l = 0.0;
-    if (e < P * coutp) {
-        const int p = e / coutp, c = e - (e / coutp) * coutp;
-        float gval = 0.f;
-        if (c < cout) {
-            const float d = y[(size_t)p * cout + c] - t[(size_t)p * cout + c];
-            l = (double)d * d;
-            gval = scale * d;
+    for (int p = blockIdx.x * 256 + threadIdx.x; p < P; p += gridDim.x * 256) {
+        for (int c8 = 0; c8 < coutp; c8 += 8) {
+            unsigned int wv[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                u16 h[2];
+#pragma unroll
+                for (int b = 0; b < 2; ++b) {
+                    const int c = c8 + 2 * j + b;
+                    float gval = 0.f;
+                    if (c < cout) {
+                        const float d = y[(size_t)p * cout + c] - t[(size_t)p * cout + c];
+                        l += (double)d * d;
+                        gval = scale * d;
+                    }
+                    h[b] = bf16_bits(gval);
+                }
+                wv[j] = h[0] | ((unsigned int)h[1] << 16);
+            }
+            *(uint4*)&dy[(size_t)p * coutp + c8] = uint4{wv[0], wv[1], wv[2], wv[3]};
         }
-        dy[e] = bf16_bits(gval);
     }
 #pragma unroll
     for (int s = 32; s >= 1; s >>= 1) l += __shfl_xor(l, s, 64);
@@ -501,12 +601,33 @@ phx_status phx_cnn_create(const phx_cnn_config* cfg, const phx_cnn_buffers* buf,
 
 void phx_cnn_destroy(phx_cnn* h) { delete h; }
 
+// Workgroups of `kernel` resident on the current device (occupancy per CU, cached in
+// `per_cu` by the caller, times the CU count); 0 if the runtime cannot tell.
+template <typename K>
+static int resident_groups(K kernel, int threads, int& per_cu)
+{
+    int dev = 0, cus = 0;
+    if (per_cu <= 0 && hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess)
+        per_cu = 0;
+    if (per_cu <= 0 || hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return 0;
+    return per_cu * cus;
+}
+
+// Tiles of 64 pixels when the width allows, else 32 (the width is a multiple of 32).
 template <int CINP, int COUTP, int MODE>
 static hipError_t launch_conv(const u16* in, const u16* w, const float* bias, int H, int W, int P, u16* ob,
                               float* of, int ostride, const u16* mask, hipStream_t s)
 {
-    const int waves = P / 16;
-    conv_fwd_kernel<CINP, COUTP, MODE><<<(waves + 3) / 4, 256, 0, s>>>(in, w, bias, H, W, P, ob, of, ostride, mask);
+    static int per_cu[2] = {0, 0};
+    const int images = P / (H * W);
+    const int mt4 = (W % 64 == 0) ? 1 : 0;
+    const int tiles = images * ((H + 3) / 4) * (W / (mt4 ? 64 : 32));
+    auto k = mt4 ? conv_fwd_kernel<CINP, COUTP, MODE, 4> : conv_fwd_kernel<CINP, COUTP, MODE, 2>;
+    const int res = resident_groups(k, 256, per_cu[mt4]);
+    const int grid = (res > 0 && res < tiles) ? res : tiles;
+    k<<<grid, 256, 0, s>>>(in, w, bias, H, W, images, ob, of, ostride, mask);
     return hipGetLastError();
 }
 
@@ -575,18 +696,25 @@ phx_status phx_cnn_forward(phx_cnn* h, const float* x, int32_t batch, float* y)
     return cnn_forward_impl(h, x, batch, y);
 }
 
+// At most `groups` workgroups (the size of the partials buffer), no more than fit.
 template <int CINP, int COUTP>
 static hipError_t launch_bwd_weight(const u16* x, const u16* dy, int H, int W, int P, float* partials, int groups,
                                     float* grads, hipStream_t s)
 {
-    const int chunks = P / 32;
-    const int g = chunks < groups ? chunks : groups;
-    conv_bwd_weight_kernel<CINP, COUTP><<<g, 256, 0, s>>>(x, dy, H, W, P, partials);
+    static int per_cu[2] = {0, 0};
+    const int images = P / (H * W);
+    const int mt4 = (W % 64 == 0) ? 1 : 0;
+    const int tiles = images * ((H + 1) / 2) * (W / (mt4 ? 64 : 32));
+    auto k = mt4 ? conv_bwd_weight_kernel<CINP, COUTP, 4> : conv_bwd_weight_kernel<CINP, COUTP, 2>;
+    int g = resident_groups(k, 256, per_cu[mt4]);
+    if (g <= 0 || g > groups) g = groups;
+    if (g > tiles) g = tiles;
+    k<<<g, 256, 0, s>>>(x, dy, H, W, images, partials);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     constexpr int KP = (9 * CINP + 31) / 32 * 32;
     const int n = COUTP * KP + COUTP;
-    sum_partials_kernel<<<(n + 255) / 256, 256, 0, s>>>(partials, n, g, grads);
+    sum_partials_kernel<<<(n + 63) / 64, 64, 0, s>>>(partials, n, g, grads);
     return hipGetLastError();
 }
 
@@ -606,7 +734,7 @@ phx_status phx_cnn_gradients(phx_cnn* h, const float* x, const float* target, in
     CNN_HIP(cnn_pack(h, true));
     // loss and dL/dy
     const int cout = h->cfg.out_channels, coutp = h->dims[NLAYERS - 1].coutp;
-    const int nl = P * coutp, lblocks = (nl + 255) / 256;
+    const int lblocks = (P + 255) / 256 < 1024 ? (P + 255) / 256 : 1024;
     mse_grad_kernel<<<lblocks, 256, 0, s>>>((const float*)(ws + h->out_f32), target, cout, coutp, P,
                                             2.0f / ((float)P * cout), (u16*)(ws + h->dy_last),
                                             (double*)(ws + h->loss_part));
