@@ -48,3 +48,21 @@ def rk4_whole_step(real_bytes: int, reservoir: bool, has_v: bool, components: in
     4-cell halo of each region again is redundant traffic, not counted here."""
     b = state_minimum(real_bytes, reservoir, has_v, components)
     return {"step": b}
+
+
+def dopri5_attempt(real_bytes: int, reservoir: bool, has_v: bool, components: int = 1) -> dict:
+    """Bytes per point of one attempted Dormand-Prince step as the stage kernels
+    move them (first same as last: K1 comes from the previous step).  A restart pass
+    forms y2 = psi + dt a21 K1 (reads psi, K1; writes y2); stage s = 2..6 reads y_s,
+    psi, K_1..K_{s-1} (and P, V) and writes K_s and y_{s+1}; stage 7 reads y_7, psi
+    and the K_j with b_j != bhat_j (all but K_2) and writes K_7.  Every complex pass
+    has a reservoir counterpart when the reservoir is on."""
+    c = 2 * real_bytes * components + (real_bytes * components if reservoir else 0)
+    p = real_bytes * components if reservoir else 0
+    v = real_bytes if has_v else 0
+    restart = 3 * c
+    stages = {s: (s + 1) * c + p + v + 2 * c for s in range(2, 7)}
+    stages[7] = 7 * c + p + v + c
+    out = {"restart": restart, **{f"stage{s}": b for s, b in stages.items()}}
+    out["attempt"] = restart + sum(stages.values())
+    return out

@@ -61,6 +61,10 @@ __device__ __forceinline__ double lane_next(double v)
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+// native two-element vector of R (the store builtins take these, not the HIP structs)
+template <typename R>
+using rvec2 = R __attribute__((ext_vector_type(2)));
+
 // index of grid coordinate g under the boundary rule; -1 for a ghost (zero boundary)
 __device__ __forceinline__ int wrap_any(int g, int n, int bc)
 {
@@ -247,10 +251,11 @@ __device__ __forceinline__ bool run_region(const StepArgs<R>& a, int tile, const
             const int gj = row0 + k;
             if (r >= 4 && r < 4 + OH && gj < a.ny) {
                 const int idx = gj * a.nx + gi;
-                a.psi_out[idx] = y[k];
+                // non-temporal: the new state is not read again within this step
+                __builtin_nontemporal_store(rvec2<R>{y[k].x, y[k].y}, (rvec2<R>*)&a.psi_out[idx]);
                 bad = bad || !(isfinite(y[k].x) && isfinite(y[k].y));
                 if (RES) {
-                    a.n_out[idx] = yn[k];
+                    __builtin_nontemporal_store(yn[k], &a.n_out[idx]);
                     bad = bad || !isfinite(yn[k]);
                 }
             }

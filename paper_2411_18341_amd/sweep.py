@@ -15,7 +15,8 @@ from HBM.
 
 With --batch it first measures the batched workload of 256 driven instances on
 grids of 128..1024 (one persistent launch per step) against stepping the same
-instances with one solver each.
+instances with one solver each; with --spinor the 4096^2 two-component workload
+with RK4 and with Dormand-Prince.
 """
 from __future__ import annotations
 
@@ -118,6 +119,63 @@ def measure_batch(steps: int = 500, warmup: int = 20, count: int = 256, seed: in
             "one_solver_per_instance_steps": loop_steps}
 
 
+def measure_spinor(n: int = 4096, accepted: int = 20, rk4_steps: int = 50):
+    """The spinor workload (inputs.spinor: two components, TE-TM coupling, cross
+    interaction, disorder potential, zero boundaries, complex64) on an n x n grid:
+    RK4 with the stage-fused kernels (the two-component family), and Dormand-Prince
+    with rtol = atol = 1e-6 from dt 1e-3 for `accepted` accepted steps.  Reports point
+    updates per second (accepted steps for RK45), attempts, and per-kernel launch
+    times with their algorithmic bandwidth."""
+    import torch
+    ph, psi0, V = inputs.spinor(n)
+    dev = torch.device("cuda:0")
+    out = {"n": n}
+    for integ in ("rk4", "rk45"):
+        psi = torch.from_numpy(psi0).to(dtype=torch.complex64, device=dev).contiguous()
+        Vd = torch.from_numpy(V).to(dtype=torch.float32, device=dev).contiguous()
+        kw = dict(precision=phx.PHX_C64)
+        if integ == "rk45":
+            kw.update(integrator=phx.PHX_RK45, rtol=1e-6, atol=1e-6, dt=1e-3)
+        cfg = phx.config_from_physics(ph, **kw)
+        solver = phx.Solver(cfg, psi, None, Vd, None)
+        try:
+            if integ == "rk4":
+                solver.autotune(reps=3, use_cache=False)
+            solver.step(2)
+            torch.cuda.synchronize()
+            info0 = solver.info()
+            solver.set_timing(True)
+            count = rk4_steps if integ == "rk4" else accepted
+            t0 = time.perf_counter()
+            solver.step(count)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            info1 = solver.info()
+            times = solver.kernel_times()
+        finally:
+            solver.close()
+        if integ == "rk4":
+            model = bytemodel.rk4_stage_fused(4, reservoir=False, has_v=True, components=2)
+            names = {f"rk4_stage{k}": model[f"stage{k}"] for k in range(1, 5)}
+        else:
+            model = bytemodel.dopri5_attempt(4, reservoir=False, has_v=True, components=2)
+            names = {f"dp_stage{k}": model[f"stage{k}"] for k in range(2, 8)}
+        ks = {}
+        for k, v in times.items():
+            us = v["ms_total"] / v["launches"] * 1e3
+            ks[k] = {"launches": v["launches"], "avg_us": us}
+            if k in names:
+                ks[k]["algorithmic_GBps"] = names[k] * n * n / (us * 1e-6) / 1e9
+        r = {"UPs": n * n * count / wall, "wall_s": wall, "kernels": ks}
+        if integ == "rk45":
+            acc = info1["steps_accepted"] - info0["steps_accepted"]
+            rej = info1["steps_rejected"] - info0["steps_rejected"]
+            r.update({"accepted": acc, "rejected": rej, "dt_final": info1["dt"],
+                      "attempts_per_s": (acc + rej) / wall, "bytes_per_point_attempt": model["attempt"]})
+        out[integ] = r
+    return out
+
+
 def table(rows) -> str:
     out = ["| N | family | tile | steps | µs/step | G UP/s | algorithmic GB/s | mean launch µs per kernel |",
            "|---|---|---|---|---|---|---|---|"]
@@ -134,7 +192,14 @@ def main():
     ap.add_argument("--families", nargs="+", default=["stage", "step"], choices=["stage", "step"])
     ap.add_argument("--out", default=None, help="write the markdown table here")
     ap.add_argument("--batch", action="store_true", help="also measure the 256-instance batched workload")
+    ap.add_argument("--spinor", action="store_true", help="also measure the 4096^2 spinor workload (RK4, RK45)")
     args = ap.parse_args()
+    if args.spinor:
+        r = measure_spinor()
+        print(json.dumps({"spinor": r}), flush=True)
+        if args.out:
+            with open(args.out + ".spinor.json", "w") as f:
+                json.dump(r, f, indent=1)
     if args.batch:
         r = measure_batch()
         print(json.dumps({"batch": r}), flush=True)
