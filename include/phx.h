@@ -81,8 +81,10 @@ typedef struct phx_config {
     double dt_min, dt_max;  /* RK45 step bounds (0 < dt_min <= dt_max; dt_max may be inf) */
     int32_t kernel;         /* PHX_KERNEL_AUTO picks the fastest applicable kernel family */
     int32_t tile_wx;        /* 0 = automatic; stage-fused kernels: waves across x (1, 2, 4);
-                               whole-step kernel: waves per workgroup (a tuned shape)      */
-    int32_t tile_rows;      /* 0 = automatic; rows per wave (stage-fused: 1..64)         */
+                               whole-step kernel: waves per workgroup of the region form,
+                               or 1 for the streaming form (a tuned shape)                 */
+    int32_t tile_rows;      /* 0 = automatic; rows per wave (stage-fused: 1..64); streaming
+                               form: rows per band (40, 64, 88, 112; state under 2 GiB)    */
     int32_t graph_steps;    /* RK4 steps per captured hipGraph chunk replayed by phx_step:
                                0 = default (64), < 0 = launch every kernel directly        */
 } phx_config;
@@ -147,9 +149,10 @@ phx_status phx_create(const phx_config *cfg, const phx_fields *fields, void *hip
 /* Advance the bound state.  RK4: n_steps steps of Eqs. rk4_K1-rk4_final (Sec. 2),
  * enqueued asynchronously; runs of graph_steps steps are captured once into a
  * hipGraph (on a private stream of default priority) and replayed on the caller's
- * stream, the rest is launched directly (also while kernel timing is on).  RK45: attempts Dormand-Prince steps until n_steps are
- * accepted; each attempt reads its error norm back to the host, so the call
- * synchronizes the stream once per attempt.  n_steps >= 0.  *out_or_null receives
+ * stream, the rest is launched directly (also while kernel timing is on).
+ * RK45: attempts Dormand-Prince steps until n_steps are accepted; each attempt
+ * reads its error norm back to the host, so the call synchronizes the stream once
+ * per attempt.  n_steps >= 0.  *out_or_null receives
  * the progress when not NULL (for RK4 without waiting for the device).
  * PHX_ENONFINITE is returned by the first call that finds the device-side
  * non-finite flag set by an earlier step; PHX_EDTMIN when RK45 cannot meet the
@@ -199,7 +202,8 @@ phx_status phx_kernel_times(phx_handle *h, phx_timing *out);
  * unchanged.  The fastest shape is adopted for later phx_step calls and reported
  * in the phx_config encoding (stage-fused: tile_wx = waves across x, tile_rows =
  * rows per wave; whole-step: tile_wx = waves per workgroup, tile_rows = rows per
- * wave), so that a caller can cache it and pass it to phx_create next time.
+ * wave, or tile_wx = 1 and tile_rows = band rows for the streaming form), so that a
+ * caller can cache it and pass it to phx_create next time.
  * Synchronizes the stream.  PHX_EUNSUPPORTED for RK45 handles. */
 typedef struct phx_tune_result {
     int32_t family;         /* PHX_KERNEL_STAGE or PHX_KERNEL_STEP                         */

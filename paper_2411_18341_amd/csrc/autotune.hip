@@ -40,8 +40,11 @@ static phx_status tune_step(phx_handle* h, int reps, phx_tune_result* out)
     const StepShapeId before = h->step_shape;
     StepShapeId best = before;
     double best_us = INFINITY, before_us = INFINITY;
+    int timed = 0;
     for (int k = 0; k < n; ++k) {
         const StepShapeId sh = shapes[k];
+        if (!step_shape_fits(h->cfg, sh.waves)) continue;
+        ++timed;
         double us;
         phx_status s = time_launches(h, reps, [&] { return rk4_step_trial<R>(h, sh); }, &us);
         if (s != PHX_OK) return s;
@@ -53,7 +56,7 @@ static phx_status tune_step(phx_handle* h, int reps, phx_tune_result* out)
     }
     h->step_shape = best;
     h->graph_dirty = true;
-    *out = phx_tune_result{PHX_KERNEL_STEP, best.waves, best.rows, n, best_us, before_us};
+    *out = phx_tune_result{PHX_KERNEL_STEP, best.waves, best.rows, timed, best_us, before_us};
     return PHX_OK;
 }
 

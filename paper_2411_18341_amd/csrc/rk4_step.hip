@@ -18,6 +18,7 @@
 // buffer (neighbouring regions still read the input's halo).
 #include "runtime.h"
 #include "step_body.h"
+#include "stream_body.h"
 
 namespace phx {
 
@@ -29,15 +30,40 @@ __global__ __launch_bounds__(WAVES * 64) void rk4_step_kernel(const StepArgs<R> 
     if (bad) a.flag[0] = 1u;  // benign race: every writer stores 1
 }
 
+// Streaming form: a workgroup is 4 adjacent strips of one band of B rows (their
+// x-halo columns are read through one L1); a.tiles_x counts strips, a.tiles
+// workgroups.  Waves past the last strip leave at once (the kernel has no barrier).
+template <typename R, bool RES, bool HASV, bool GHOSTS, bool YZERO, int B>
+__global__ __launch_bounds__(256) void rk4_stream_kernel(const StepArgs<R> a)
+{
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int t = xcd_tile(blockIdx.x, gridDim.x);
+    const int groups_x = (a.tiles_x + 3) / 4;
+    const int band = t / groups_x, strip = (t - band * groups_x) * 4 + wave;
+    if (strip >= a.tiles_x) return;
+    if (stream_band<R, RES, HASV, GHOSTS, YZERO, B>(a, strip, band)) a.flag[0] = 1u;  // benign race
+}
+
 // GHOSTS: some boundary is zero, so region cells outside the grid must be held at 0
 // after every stage; with periodic boundaries in both directions there are none.
+// WAVES == 1 selects the streaming kernel with bands of ROWS rows.
 template <typename R, bool RES, bool HASV, int WAVES, int ROWS>
 static hipError_t launch_step_t(const StepArgs<R>& a, hipStream_t s)
 {
-    if (a.bcx == PHX_BC_ZERO || a.bcy == PHX_BC_ZERO)
-        rk4_step_kernel<R, RES, HASV, true, WAVES, ROWS><<<a.tiles, WAVES * 64, 0, s>>>(a);
-    else
-        rk4_step_kernel<R, RES, HASV, false, WAVES, ROWS><<<a.tiles, WAVES * 64, 0, s>>>(a);
+    const bool ghosts = a.bcx == PHX_BC_ZERO || a.bcy == PHX_BC_ZERO;
+    if constexpr (WAVES == 1) {
+        if (a.bcy == PHX_BC_ZERO)
+            rk4_stream_kernel<R, RES, HASV, true, true, ROWS><<<a.tiles, 256, 0, s>>>(a);
+        else if (ghosts)
+            rk4_stream_kernel<R, RES, HASV, true, false, ROWS><<<a.tiles, 256, 0, s>>>(a);
+        else
+            rk4_stream_kernel<R, RES, HASV, false, false, ROWS><<<a.tiles, 256, 0, s>>>(a);
+    } else {
+        if (ghosts)
+            rk4_step_kernel<R, RES, HASV, true, WAVES, ROWS><<<a.tiles, WAVES * 64, 0, s>>>(a);
+        else
+            rk4_step_kernel<R, RES, HASV, false, WAVES, ROWS><<<a.tiles, WAVES * 64, 0, s>>>(a);
+    }
     return hipGetLastError();
 }
 
@@ -45,8 +71,10 @@ static hipError_t launch_step_t(const StepArgs<R>& a, hipStream_t s)
 // A region of WAVES*ROWS rows yields WAVES*ROWS - 8 output rows; taller regions
 // recompute less halo, shorter ones need fewer registers per lane (more waves
 // per SIMD).  The first entry is the default; phx_autotune measures them all.
-static const StepShapeId kFloatShapes[] = {{8, 4}, {16, 4}, {8, 8}, {12, 4}, {12, 6}, {8, 6}, {4, 8}, {16, 6}};
-static const StepShapeId kDoubleShapes[] = {{8, 4}, {16, 2}, {8, 2}, {12, 4}, {4, 4}};
+// Shapes {1, B} are the streaming kernel with bands of B rows (B + 8 a multiple of 24).
+static const StepShapeId kFloatShapes[] = {{8, 4}, {16, 4}, {8, 8}, {12, 4}, {12, 6}, {8, 6}, {4, 8}, {16, 6},
+                                           {1, 40}, {1, 64}, {1, 88}, {1, 112}};
+static const StepShapeId kDoubleShapes[] = {{8, 4}, {16, 2}, {8, 2}, {12, 4}, {4, 4}, {1, 40}, {1, 64}};
 
 int step_shapes(int precision, const StepShapeId** out)
 {
@@ -66,8 +94,10 @@ static hipError_t launch_step_shape(const StepShapeId& sh, const StepArgs<R>& a,
     if constexpr (sizeof(R) == 4) {
         PHX_SHAPE(8, 4); PHX_SHAPE(16, 4); PHX_SHAPE(8, 8); PHX_SHAPE(12, 4);
         PHX_SHAPE(12, 6); PHX_SHAPE(8, 6); PHX_SHAPE(4, 8); PHX_SHAPE(16, 6);
+        PHX_SHAPE(1, 40); PHX_SHAPE(1, 64); PHX_SHAPE(1, 88); PHX_SHAPE(1, 112);
     } else {
         PHX_SHAPE(8, 4); PHX_SHAPE(16, 2); PHX_SHAPE(8, 2); PHX_SHAPE(12, 4); PHX_SHAPE(4, 4);
+        PHX_SHAPE(1, 40); PHX_SHAPE(1, 64);
     }
 #undef PHX_SHAPE
     return hipErrorInvalidValue;
@@ -93,9 +123,13 @@ static StepArgs<R> step_args(const phx_handle* h, const StepShapeId& sh, const v
     a.ny = c.ny;
     a.bcx = c.bc_x;
     a.bcy = c.bc_y;
-    const int oh = sh.waves * sh.rows - 8;
     a.tiles_x = (c.nx + 55) / 56;
-    a.tiles = a.tiles_x * ((c.ny + oh - 1) / oh);
+    if (sh.waves == 1) {  // streaming: strips of 56 columns, workgroups of 4 strips x one band
+        a.tiles = ((a.tiles_x + 3) / 4) * ((c.ny + sh.rows - 1) / sh.rows);
+    } else {
+        const int oh = sh.waves * sh.rows - 8;
+        a.tiles = a.tiles_x * ((c.ny + oh - 1) / oh);
+    }
     a.c = make_coef<R>(c);
     a.half_dt = (R)(0.5 * c.dt);
     a.dt = (R)c.dt;

@@ -111,6 +111,7 @@ template <typename R> phx_status rk4_run_graph(phx_handle* h, int64_t n);
 template <typename R> hipError_t rk4_step_trial(phx_handle* h, const StepShapeId& sh);
 template <typename R> hipError_t rk4_stage_trial(phx_handle* h, const TileShape& ts);
 int step_shapes(int precision, const StepShapeId** out);
+bool step_shape_fits(const phx_config& c, int waves);
 int rk4_family(const phx_config& c);
 phx_status step_rk45(phx_handle* h, int64_t n, phx_info* out);
 phx_status set_info_rk45(phx_handle* h, const phx_info* in);

@@ -60,6 +60,8 @@ phx_status validate_config(const phx_config* c)
         if (c->integrator == PHX_RK4 && rk4_family(*c) == PHX_KERNEL_STEP) {
             if (!valid_step_shape(c->precision, c->tile_wx, c->tile_rows))
                 return fail(PHX_EINVAL, "tile %d x %d is not a whole-step kernel shape", c->tile_wx, c->tile_rows);
+            if (!step_shape_fits(*c, c->tile_wx))
+                return fail(PHX_EINVAL, "streaming shapes (tile_wx 1) need a state array under 2 GiB");
         } else if ((c->tile_wx != 1 && c->tile_wx != 2 && c->tile_wx != 4) || c->tile_rows < 1 || c->tile_rows > 64) {
             return fail(PHX_EINVAL, "tile_wx must be 1, 2 or 4 and tile_rows 1..64");
         }
@@ -124,6 +126,14 @@ Layout make_layout(const phx_config& c)
     }
     L.total = off;
     return L;
+}
+
+// The streaming shapes (waves == 1) address their output through 32-bit buffer
+// offsets: the complex state array must stay below 2 GiB.
+bool step_shape_fits(const phx_config& c, int waves)
+{
+    const double bytes = (double)c.nx * c.ny * c.components * (c.precision == PHX_C64 ? 8.0 : 16.0);
+    return waves != 1 || bytes < 2147483648.0 - 256.0;
 }
 
 bool valid_step_shape(int precision, int waves, int rows)

@@ -1,0 +1,253 @@
+// Device code of the streaming whole-step RK4 kernel: all four stages of Eqs.
+// rk4_K1-rk4_final in one pass down a band of rows, one wave per strip of columns,
+// with no LDS and no barrier.
+//
+// Lane l of a wave owns grid column strip*56 - 4 + l (the strip's 56 output columns
+// plus a 4-column halo on each side, recomputed as in the region kernel; x-neighbours
+// come from DPP wave shifts).  The wave walks the rows j = b0-4 .. b0+B+3 of its band
+// [b0, b0+B) once; at row j it evaluates
+//   stage 1 at row j-1, stage 2 at row j-2, stage 3 at row j-3, stage 4 at row j-4
+// (each stage needs its argument at rows r-1..r+1, produced by the previous stage at
+// this or an earlier row), and stores the finished row j-4 when it lies in the band;
+// the walk ends with row b0+B+3, which finishes row b0+B-1.
+// Per-row inputs (psi, n, P, V) wait in an 8-row ring, loaded 3 rows ahead of their
+// first use; the running sums K1 + 2K2 + 2K3 in a 4-row ring; the stage arguments
+// of stages 2..4 in 3-row windows.  The row loop is unrolled by 24 (a multiple of
+// every ring length; the B + 8 rows of the walk are a multiple of 24), so every ring slot is a fixed
+// register and no value moves.  Ring slots before row b0-4 hold zeros and feed only
+// rows that are never stored.
+#pragma once
+
+#include "step_body.h"
+
+namespace phx {
+
+// ring slot of the value that belongs to loop position t - back, ring length K
+// (t and back are compile-time constants after unrolling)
+template <int K>
+__device__ __forceinline__ constexpr int slot(int t, int back)
+{
+    return ((t - back) % K + K) % K;
+}
+
+// Right-hand side of one cell from its stage argument p, the neighbour sums lr
+// (x) and ud (y), the reservoir value nn and the per-cell constant kv (see
+// step_stages for the formula).  Returns f and fn.
+template <typename R, bool RES>
+__device__ __forceinline__ void cell_rhs(const Coef<R>& c, typename cvec<R>::type p, R lrx, R lry, R udx, R udy,
+                                         R nn, R pv, R kv, R& fx, R& fy, R& fn)
+{
+    const R rho = fma(p.x, p.x, p.y * p.y);
+    R om = kv;
+    if (RES) om = fma(c.grh, nn, om);
+    om = fma(c.gh, rho, om);
+    const R u = RES ? fma(c.half_R, nn, -c.half_gamma) : -c.half_gamma;
+    const R tx = fma(c.ax, lrx, c.ay * udx);
+    const R ty = fma(c.ax, lry, c.ay * udy);
+    fx = fma(u, p.x, fma(om, p.y, -ty));
+    fy = fma(u, p.y, fma(-om, p.x, tx));
+    fn = RES ? fma(-fma(c.R_, rho, c.gamma_r), nn, pv) : R(0);
+}
+
+// Raw buffer stores (hardware range check: a store at an offset past the buffer's
+// size is dropped), so lanes and rows that must not store take an out-of-range
+// offset instead of a branch.  Offsets are in bytes; the output buffers are smaller
+// than 2 GiB (enforced when the shape is chosen).
+constexpr unsigned int kBufferWord3 = 0x00020000u;  // raw 32-bit data, gfx9 family
+constexpr int kOutOfRange = 0x7fffffff;
+constexpr int kNonTemporal = 2;  // cache-policy bit of the store
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_of(const void* p, size_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), 0, (int)bytes, (int)kBufferWord3);
+}
+
+__device__ __forceinline__ void buf_store_nt(float v, __amdgpu_buffer_rsrc_t r, int off)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, off, 0, kNonTemporal);
+}
+__device__ __forceinline__ void buf_store_nt(double v, __amdgpu_buffer_rsrc_t r, int off)
+{
+    typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, off, 0, kNonTemporal);
+}
+__device__ __forceinline__ void buf_store_nt(float2 v, __amdgpu_buffer_rsrc_t r, int off)
+{
+    typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(u2{__builtin_bit_cast(unsigned int, v.x), __builtin_bit_cast(unsigned int, v.y)},
+                                          r, off, 0, kNonTemporal);
+}
+__device__ __forceinline__ void buf_store_nt(double2 v, __amdgpu_buffer_rsrc_t r, int off)
+{
+    typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+    const unsigned long long x = __builtin_bit_cast(unsigned long long, v.x);
+    const unsigned long long y = __builtin_bit_cast(unsigned long long, v.y);
+    __builtin_amdgcn_raw_buffer_store_b128(u4{(unsigned int)x, (unsigned int)(x >> 32), (unsigned int)y,
+                                              (unsigned int)(y >> 32)},
+                                           r, off, 0, kNonTemporal);
+}
+
+// YZERO: the y boundary is zero (ghost rows); else periodic in y.
+template <typename R, bool RES, bool HASV, bool GHOSTS, bool YZERO, int B>
+__device__ __forceinline__ bool stream_band(const StepArgs<R>& a, int strip, int band)
+{
+    using C = typename cvec<R>::type;
+    static_assert((B + 8) % 24 == 0, "band rows + 8 must be a multiple of the unroll length");
+    constexpr int PF = 3;  // rows loaded ahead of their first use
+    const int lane = threadIdx.x & 63;
+    const Coef<R>& c = a.c;
+    const int gi = strip * 56 - 4 + lane;
+    const int ci = wrap_any(gi, a.nx, a.bcx);
+    const bool gcol = GHOSTS && ci < 0;
+    const int b0 = band * B;
+    const R kdiag = R(2) * (c.ax + c.ay);
+    const size_t cells = (size_t)a.nx * a.ny;
+    const __amdgpu_buffer_rsrc_t rpo = buffer_of(a.psi_out, cells * sizeof(C));
+    const __amdgpu_buffer_rsrc_t rno = buffer_of(a.n_out, RES ? cells * sizeof(R) : 0);
+
+    // 8-row ring of inputs; ghost flags in bit s of gmask
+    C sp[8];
+    R sn[8], sP[8], sk[8];
+    unsigned int gmask = 0;
+    C acc[4];
+    R accn[4];
+    C w2[3], w3[3], w4[3];
+    R n2[2], n3[2], n4[2];
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+        sp[s] = czero<C>();
+        sn[s] = R(0);
+        sP[s] = R(0);
+        sk[s] = kdiag;
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        acc[s] = czero<C>();
+        accn[s] = R(0);
+    }
+#pragma unroll
+    for (int s = 0; s < 3; ++s) w2[s] = w3[s] = w4[s] = czero<C>();
+#pragma unroll
+    for (int s = 0; s < 2; ++s) n2[s] = n3[s] = n4[s] = R(0);
+
+    // The row to fetch advances by one per position: g unwrapped, rw its index under
+    // the boundary rule (-1 for a ghost row), advanced with selects so that the
+    // unrolled body has no branch.  Past the band's last needed row (use == false) rw
+    // stays put: the load repeats a row just read (a cache hit) and is never used.
+    int g = b0 - 4;
+    int rw = wrap_any(g, a.ny, a.bcy);
+    const int ci0 = ci < 0 ? 0 : ci;
+    auto fetch = [&](int s, bool use) {
+        const bool gh = GHOSTS && (gcol || rw < 0);
+        const int idx = gh ? 0 : rw * a.nx + ci0;
+        const C v = a.psi_in[idx];
+        sp[s] = gh ? czero<C>() : v;
+        if (RES) {
+            const R nv = a.n_in[idx];
+            const R pv = a.P[idx];
+            sn[s] = gh ? R(0) : nv;
+            sP[s] = gh ? R(0) : pv;
+        }
+        if (HASV) {
+            const R vv = a.V[idx];
+            sk[s] = gh ? kdiag : fma(c.inv_hbar, vv, kdiag);
+        }
+        if (GHOSTS) gmask = (gmask & ~(1u << s)) | ((gh ? 1u : 0u) << s);
+        const int gn = g + 1;
+        int rn;
+        if (YZERO) rn = (gn >= 0 && gn < a.ny) ? gn : -1;
+        else rn = (rw + 1 == a.ny) ? 0 : rw + 1;
+        g = use ? gn : g;
+        rw = use ? rn : rw;
+    };
+#pragma unroll
+    for (int t = 0; t < PF; ++t) fetch(t, true);
+
+    bool bad = false;
+    const bool out_col = lane >= 4 && lane < 60 && gi < a.nx;
+    for (int base = 0; base < B + 8; base += 24) {
+#pragma unroll
+        for (int u = 0; u < 24; ++u) {
+            const int j = b0 - 4 + base + u;  // newest row of this position
+            fetch(slot<8>(u, -PF), base + u + PF < B + 8);  // row j + PF
+            R fx, fy, fn;
+            // stage 1 at row j-1: argument = the state, rows j-2..j from the input ring
+            {
+                const int s0 = slot<8>(u, 1);
+                const C cur = sp[s0];
+                const C up = sp[slot<8>(u, 2)], dn = sp[slot<8>(u, 0)];
+                const R lrx = lane_prev(cur.x) + lane_next(cur.x);
+                const R lry = lane_prev(cur.y) + lane_next(cur.y);
+                cell_rhs<R, RES>(c, cur, lrx, lry, up.x + dn.x, up.y + dn.y, sn[s0], sP[s0], sk[s0], fx, fy, fn);
+                const bool g = GHOSTS && ((gmask >> s0) & 1u);
+                acc[slot<4>(u, 1)] = C{fx, fy};
+                accn[slot<4>(u, 1)] = fn;
+                w2[slot<3>(u, 1)] = g ? czero<C>() : C{fma(a.half_dt, fx, cur.x), fma(a.half_dt, fy, cur.y)};
+                n2[slot<2>(u, 1)] = g ? R(0) : fma(a.half_dt, fn, sn[s0]);
+            }
+            // stage 2 at row j-2: argument in w2 (rows j-3..j-1)
+            {
+                const int s0 = slot<8>(u, 2);
+                const C cur = w2[slot<3>(u, 2)];
+                const C up = w2[slot<3>(u, 3)], dn = w2[slot<3>(u, 1)];
+                const R nn = n2[slot<2>(u, 2)];
+                const R lrx = lane_prev(cur.x) + lane_next(cur.x);
+                const R lry = lane_prev(cur.y) + lane_next(cur.y);
+                cell_rhs<R, RES>(c, cur, lrx, lry, up.x + dn.x, up.y + dn.y, nn, sP[s0], sk[s0], fx, fy, fn);
+                const bool g = GHOSTS && ((gmask >> s0) & 1u);
+                C& ac = acc[slot<4>(u, 2)];
+                ac = C{fma(R(2), fx, ac.x), fma(R(2), fy, ac.y)};
+                accn[slot<4>(u, 2)] = fma(R(2), fn, accn[slot<4>(u, 2)]);
+                const C p0 = sp[s0];
+                w3[slot<3>(u, 2)] = g ? czero<C>() : C{fma(a.half_dt, fx, p0.x), fma(a.half_dt, fy, p0.y)};
+                n3[slot<2>(u, 2)] = g ? R(0) : fma(a.half_dt, fn, sn[s0]);
+            }
+            // stage 3 at row j-3: argument in w3 (rows j-4..j-2)
+            {
+                const int s0 = slot<8>(u, 3);
+                const C cur = w3[slot<3>(u, 3)];
+                const C up = w3[slot<3>(u, 4)], dn = w3[slot<3>(u, 2)];
+                const R nn = n3[slot<2>(u, 3)];
+                const R lrx = lane_prev(cur.x) + lane_next(cur.x);
+                const R lry = lane_prev(cur.y) + lane_next(cur.y);
+                cell_rhs<R, RES>(c, cur, lrx, lry, up.x + dn.x, up.y + dn.y, nn, sP[s0], sk[s0], fx, fy, fn);
+                const bool g = GHOSTS && ((gmask >> s0) & 1u);
+                C& ac = acc[slot<4>(u, 3)];
+                ac = C{fma(R(2), fx, ac.x), fma(R(2), fy, ac.y)};
+                accn[slot<4>(u, 3)] = fma(R(2), fn, accn[slot<4>(u, 3)]);
+                const C p0 = sp[s0];
+                w4[slot<3>(u, 3)] = g ? czero<C>() : C{fma(a.dt, fx, p0.x), fma(a.dt, fy, p0.y)};
+                n4[slot<2>(u, 3)] = g ? R(0) : fma(a.dt, fn, sn[s0]);
+            }
+            // stage 4 at row j-4: argument in w4 (rows j-5..j-3); the row is finished and
+            // stored when it lies in the band and in the grid (else the offset is out of
+            // range and the store is dropped)
+            {
+                const int s0 = slot<8>(u, 4);
+                const C cur = w4[slot<3>(u, 4)];
+                const C up = w4[slot<3>(u, 5)], dn = w4[slot<3>(u, 3)];
+                const R nn = n4[slot<2>(u, 4)];
+                const R lrx = lane_prev(cur.x) + lane_next(cur.x);
+                const R lry = lane_prev(cur.y) + lane_next(cur.y);
+                cell_rhs<R, RES>(c, cur, lrx, lry, up.x + dn.x, up.y + dn.y, nn, sP[s0], sk[s0], fx, fy, fn);
+                const C ac = acc[slot<4>(u, 4)];
+                const C p0 = sp[s0];
+                const C y = C{fma(a.dt6, ac.x + fx, p0.x), fma(a.dt6, ac.y + fy, p0.y)};
+                const R yn = fma(a.dt6, accn[slot<4>(u, 4)] + fn, sn[s0]);
+                const int r = j - 4;
+                const bool st = out_col && r >= b0 && r < b0 + B && r < a.ny;
+                const int cell = r * a.nx + gi;
+                buf_store_nt(y, rpo, st ? cell * (int)sizeof(C) : kOutOfRange);
+                bool b = !(isfinite(y.x) && isfinite(y.y));
+                if (RES) {
+                    buf_store_nt(yn, rno, st ? cell * (int)sizeof(R) : kOutOfRange);
+                    b = b || !isfinite(yn);
+                }
+                bad = bad || (st && b);
+            }
+        }
+    }
+    return bad;
+}
+
+}  // namespace phx

@@ -180,6 +180,20 @@ def test_tile_shape_validation_per_family():
         with pytest.raises(phx.PhxError) as e:
             phx.phx_workspace_bytes(good_config(tile_wx=bad[0], tile_rows=bad[1]))
         assert e.value.status == phx.PHX_EINVAL
+    # streaming form: tile_wx 1 with the instantiated band lengths, state under 2 GiB
+    for band in (40, 64, 88, 112):
+        phx.phx_workspace_bytes(good_config(tile_wx=1, tile_rows=band))
+    phx.phx_workspace_bytes(good_config(precision=phx.PHX_C128, tile_wx=1, tile_rows=64))
+    for bad in [(1, 44), (1, 16)]:
+        with pytest.raises(phx.PhxError):
+            phx.phx_workspace_bytes(good_config(tile_wx=bad[0], tile_rows=bad[1]))
+    big = good_config(tile_wx=1, tile_rows=40)
+    big.nx, big.ny = 16384, 16384          # 2 GiB of complex64 state
+    with pytest.raises(phx.PhxError) as e:
+        phx.phx_workspace_bytes(big)
+    assert e.value.status == phx.PHX_EINVAL
+    big.tile_wx, big.tile_rows = 8, 8      # the region form has no such limit
+    phx.phx_workspace_bytes(big)
 
 
 def test_tune_cache_roundtrip(tmp_path, monkeypatch):

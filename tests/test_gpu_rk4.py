@@ -270,8 +270,42 @@ def test_checkpoint_resume_bitwise(family):
     assert np.array_equal(out[0], ref[0]) and np.array_equal(out[1], ref[1])
 
 
-STEP_SHAPES = {C64: [(8, 4), (16, 4), (8, 8), (12, 4), (12, 6), (8, 6), (4, 8), (16, 6)],
-               C128: [(8, 4), (16, 2), (8, 2), (12, 4), (4, 4)]}
+STEP_SHAPES = {C64: [(8, 4), (16, 4), (8, 8), (12, 4), (12, 6), (8, 6), (4, 8), (16, 6),
+                     (1, 40), (1, 64), (1, 88), (1, 112)],
+               C128: [(8, 4), (16, 2), (8, 2), (12, 4), (4, 4), (1, 40), (1, 64)]}
+
+
+@pytest.mark.parametrize("precision", PREC)
+@pytest.mark.parametrize("bc", BCS)
+@pytest.mark.parametrize("shape", [(57, 40), (113, 41), (56, 131), (55, 39), (1, 1), (1, 5), (5, 1), (64, 1),
+                                   (65, 3), (3, 65)])
+def test_stream_kernel_edges(shape, bc, precision):
+    """Streaming whole-step kernel (bands of 40 rows, strips of 56 columns) on grids
+    around multiples of both, on single cells, rows and columns, for 1, 2 and 7 steps."""
+    nx, ny = shape
+    ph, psi, n, V, P = workload("driven_v", nx, ny, bc, seed=18)
+    for steps in (1, 2, 7):
+        e_psi, e_n = compare(ph, psi, n, V, P, steps, precision, kernel=phx.PHX_KERNEL_STEP,
+                             tile_wx=1, tile_rows=40)
+        assert e_psi <= TOL[precision] and e_n <= TOL[precision], (steps, e_psi, e_n)
+
+
+@pytest.mark.parametrize("bc", [(0, 0), (1, 1), (0, 1)])
+def test_stream_and_region_kernels_bitwise(bc):
+    """The streaming and the region whole-step kernels apply the same per-cell
+    arithmetic in the same order: their states agree bit for bit."""
+    for precision in PREC:
+        ph, psi, n, V, P = workload("driven_v", 300, 211, bc, seed=19)
+        q = quantize(precision, psi, n, V, P)
+        out = []
+        for shape in [(8, 4), (1, 40), (1, 64)]:
+            run = GpuRun(ph, *q, precision=precision, kernel=phx.PHX_KERNEL_STEP, tile_wx=shape[0],
+                         tile_rows=shape[1])
+            run.step(9)
+            out.append(run.state())
+            run.close()
+        for p_, n_ in out[1:]:
+            assert np.array_equal(p_, out[0][0]) and np.array_equal(n_, out[0][1])
 
 
 @pytest.mark.parametrize("precision", PREC)
