@@ -127,7 +127,7 @@ def main():
     if args.tile:
         tune = {"tile_wx": args.tile[0], "tile_rows": args.tile[1]}
     else:
-        tune = solver.autotune(reps=10, use_cache=False) if not args.no_tune else None
+        tune = solver.autotune(reps=30, use_cache=False) if not args.no_tune else None
 
     copy_gbps = copy_bandwidth_gbps(torch)
 

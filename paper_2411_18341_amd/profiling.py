@@ -27,7 +27,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 # sources whose change invalidates a stored counter measurement of the RK4 kernels
 KERNEL_SOURCES = ["paper_2411_18341_amd/csrc/rk4.hip", "paper_2411_18341_amd/csrc/stencil.h",
                   "paper_2411_18341_amd/csrc/phx_kernels.h", "paper_2411_18341_amd/csrc/rk4_step.hip",
-                  "paper_2411_18341_amd/csrc/step_body.h"]
+                  "paper_2411_18341_amd/csrc/step_body.h", "paper_2411_18341_amd/csrc/stream_body.h"]
 
 
 def kernel_source_hash() -> str:
@@ -42,14 +42,18 @@ def kernel_source_hash() -> str:
 
 def kernel_kind(name: str) -> str:
     """Kernel kind as the solver's timing API names it (rk4_stage2, dp_stage7, ...),
-    the whole-step kernel with its region shape (rk4_step_8x6: 8 waves x 6 rows), or
-    a shortened name for other kernels."""
+    the whole-step kernel with its shape (rk4_step_8x6: 8 waves x 6 rows; the
+    streaming form rk4_step_1x40: bands of 40 rows), or a shortened name for other
+    kernels."""
     m = re.search(r"(rk4_stage_kernel|dp_stage_kernel)<[^>]*?(\d+)>", name)
     if m:
         return ("rk4_stage" if m.group(1).startswith("rk4") else "dp_stage") + m.group(2)
     m = re.search(r"rk4_step_kernel<[^>]*?(\d+), (\d+)>", name)
     if m:
         return f"rk4_step_{m.group(1)}x{m.group(2)}"
+    m = re.search(r"rk4_stream_kernel<[^>]*?(\d+)>", name)
+    if m:  # streaming form: shape 1 x band rows
+        return f"rk4_step_1x{m.group(1)}"
     named = {"rk4_step_kernel": "rk4_step", "batch_step_kernel": "batch_step", "dp_restart_kernel": "dp_restart",
              "dp_err_sum_kernel": "dp_error", "obs_pass1": "obs_pass1", "obs_pass2": "obs_pass2",
              "conv_fwd_kernel": "conv_fwd", "conv_bwd_weight_kernel": "conv_bwd_weight"}
