@@ -18,9 +18,9 @@ static phx_status time_launches(phx_handle* h, int reps, F launch, double* us)
         (void)hipEventDestroy(e0);
         return fail(PHX_EHIP, "hipEventCreate failed");
     }
-    hipError_t e = launch();  // warm-up
+    hipError_t e = launch(0);  // warm-up
     if (e == hipSuccess) e = hipEventRecord(e0, h->stream);
-    for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch();
+    for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch(r + 1);
     if (e == hipSuccess) e = hipEventRecord(e1, h->stream);
     if (e == hipSuccess) e = hipEventSynchronize(e1);
     float ms = 0.f;
@@ -46,7 +46,7 @@ static phx_status tune_step(phx_handle* h, int reps, phx_tune_result* out)
         if (!step_shape_fits(h->cfg, sh.waves)) continue;
         ++timed;
         double us;
-        phx_status s = time_launches(h, reps, [&] { return rk4_step_trial<R>(h, sh); }, &us);
+        phx_status s = time_launches(h, reps, [&](int k) { return rk4_step_trial<R>(h, sh, k); }, &us);
         if (s != PHX_OK) return s;
         if (sh.waves == before.waves && sh.rows == before.rows) before_us = us;
         if (us < best_us) {
@@ -73,7 +73,7 @@ static phx_status tune_stage(phx_handle* h, int reps, phx_tune_result* out)
         for (int r : rows) {
             const TileShape ts{wx, r};
             double us;
-            phx_status s = time_launches(h, reps, [&] { return rk4_stage_trial<R>(h, ts); }, &us);
+            phx_status s = time_launches(h, reps, [&](int) { return rk4_stage_trial<R>(h, ts); }, &us);
             if (s != PHX_OK) return s;
             ++count;
             if (wx == before.wx && r == before.rows) before_us = us;

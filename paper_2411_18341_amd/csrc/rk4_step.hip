@@ -41,7 +41,8 @@ __global__ __launch_bounds__(256) void rk4_stream_kernel(const StepArgs<R> a)
     const int groups_x = (a.tiles_x + 3) / 4;
     const int band = t / groups_x, strip = (t - band * groups_x) * 4 + wave;
     if (strip >= a.tiles_x) return;
-    if (stream_band<R, RES, HASV, GHOSTS, YZERO, B>(a, strip, band)) a.flag[0] = 1u;  // benign race
+    if (stream_band<R, RES, HASV, GHOSTS, YZERO, B>(a, strip, band, (band & 1) ? -1 : 1))
+        a.flag[0] = 1u;  // benign race
 }
 
 // GHOSTS: some boundary is zero, so region cells outside the grid must be held at 0
@@ -144,18 +145,31 @@ static StepArgs<R> step_args(const phx_handle* h, const StepShapeId& sh, const v
     return a;
 }
 
-// One trial launch for the tuner: reads the caller's state, writes the workspace
-// copy, so the state is left unchanged.
+// Trial launch k of the tuner.  k = 0 steps the caller's state into the workspace
+// copy; later trials alternate between the two workspace copies, so that each one
+// reads the state the previous one wrote, as real steps do (a launch that re-read one
+// unchanged input would find part of it in the Infinity Cache).  The caller's state
+// is never written.
 template <typename R>
-hipError_t rk4_step_trial(phx_handle* h, const StepShapeId& sh)
+hipError_t rk4_step_trial(phx_handle* h, const StepShapeId& sh, int k)
 {
-    const StepArgs<R> a = step_args<R>(h, sh, h->f.psi, h->f.n, h->ws + h->L.alt,
-                                       h->cfg.reservoir ? h->ws + h->L.alt_n : nullptr);
-    return launch_rk4_step<R>(h->cfg.reservoir != 0, h->f.V != nullptr, sh, a, h->stream);
+    const bool res = h->cfg.reservoir != 0;
+    char* A = h->ws + h->L.alt;
+    char* An = res ? h->ws + h->L.alt_n : nullptr;
+    char* B = h->ws + h->L.alt2;
+    char* Bn = res ? h->ws + h->L.alt2_n : nullptr;
+    StepArgs<R> a;
+    if (k == 0)
+        a = step_args<R>(h, sh, h->f.psi, h->f.n, A, An);
+    else if (k & 1)
+        a = step_args<R>(h, sh, A, An, B, Bn);
+    else
+        a = step_args<R>(h, sh, B, Bn, A, An);
+    return launch_rk4_step<R>(res, h->f.V != nullptr, sh, a, h->stream);
 }
 
-template hipError_t rk4_step_trial<float>(phx_handle*, const StepShapeId&);
-template hipError_t rk4_step_trial<double>(phx_handle*, const StepShapeId&);
+template hipError_t rk4_step_trial<float>(phx_handle*, const StepShapeId&, int);
+template hipError_t rk4_step_trial<double>(phx_handle*, const StepShapeId&, int);
 
 // Enqueues n whole steps on stream s, alternating between the caller's arrays
 // (buffer 0) and the workspace copy (buffer 1); h->step_parity is the buffer that

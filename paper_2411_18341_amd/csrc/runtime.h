@@ -32,6 +32,7 @@ struct Layout {
     size_t ys;          // Dormand-Prince stage argument
     size_t alt;         // second state buffer for psi (whole-step RK4, Dormand-Prince)
     size_t alt_n;       // second state buffer for n (whole-step RK4)
+    size_t alt2, alt2_n;  // third state buffer (whole-step RK4: the tuner's trial launches)
     int family;         // PHX_KERNEL_STAGE or PHX_KERNEL_STEP for RK4
     size_t err;         // Dormand-Prince error partials
     int obs_blocks;
@@ -108,7 +109,7 @@ template <typename R> phx_status rk4_fused_launches(phx_handle* h, int64_t n, hi
 template <typename R> phx_status rk4_stage_launches(phx_handle* h, int64_t n, hipStream_t s);
 int graph_chunk(const phx_config& c);
 template <typename R> phx_status rk4_run_graph(phx_handle* h, int64_t n);
-template <typename R> hipError_t rk4_step_trial(phx_handle* h, const StepShapeId& sh);
+template <typename R> hipError_t rk4_step_trial(phx_handle* h, const StepShapeId& sh, int k);
 template <typename R> hipError_t rk4_stage_trial(phx_handle* h, const TileShape& ts);
 int step_shapes(int precision, const StepShapeId** out);
 bool step_shape_fits(const phx_config& c, int waves);

@@ -107,6 +107,8 @@ Layout make_layout(const phx_config& c)
         if (L.family == PHX_KERNEL_STEP) {
             L.alt = take(cb);
             if (c.reservoir) L.alt_n = take(rb);
+            L.alt2 = take(cb);
+            if (c.reservoir) L.alt2_n = take(rb);
         } else {
             L.y[0] = take(cb);
             L.y[1] = take(cb);

@@ -10,6 +10,7 @@
 // (each stage needs its argument at rows r-1..r+1, produced by the previous stage at
 // this or an earlier row), and stores the finished row j-4 when it lies in the band;
 // the walk ends with row b0+B+3, which finishes row b0+B-1.
+// (Rows are named for a downward walk; an upward walk mirrors them.)
 // Per-row inputs (psi, n, P, V) wait in an 8-row ring, loaded 3 rows ahead of their
 // first use; the running sums K1 + 2K2 + 2K3 in a 4-row ring; the stage arguments
 // of stages 2..4 in 3-row windows.  The row loop is unrolled by 24 (a multiple of
@@ -87,9 +88,13 @@ __device__ __forceinline__ void buf_store_nt(double2 v, __amdgpu_buffer_rsrc_t r
                                            r, off, 0, kNonTemporal);
 }
 
-// YZERO: the y boundary is zero (ghost rows); else periodic in y.
+// YZERO: the y boundary is zero (ghost rows); else periodic in y.  dir = +1 walks the
+// band downwards (rows b0-4 .. b0+B+3), dir = -1 upwards (rows b0+B+3 .. b0-4): odd
+// bands walk up, so that neighbouring bands reach the 8 rows they both read at the same
+// time (the second read is an L2 hit).  The stencil is symmetric in y, so the result
+// does not depend on the direction.
 template <typename R, bool RES, bool HASV, bool GHOSTS, bool YZERO, int B>
-__device__ __forceinline__ bool stream_band(const StepArgs<R>& a, int strip, int band)
+__device__ __forceinline__ bool stream_band(const StepArgs<R>& a, int strip, int band, int dir)
 {
     using C = typename cvec<R>::type;
     static_assert((B + 8) % 24 == 0, "band rows + 8 must be a multiple of the unroll length");
@@ -134,7 +139,8 @@ __device__ __forceinline__ bool stream_band(const StepArgs<R>& a, int strip, int
     // the boundary rule (-1 for a ghost row), advanced with selects so that the
     // unrolled body has no branch.  Past the band's last needed row (use == false) rw
     // stays put: the load repeats a row just read (a cache hit) and is never used.
-    int g = b0 - 4;
+    const int start = dir > 0 ? b0 - 4 : b0 + B + 3;
+    int g = start;
     int rw = wrap_any(g, a.ny, a.bcy);
     const int ci0 = ci < 0 ? 0 : ci;
     auto fetch = [&](int s, bool use) {
@@ -153,10 +159,14 @@ __device__ __forceinline__ bool stream_band(const StepArgs<R>& a, int strip, int
             sk[s] = gh ? kdiag : fma(c.inv_hbar, vv, kdiag);
         }
         if (GHOSTS) gmask = (gmask & ~(1u << s)) | ((gh ? 1u : 0u) << s);
-        const int gn = g + 1;
+        const int gn = g + dir;
         int rn;
-        if (YZERO) rn = (gn >= 0 && gn < a.ny) ? gn : -1;
-        else rn = (rw + 1 == a.ny) ? 0 : rw + 1;
+        if (YZERO) {
+            rn = (gn >= 0 && gn < a.ny) ? gn : -1;
+        } else {
+            rn = rw + dir;
+            rn = rn == a.ny ? 0 : (rn < 0 ? a.ny - 1 : rn);
+        }
         g = use ? gn : g;
         rw = use ? rn : rw;
     };
@@ -168,7 +178,7 @@ __device__ __forceinline__ bool stream_band(const StepArgs<R>& a, int strip, int
     for (int base = 0; base < B + 8; base += 24) {
 #pragma unroll
         for (int u = 0; u < 24; ++u) {
-            const int j = b0 - 4 + base + u;  // newest row of this position
+            const int j = start + dir * (base + u);  // newest row of this position
             fetch(slot<8>(u, -PF), base + u + PF < B + 8);  // row j + PF
             R fx, fy, fn;
             // stage 1 at row j-1: argument = the state, rows j-2..j from the input ring
@@ -234,7 +244,7 @@ __device__ __forceinline__ bool stream_band(const StepArgs<R>& a, int strip, int
                 const C p0 = sp[s0];
                 const C y = C{fma(a.dt6, ac.x + fx, p0.x), fma(a.dt6, ac.y + fy, p0.y)};
                 const R yn = fma(a.dt6, accn[slot<4>(u, 4)] + fn, sn[s0]);
-                const int r = j - 4;
+                const int r = j - 4 * dir;
                 const bool st = out_col && r >= b0 && r < b0 + B && r < a.ny;
                 const int cell = r * a.nx + gi;
                 buf_store_nt(y, rpo, st ? cell * (int)sizeof(C) : kOutOfRange);
