@@ -160,6 +160,7 @@ def measure_spinor(n: int = 4096, accepted: int = 20, rk4_steps: int = 50):
         else:
             model = bytemodel.dopri5_attempt(4, reservoir=False, has_v=True, components=2)
             names = {f"dp_stage{k}": model[f"stage{k}"] for k in range(2, 8)}
+            names["dp_stage1"] = model["restart"]  # after the first step every attempt restarts from K1
         ks = {}
         for k, v in times.items():
             us = v["ms_total"] / v["launches"] * 1e3
