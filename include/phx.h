@@ -87,6 +87,17 @@ typedef struct phx_config {
                                form: rows per band (40, 64, 88, 112; state under 2 GiB)    */
     int32_t graph_steps;    /* RK4 steps per captured hipGraph chunk replayed by phx_step:
                                0 = default (64), < 0 = launch every kernel directly        */
+    double noise;           /* intensity nu of the complex Wiener noise dW (Sec. 5, truncated
+                               Wigner); 0 = deterministic.  RK4 only (PHX_EUNSUPPORTED
+                               otherwise): after every step each cell of each component gets
+                               dW = sqrt(nu (R n + gamma_c) dt / (4 dx dy)) (xi1 + i xi2),
+                               <dW dW*> = nu (R n + gamma_c) dt / (2 dx dy), n the cell's
+                               reservoir after the step (0 without the reservoir)          */
+    uint64_t seed;          /* noise key: xi1, xi2 are the Box-Muller pair of the first two
+                               words of Philox4x32-10 (Salmon et al., SC'11) of the counter
+                               (j nx + i, component, step low word, step high word) under the
+                               key (seed low word, seed high word), u = (x + 1/2) 2^-32; the
+                               step index is phx_info.steps_accepted before the step        */
 } phx_config;
 
 /* Caller-owned device arrays bound to a handle (borrowed until phx_destroy). */

@@ -106,6 +106,14 @@ def _load():
                                    ctypes.c_double, ctypes.c_double, ctypes.c_int64, P(_Ctrl),
                                    vp, ctypes.c_int64]
         lib.orc_observables.argtypes = [P(_Params), vp, vp, vp, vp, P(_Obs)]
+        u32p = P(ctypes.c_uint32)
+        lib.orc_philox.argtypes = [u32p, u32p, u32p]
+        lib.orc_gauss_pair.argtypes = [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int64, ctypes.c_uint64,
+                                       P(ctypes.c_double)]
+        lib.orc_noise.argtypes = [P(_Params), vp, vp, ctypes.c_double, ctypes.c_double, ctypes.c_uint64,
+                                  ctypes.c_int64]
+        lib.orc_rk4_noise.argtypes = [P(_Params), vp, vp, vp, vp, ctypes.c_double, ctypes.c_int64,
+                                      ctypes.c_double, ctypes.c_uint64, ctypes.c_int64]
         _lib = lib
     return _lib
 
@@ -265,6 +273,45 @@ def observables(ph: Physics, psi, n=None, V=None, P=None) -> dict:
     d = {k: getattr(o, k) for k, _ in _Obs._fields_ if k != "norm"}
     d["norm"] = (o.norm[0], o.norm[1])
     return d
+
+
+def philox(counter, key):
+    """Philox4x32-10 of a 4-word counter and a 2-word key (4 uint32)."""
+    c = (ctypes.c_uint32 * 4)(*[int(v) & 0xffffffff for v in counter])
+    k = (ctypes.c_uint32 * 2)(*[int(v) & 0xffffffff for v in key])
+    out = (ctypes.c_uint32 * 4)()
+    _load().orc_philox(c, k, out)
+    return tuple(int(v) for v in out)
+
+
+def gauss_pair(q: int, comp: int, step: int, seed: int):
+    """The two standard normals of cell q, component comp, step `step`."""
+    out = (ctypes.c_double * 2)()
+    _load().orc_gauss_pair(q, comp, step, seed, out)
+    return out[0], out[1]
+
+
+def noise(ph: Physics, psi, n, dt: float, nu: float, seed: int, step: int):
+    """Adds the Wiener increment of step `step`; returns the new psi."""
+    lib = _load()
+    sp, sn, _ = _shapes(ph)
+    psi = _cplx(psi, sp)
+    n = _real(n, sn, ph.reservoir)
+    lib.orc_noise(ctypes.byref(ph._c()), _ptr(psi), _ptr(n), float(dt), float(nu), int(seed), int(step))
+    return psi
+
+
+def rk4_noise(ph: Physics, psi, n=None, V=None, P=None, dt=1e-3, steps=1, nu=1.0, seed=0, step0=0):
+    """`steps` RK4 steps, each followed by its Wiener increment; returns new arrays."""
+    lib = _load()
+    sp, sn, sv = _shapes(ph)
+    psi = _cplx(psi, sp)
+    n = _real(n, sn, ph.reservoir)
+    P = _real(P, sn, ph.reservoir)
+    V = _real(V, sv, False)
+    lib.orc_rk4_noise(ctypes.byref(ph._c()), _ptr(psi), _ptr(n), _ptr(V), _ptr(P), float(dt), int(steps),
+                      float(nu), int(seed), int(step0))
+    return psi, n
 
 
 def num_threads() -> int:

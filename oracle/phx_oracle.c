@@ -20,6 +20,8 @@
  *   - Adaptive Dormand-Prince 5(4), named in Sec. 2; tableau from Dormand & Prince,
  *     J. Comput. Appl. Math. 6 (1980) 19-26; step controller as in Hairer, Norsett &
  *     Wanner, Solving ODEs I, Sec. II.4.
+ *   - Complex Wiener noise dW of Eq. (PULSE_psi) with the correlations of Sec. 5
+ *     (truncated Wigner), drawn from Philox4x32-10 and the Box-Muller transform.
  *
  * Readings where the paper is silent (each is also listed in the design notes):
  *   - f in Eqs. (rk4_K1)-(rk4_K4) is the time derivative d psi/dt = -(i/hbar) H psi.
@@ -29,6 +31,9 @@
  *   - (psi, n) form one coupled state advanced by the same Runge-Kutta stages.
  *   - The loss gamma of Eq. (1) and the gamma of Eq. (PULSE_psi) are the same
  *     parameter (gamma_c here).
+ *   - The noise correlation carries the factor dt of a Wiener increment and the
+ *     intensity factor nu; it is added after each deterministic RK4 step (Euler-
+ *     Maruyama splitting) with the reservoir value after that step.
  *
  * Layout: psi is [components][ny][nx] complex, x fastest; n and P are
  * [components][ny][nx] real when the reservoir is on; V is [ny][nx] real (NULL = 0).
@@ -122,7 +127,7 @@ void orc_rhs(const orc_params *p, const cplx *psi, const double *n, const double
         const cplx *ps = psi + (size_t)c * N;
         const cplx *po = psi + (size_t)(C - 1 - c) * N;
         const double sgn = (c == 0) ? 1.0 : -1.0;
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (N >= 16384)
         for (int j = 0; j < p->ny; ++j) {
             for (int i = 0; i < p->nx; ++i) {
                 const size_t k = (size_t)j * p->nx + i;
@@ -415,6 +420,83 @@ void orc_observables(const orc_params *p, const cplx *psi, const double *n, cons
     o->steady_res_density = (s_rho2 > 0) ? sqrt(s_drho2) / sqrt(s_rho2) : 0.0;
     o->steady_res_reservoir = (p->reservoir && s_p2 > 0) ? sqrt(s_fn2) / sqrt(s_p2) : 0.0;
     free(fp); free(fn);
+}
+
+/* ------------------------------------------------- stochastic (Wiener) noise */
+
+/* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as easy as
+ * 1, 2, 3", SC'11): ten rounds of the Philox S-box on a 4 x 32-bit counter with a
+ * 2 x 32-bit key.  One round multiplies words 0 and 2 by the two round constants,
+ * takes the 64-bit products apart, and forms the new counter from their high words
+ * xor-ed with words 1 and 3 and the key, and their low words; the key is bumped by
+ * the two Weyl constants between rounds. */
+void orc_philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;  /* multipliers of the paper */
+    const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;  /* key schedule (Weyl) */
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        const uint64_t p0 = (uint64_t)M0 * c0, p1 = (uint64_t)M1 * c2;
+        const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        const uint32_t n0 = hi1 ^ c1 ^ k0, n1 = lo1, n2 = hi0 ^ c3 ^ k1, n3 = lo0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+        k0 += W0;
+        k1 += W1;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* Two standard normal numbers for (cell q of component s, step) and a 64-bit seed:
+ * Philox4x32-10 of the counter (q, s, step low word, step high word) with the key
+ * (seed low word, seed high word); its first two words x0, x1 give the uniforms
+ * u = (x + 1/2) 2^-32 in (0, 1), and the Box-Muller transform (Box & Muller, Ann.
+ * Math. Statist. 29 (1958) 610) gives r cos(2 pi u2), r sin(2 pi u2) with
+ * r = sqrt(-2 ln u1). */
+void orc_gauss_pair(uint32_t q, uint32_t s, int64_t step, uint64_t seed, double out[2])
+{
+    const uint32_t ctr[4] = {q, s, (uint32_t)(uint64_t)step, (uint32_t)((uint64_t)step >> 32)};
+    const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t x[4];
+    orc_philox(ctr, key, x);
+    const double u1 = ((double)x[0] + 0.5) / 4294967296.0;
+    const double u2 = ((double)x[1] + 0.5) / 4294967296.0;
+    const double r = sqrt(-2.0 * log(u1));
+    const double two_pi = 6.283185307179586476925286766559;
+    out[0] = r * cos(two_pi * u2);
+    out[1] = r * sin(two_pi * u2);
+}
+
+/* The complex Wiener increment of step `step` added to every cell (Sec. 5, truncated
+ * Wigner): <dW dW> = 0 and <dW dW*> = nu (R n + gamma_c) dt / (2 dV) per cell, with
+ * dV = dx dy the cell area and n the reservoir value of the cell (0 without the
+ * reservoir); dW = sqrt(nu (R n + gamma_c) dt / (4 dV)) (xi1 + i xi2). */
+void orc_noise(const orc_params *p, cplx *psi, const double *n, double dt, double nu, uint64_t seed,
+               int64_t step)
+{
+    const size_t N = cells(p);
+    const double dV = p->dx * p->dy;
+    for (int s = 0; s < p->components; ++s) {
+        for (size_t q = 0; q < N; ++q) {
+            const double nn = p->reservoir ? n[(size_t)s * N + q] : 0.0;
+            const double var = nu * (p->R * nn + p->gamma_c) * dt / (4.0 * dV);
+            double xi[2];
+            orc_gauss_pair((uint32_t)q, (uint32_t)s, step, seed, xi);
+            psi[(size_t)s * N + q] += sqrt(var > 0.0 ? var : 0.0) * (xi[0] + I * xi[1]);
+        }
+    }
+}
+
+/* n_steps RK4 steps, each followed by the Wiener increment of its step index
+ * step0, step0 + 1, ... (the noise amplitude uses the reservoir after the step). */
+void orc_rk4_noise(const orc_params *p, cplx *psi, double *n, const double *V, const double *P, double dt,
+                   int64_t n_steps, double nu, uint64_t seed, int64_t step0)
+{
+    for (int64_t k = 0; k < n_steps; ++k) {
+        orc_rk4(p, psi, n, V, P, dt, 1);
+        orc_noise(p, psi, n, dt, nu, seed, step0 + k);
+    }
 }
 
 /* Threads the OpenMP loops above use (reported beside timings of this oracle). */

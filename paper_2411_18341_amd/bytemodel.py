@@ -66,3 +66,9 @@ def dopri5_attempt(real_bytes: int, reservoir: bool, has_v: bool, components: in
     out = {"restart": restart, **{f"stage{s}": b for s, b in stages.items()}}
     out["attempt"] = restart + sum(stages.values())
     return out
+
+
+def wiener_noise(real_bytes: int, reservoir: bool, components: int = 1) -> int:
+    """Bytes per point of the Wiener-increment pass: every complex value is read and
+    written once, the reservoir (the amplitude's n) is read once."""
+    return components * (4 * real_bytes + (real_bytes if reservoir else 0))

@@ -191,8 +191,16 @@ phx_status rk4_fused_launches(phx_handle* h, int64_t n, hipStream_t s)
         if (e == hipSuccess) e = timing_end(h, t0, K_RK4_STEP);
         if (e != hipSuccess) return fail(PHX_EHIP, "RK4 step kernel launch: %s", hipGetErrorString(e));
         cur ^= 1;
+        if (c.noise > 0.0) {
+            e = timing_begin(h, &t0);
+            if (e == hipSuccess) e = launch_noise<R>(h, S[cur], SN[cur], k, s);
+            if (e == hipSuccess) e = timing_end(h, t0, K_NOISE);
+            if (e != hipSuccess) return fail(PHX_EHIP, "noise launch: %s", hipGetErrorString(e));
+        }
     }
     h->step_parity = cur;
+    if (c.noise > 0.0 && n > 0 && advance_noise_step(h, n, s) != hipSuccess)
+        return fail(PHX_EHIP, "noise step advance launch failed");
     return PHX_OK;
 }
 

@@ -33,6 +33,7 @@ struct Layout {
     size_t alt;         // second state buffer for psi (whole-step RK4, Dormand-Prince)
     size_t alt_n;       // second state buffer for n (whole-step RK4)
     size_t alt2, alt2_n;  // third state buffer (whole-step RK4: the tuner's trial launches)
+    size_t noise;       // step index of the next Wiener increment (uint64; noise on only)
     int family;         // PHX_KERNEL_STAGE or PHX_KERNEL_STEP for RK4
     size_t err;         // Dormand-Prince error partials
     int obs_blocks;
@@ -95,7 +96,7 @@ namespace phx {
 // Kernel kinds for phx_kernel_times; names in kernel_kind_name().
 enum KernelKind {
     K_RK4_S1 = 0, K_RK4_S2, K_RK4_S3, K_RK4_S4, K_OBS, K_DP_S1, K_DP_S2, K_DP_S3, K_DP_S4,
-    K_DP_S5, K_DP_S6, K_DP_S7, K_DP_ERR, K_BATCH, K_RK4_STEP, K_KINDS_
+    K_DP_S5, K_DP_S6, K_DP_S7, K_DP_ERR, K_BATCH, K_RK4_STEP, K_NOISE, K_KINDS_
 };
 const char* kernel_kind_name(int k);
 // Timing brackets around one launch (no-ops unless timing is on).
@@ -116,4 +117,10 @@ bool step_shape_fits(const phx_config& c, int waves);
 int rk4_family(const phx_config& c);
 phx_status step_rk45(phx_handle* h, int64_t n, phx_info* out);
 phx_status set_info_rk45(phx_handle* h, const phx_info* in);
+// Wiener increment of one step on (psi, n) with step index base + offset; the base
+// is advanced after each run of steps and set at creation and by phx_set_info.
+template <typename R> hipError_t launch_noise(const phx_handle* h, void* psi, const void* n, int64_t offset,
+                                              hipStream_t s);
+hipError_t advance_noise_step(const phx_handle* h, int64_t by, hipStream_t s);
+hipError_t set_noise_step(const phx_handle* h, int64_t value, hipStream_t s);
 }  // namespace phx

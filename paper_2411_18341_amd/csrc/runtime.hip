@@ -71,6 +71,9 @@ phx_status validate_config(const phx_config* c)
     for (double x : coefs)
         if (!isfinite(x)) return fail(PHX_EINVAL, "equation parameters must be finite");
     if (!finite_pos(c->dt)) return fail(PHX_EINVAL, "dt must be finite and > 0");
+    if (!isfinite(c->noise) || c->noise < 0.0) return fail(PHX_EINVAL, "noise must be finite and >= 0");
+    if (c->noise > 0.0 && c->integrator != PHX_RK4)
+        return fail(PHX_EUNSUPPORTED, "Wiener noise is implemented for RK4 only");
     if (c->integrator == PHX_RK4) {
         // Largest |lambda| of the kinetic term on the grid: (hbar/2m) 4 (1/dx^2 + 1/dy^2);
         // RK4 is unstable on the imaginary axis beyond |lambda dt| = 2 sqrt(2).
@@ -102,6 +105,7 @@ Layout make_layout(const phx_config& c)
     L.tiles = plan_tiles(c.nx, c.ny, stage_tiles ? c.tile_wx : 0, stage_tiles ? c.tile_rows : 0);
     L.obs_blocks = L.tiles.tiles < 1024 ? L.tiles.tiles : 1024;
     L.partials = take((size_t)L.obs_blocks * OBS_SLOTS * sizeof(double));
+    if (c.noise > 0.0) L.noise = take(sizeof(uint64_t));
     if (c.integrator == PHX_RK4) {
         L.family = rk4_family(c);
         if (L.family == PHX_KERNEL_STEP) {
@@ -255,8 +259,10 @@ phx_status phx_create(const phx_config* cfg, const phx_fields* f, void* stream,
     hipError_t e = hipHostMalloc((void**)&h->host, (OBS_SLOTS + 2) * sizeof(double), hipHostMallocDefault);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&h->flag_ready, hipEventDisableTiming);
     if (e == hipSuccess) e = hipMemsetAsync(h->ws + L.flag, 0, 256, h->stream);
+    if (e == hipSuccess && cfg->noise > 0.0) e = set_noise_step(h, 0, h->stream);
     if (e != hipSuccess) {
         if (h->host) (void)hipHostFree(h->host);
+        if (h->flag_ready) (void)hipEventDestroy(h->flag_ready);
         delete h;
         return fail(PHX_EHIP, "phx_create: %s", hipGetErrorString(e));
     }
@@ -345,7 +351,16 @@ phx_status rk4_stage_launches(phx_handle* h, int64_t n, hipStream_t stream)
             if (e == hipSuccess) e = timing_end(h, t0, K_RK4_S1 + s);
             if (e != hipSuccess) return fail(PHX_EHIP, "RK4 stage %d launch: %s", s + 1, hipGetErrorString(e));
         }
+        if (c.noise > 0.0) {
+            hipEvent_t t0 = nullptr;
+            hipError_t e = timing_begin(h, &t0);
+            if (e == hipSuccess) e = launch_noise<R>(h, psi, n0, k, stream);
+            if (e == hipSuccess) e = timing_end(h, t0, K_NOISE);
+            if (e != hipSuccess) return fail(PHX_EHIP, "noise launch: %s", hipGetErrorString(e));
+        }
     }
+    if (c.noise > 0.0 && n > 0 && advance_noise_step(h, n, stream) != hipSuccess)
+        return fail(PHX_EHIP, "noise step advance launch failed");
     return PHX_OK;
 }
 
@@ -572,6 +587,8 @@ phx_status phx_set_info(phx_handle* h, const phx_info* in)
         HIP_OR_FAIL(hipMemsetAsync(h->ws + h->L.flag, 0, 256, h->stream));
         h->flag_pending = false;
     }
+    // the next Wiener increment continues the restored run's sequence
+    if (h->cfg.noise > 0.0) HIP_OR_FAIL(set_noise_step(h, in->steps_accepted, h->stream));
     h->info = *in;
     return PHX_OK;
 }
@@ -585,7 +602,7 @@ const char* kernel_kind_name(int k)
     static const char* names[K_KINDS_] = {
         "rk4_stage1", "rk4_stage2", "rk4_stage3", "rk4_stage4", "observables",
         "dp_stage1", "dp_stage2", "dp_stage3", "dp_stage4", "dp_stage5", "dp_stage6",
-        "dp_stage7", "dp_error", "batch_stage", "rk4_step"};
+        "dp_stage7", "dp_error", "batch_stage", "rk4_step", "wiener_noise"};
     return (k >= 0 && k < K_KINDS_) ? names[k] : "unknown";
 }
 

@@ -16,7 +16,8 @@ from HBM.
 With --batch it first measures the batched workload of 256 driven instances on
 grids of 128..1024 (one persistent launch per step) against stepping the same
 instances with one solver each; with --spinor the 4096^2 two-component workload
-with RK4 and with Dormand-Prince.
+with RK4 and with Dormand-Prince; with --noise the 4096^2 driven workload with the
+truncated-Wigner noise on and off.
 """
 from __future__ import annotations
 
@@ -177,6 +178,45 @@ def measure_spinor(n: int = 4096, accepted: int = 20, rk4_steps: int = 50):
     return out
 
 
+def measure_noise(n: int = 4096, nu: float = 1.0, steps: int = 300, warmup: int = 20, timed_steps: int = 40):
+    """The driven workload (complex64, n x n) with the complex Wiener noise of the
+    truncated-Wigner form switched on: point updates per second of whole noisy RK4
+    steps (graph replays, as phx_step runs them), the same without noise, and the
+    mean launch time of the step kernel and of the noise pass with the pass's
+    algorithmic bandwidth (complex read + write, reservoir read)."""
+    import torch
+    ph, psi0, n0, P = inputs.driven(n)
+    dev = torch.device("cuda:0")
+    out = {"n": n, "nu": nu}
+    for label, noise in (("deterministic", 0.0), ("noisy", nu)):
+        psi = torch.from_numpy(psi0).to(dtype=torch.complex64, device=dev).contiguous()
+        nn = torch.from_numpy(n0).to(dtype=torch.float32, device=dev).contiguous()
+        Pd = torch.from_numpy(P).to(dtype=torch.float32, device=dev).contiguous()
+        cfg = phx.config_from_physics(ph, precision=phx.PHX_C64, noise=noise, seed=1234)
+        solver = phx.Solver(cfg, psi, nn, None, Pd)
+        try:
+            tune = solver.autotune(reps=10, use_cache=False)
+            solver.step(warmup)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            solver.step(steps)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            solver.set_timing(True)
+            solver.step(timed_steps)
+            torch.cuda.synchronize()
+            times = solver.kernel_times()
+        finally:
+            solver.close()
+        ks = {k: v["ms_total"] / v["launches"] * 1e3 for k, v in times.items()}
+        r = {"tile": [tune["tile_wx"], tune["tile_rows"]], "UPs": n * n * steps / wall,
+             "us_per_step": wall / steps * 1e6, "kernels_us": ks}
+        if "wiener_noise" in ks:
+            r["noise_algorithmic_GBps"] = bytemodel.wiener_noise(4, True) * n * n / (ks["wiener_noise"] * 1e-6) / 1e9
+        out[label] = r
+    return out
+
+
 def table(rows) -> str:
     out = ["| N | family | tile | steps | µs/step | G UP/s | algorithmic GB/s | mean launch µs per kernel |",
            "|---|---|---|---|---|---|---|---|"]
@@ -189,12 +229,19 @@ def table(rows) -> str:
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
-    ap.add_argument("--sizes", type=int, nargs="+", default=[128, 256, 512, 1024, 2048, 4096, 8192])
+    ap.add_argument("--sizes", type=int, nargs="*", default=[128, 256, 512, 1024, 2048, 4096, 8192])
     ap.add_argument("--families", nargs="+", default=["stage", "step"], choices=["stage", "step"])
     ap.add_argument("--out", default=None, help="write the markdown table here")
     ap.add_argument("--batch", action="store_true", help="also measure the 256-instance batched workload")
     ap.add_argument("--spinor", action="store_true", help="also measure the 4096^2 spinor workload (RK4, RK45)")
+    ap.add_argument("--noise", action="store_true", help="also measure the 4096^2 driven workload with Wiener noise")
     args = ap.parse_args()
+    if args.noise:
+        r = measure_noise()
+        print(json.dumps({"noise": r}), flush=True)
+        if args.out:
+            with open(args.out + ".noise.json", "w") as f:
+                json.dump(r, f, indent=1)
     if args.spinor:
         r = measure_spinor()
         print(json.dumps({"spinor": r}), flush=True)

@@ -40,7 +40,7 @@ def _c_layout():
 #define F(T, m) printf(#T "." #m " %zu\n", offsetof(T, m));
 int main(void) {
   printf("phx_config %zu\n", sizeof(phx_config)); F(phx_config, dx) F(phx_config, bc_x) F(phx_config, hbar)
-  F(phx_config, delta_lt) F(phx_config, dt) F(phx_config, dt_max) F(phx_config, kernel) F(phx_config, tile_rows) F(phx_config, graph_steps)
+  F(phx_config, delta_lt) F(phx_config, dt) F(phx_config, dt_max) F(phx_config, kernel) F(phx_config, tile_rows) F(phx_config, graph_steps) F(phx_config, noise) F(phx_config, seed)
   printf("phx_fields %zu\n", sizeof(phx_fields)); F(phx_fields, workspace_bytes)
   printf("phx_obs %zu\n", sizeof(phx_obs)); F(phx_obs, energy) F(phx_obs, max_density) F(phx_obs, nonfinite)
   printf("phx_info %zu\n", sizeof(phx_info)); F(phx_info, steps_rejected) F(phx_info, nonfinite)
@@ -102,7 +102,7 @@ def test_workspace_bytes_scale_with_precision_and_reservoir():
     ("nx", 0), ("ny", -3), ("dx", 0.0), ("dy", float("nan")), ("bc_x", 2), ("components", 3),
     ("reservoir", 2), ("precision", 5), ("integrator", 9), ("hbar", 0.0), ("mass", -1.0),
     ("g", float("inf")), ("dt", 0.0), ("dt", 1.0), ("kernel", 7),
-    ("tile_wx", 3), ("tile_rows", 5), ("tile_rows", 65),
+    ("tile_wx", 3), ("tile_rows", 5), ("tile_rows", 65), ("noise", -1.0), ("noise", float("nan")),
 ])
 def test_invalid_config_rejected(field, value):
     cfg = good_config()
@@ -111,6 +111,18 @@ def test_invalid_config_rejected(field, value):
         phx.phx_workspace_bytes(cfg)
     assert e.value.status == phx.PHX_EINVAL
     assert phx.phx_last_error()
+
+
+def test_noise_config_validation():
+    """Wiener noise: RK4 only; it adds one 256-byte slot (the step index) to the
+    workspace; the seed takes all 64 bits."""
+    base = phx.phx_workspace_bytes(good_config())
+    assert phx.phx_workspace_bytes(good_config(noise=1.0, seed=2 ** 64 - 1)) == base + 256
+    assert phx.phx_workspace_bytes(good_config(noise=1.0, kernel=phx.PHX_KERNEL_STAGE)) == \
+        phx.phx_workspace_bytes(good_config(kernel=phx.PHX_KERNEL_STAGE)) + 256
+    with pytest.raises(phx.PhxError) as e:
+        phx.phx_workspace_bytes(good_config(noise=1.0, integrator=phx.PHX_RK45))
+    assert e.value.status == phx.PHX_EUNSUPPORTED
 
 
 def test_rk45_tolerance_validation():

@@ -1,0 +1,163 @@
+"""GPU parity of the stochastic RK4 path (complex Wiener noise of Sec. 5, truncated
+Wigner) against the oracle, through the C-ABI.
+
+The increments are a deterministic function of (cell, component, step, seed), so
+the HIP run and the oracle draw the same numbers and are compared element by
+element like the deterministic path: relative L2 1e-12 (complex128), 1e-5
+(complex64).  Cases: both kernel families, the graph-replay and direct launch
+paths, odd and even step counts, both boundary rules, reservoir and spinor forms;
+restart through phx_set_info continues the sequence bitwise; and at the size the
+benchmark uses (driven 4096^2, complex64) the increment of sampled cells, including
+the last ones, equals the oracle's Gaussian pair times the amplitude.
+"""
+import numpy as np
+import pytest
+
+from paper_2411_18341_amd import inputs, phx
+from gpu_helpers import C64, C128, TOL, GpuRun, oracle_physics, quantize, rel_l2
+
+import oracle
+from test_gpu_rk4 import workload
+
+pytestmark = pytest.mark.gpu
+
+FAMILIES = [phx.PHX_KERNEL_STAGE, phx.PHX_KERNEL_AUTO]  # AUTO: the whole-step kernel where it applies
+
+
+def run_both(kind, nx, ny, bc, precision, steps, nu, seed, **cfg_kw):
+    ph, psi, n, V, P = workload(kind, nx, ny, bc, seed=3)
+    q = quantize(precision, psi, n, V, P)
+    run = GpuRun(ph, *q, precision=precision, noise=nu, seed=seed, **cfg_kw)
+    run.step(steps)
+    g_psi, g_n = run.state()
+    info = run.solver.info()
+    run.close()
+    o_psi, o_n = oracle.rk4_noise(oracle_physics(ph), q[0], q[1], q[2], q[3], dt=ph.dt, steps=steps,
+                                  nu=nu, seed=seed, step0=0)
+    assert info["steps_accepted"] == steps
+    e_psi = rel_l2(g_psi, o_psi)
+    e_n = rel_l2(g_n, o_n) if ph.reservoir else 0.0
+    # the noise is a visible part of the result: the deterministic run differs
+    d_psi, _ = oracle.rk4(oracle_physics(ph), *q, dt=ph.dt, steps=steps)
+    assert rel_l2(d_psi, o_psi) > 100 * TOL[precision]
+    return e_psi, e_n
+
+
+@pytest.mark.parametrize("family", FAMILIES)
+@pytest.mark.parametrize("precision", [C64, C128])
+@pytest.mark.parametrize("kind,bc", [("driven", (0, 0)), ("driven_v", (1, 0)), ("spinor_res", (0, 1)),
+                                     ("spinor_res", (1, 1))])
+def test_noise_parity(kind, bc, precision, family):
+    e_psi, e_n = run_both(kind, 97, 61, bc, precision, 7, 1.0, seed=0x1234_5678_9ABC, kernel=family,
+                          graph_steps=2)
+    print(f"{kind} bc={bc} family={family}: psi {e_psi:.3e} n {e_n:.3e}")
+    assert e_psi <= TOL[precision] and e_n <= TOL[precision]
+
+
+@pytest.mark.parametrize("family", FAMILIES)
+@pytest.mark.parametrize("graph_steps", [-1, 4])
+@pytest.mark.parametrize("steps", [1, 2, 9])
+def test_noise_launch_paths(steps, graph_steps, family):
+    """Direct launches and graph replays draw the same step indices."""
+    e_psi, e_n = run_both("driven", 120, 75, (1, 1), C128, steps, 0.5, seed=99, kernel=family,
+                          graph_steps=graph_steps)
+    assert e_psi <= TOL[C128] and e_n <= TOL[C128]
+
+
+@pytest.mark.parametrize("family", FAMILIES)
+def test_noise_restart_bitwise(family):
+    """Stopping, restoring the state and phx_info, and going on continues the noise
+    sequence: the same result as one uninterrupted run."""
+    ph, psi, n, V, P = workload("driven_v", 150, 90, (0, 0), seed=8)
+    kw = dict(precision=C128, kernel=family, noise=1.0, seed=5)
+    a = GpuRun(ph, psi, n, V, P, **kw)
+    a.step(12)
+    ref = a.state()
+    a.close()
+    b = GpuRun(ph, psi, n, V, P, **kw)
+    b.step(5)
+    mid = b.state()
+    info = b.solver.info()
+    b.step(3)  # steps that the restore below discards
+    b.torch.cuda.synchronize()
+    b.psi.copy_(b.torch.from_numpy(mid[0]).to(b.psi.device, b.psi.dtype))
+    b.n.copy_(b.torch.from_numpy(mid[1]).to(b.n.device, b.n.dtype))
+    b.solver.set_info(t=info["t"], steps_accepted=info["steps_accepted"])
+    b.step(7)
+    out = b.state()
+    b.close()
+    assert np.array_equal(out[0], ref[0]) and np.array_equal(out[1], ref[1])
+
+
+@pytest.mark.parametrize("family", FAMILIES)
+def test_zero_amplitude_is_the_deterministic_step(family):
+    """No loss and no gain (gamma_c = R = 0): the increment has amplitude 0 and the
+    noisy run equals the deterministic one bitwise."""
+    ph, psi, n, V, P = workload("spinor", 70, 50, (0, 1), seed=2)
+    outs = []
+    for nu in (0.0, 1.0):
+        r = GpuRun(ph, psi, n, V, P, precision=C64, kernel=family, noise=nu, seed=3)
+        r.step(5)
+        outs.append(r.state()[0])
+        r.close()
+    assert np.array_equal(outs[0], outs[1])
+
+
+def test_noise_seeds_differ_and_repeat():
+    ph, psi, n, V, P = workload("driven", 64, 64, (0, 0), seed=1)
+    outs = []
+    for seed in (7, 7, 8):
+        r = GpuRun(ph, psi, n, V, P, precision=C64, noise=1.0, seed=seed)
+        r.step(3)
+        outs.append(r.state()[0])
+        r.close()
+    assert np.array_equal(outs[0], outs[1])
+    assert not np.array_equal(outs[0], outs[2])
+
+
+def test_noise_rejected_where_not_implemented():
+    ph, psi, n, V, P = workload("driven", 32, 32, (0, 0))
+    with pytest.raises(phx.PhxError) as e:
+        GpuRun(ph, psi, n, V, P, precision=C64, noise=1.0, integrator=phx.PHX_RK45)
+    assert e.value.status == phx.PHX_EUNSUPPORTED
+
+
+def test_noise_4096_increment_sampled():
+    """At the benchmark's size and launch configuration: one noisy step minus one
+    deterministic step from the same state is the increment; at sampled cells
+    (random ones, the first and the last of the grid) it equals
+    sqrt(nu (R n' + gamma_c) dt / (4 dV)) (xi1 + i xi2), with n' the reservoir after the step
+    and (xi1, xi2) the oracle's pair for that cell and step."""
+    ph, psi, n0, P = inputs.driven(4096)
+    q = quantize(C64, psi, n0, None, P)
+    nu, seed = 0.8, 2024
+    noisy = GpuRun(ph, *q, precision=C64, noise=nu, seed=seed)
+    noisy.solver.set_info(t=0.0, steps_accepted=3_000_000_000)  # step index above 2^31
+    noisy.step(1)
+    g_noisy, g_n = noisy.state()
+    noisy.close()
+    det = GpuRun(ph, *q, precision=C64)
+    det.step(1)
+    g_det, g_n_det = det.state()
+    det.close()
+    assert np.array_equal(g_n, g_n_det)
+    inc = (g_noisy - g_det)[0].ravel()
+    N = 4096 * 4096
+    rng = np.random.default_rng(4)
+    cells = np.concatenate([rng.integers(0, N, 2000), [0, 1, 4095, 4096, N - 2, N - 1]])
+    scale = nu * ph.dt / (4 * ph.dx * ph.dy)
+    want = []
+    for c in cells:
+        x1, x2 = oracle.gauss_pair(int(c), 0, 3_000_000_000, seed)
+        amp = np.sqrt(scale * (ph.R * float(g_n[0].ravel()[c]) + ph.gamma_c))
+        want.append(amp * (x1 + 1j * x2))
+    want = np.array(want)
+    got = inc[cells]
+    # the difference of two complex64 states carries their rounding (|psi| ulp)
+    ulp = np.abs(np.maximum(np.abs(g_noisy[0].ravel()[cells]), np.abs(g_det[0].ravel()[cells]))) * 2.0 ** -23
+    err = np.abs(got - want)
+    assert np.all(err <= 4 * ulp + 1e-5 * np.abs(want)), np.max(err / (ulp + 1e-30))
+    # the increment's variance over the whole grid follows the amplitude
+    var = np.mean(np.abs(inc) ** 2)
+    exp_var = np.mean(2 * scale * (ph.R * g_n[0].ravel().astype(np.float64) + ph.gamma_c))
+    assert var == pytest.approx(exp_var, rel=0.01)

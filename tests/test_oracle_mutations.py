@@ -37,17 +37,45 @@ MUTATIONS = {
     "energy_int_half": ("o->e_int = 0.5 * p->g * dA * s_int;", "o->e_int = p->g * dA * s_int;"),
 }
 
+# Mistakes in the stochastic part, checked by the noise pins.
+NOISE_MUTATIONS = {
+    "philox_multiplier": ("M1 = 0xCD9E8D57u", "M1 = 0xCD9E8D59u"),
+    "philox_weyl": ("W1 = 0xBB67AE85u", "W1 = 0xBB67AE87u"),
+    "philox_rounds": ("round < 10; ++round", "round < 7; ++round"),
+    "philox_word_order": ("n0 = hi1 ^ c1 ^ k0, n1 = lo1, n2 = hi0 ^ c3 ^ k1, n3 = lo0",
+                          "n0 = hi0 ^ c1 ^ k0, n1 = lo0, n2 = hi1 ^ c3 ^ k1, n3 = lo1"),
+    "counter_component_cell_swapped": ("ctr[4] = {q, s,", "ctr[4] = {s, q,"),
+    "box_muller_radius": ("sqrt(-2.0 * log(u1))", "sqrt(-log(u1))"),
+    "box_muller_same_angle": ("out[1] = r * sin(two_pi * u2);", "out[1] = r * cos(two_pi * u2);"),
+    "noise_cell_area": ("nu * (p->R * nn + p->gamma_c) * dt / (4.0 * dV)", "nu * (p->R * nn + p->gamma_c) * dt / (4.0)"),
+    "noise_half": ("* dt / (4.0 * dV);", "* dt / (2.0 * dV);"),
+    "noise_gain_dropped": ("nu * (p->R * nn + p->gamma_c)", "nu * (p->gamma_c)"),
+    "noise_real_only": ("(xi[0] + I * xi[1])", "(xi[0] + I * xi[0])"),
+    "noise_step_index": ("orc_noise(p, psi, n, dt, nu, seed, step0 + k);", "orc_noise(p, psi, n, dt, nu, seed, step0);"),
+}
 
-@pytest.mark.parametrize("name", sorted(MUTATIONS))
-def test_pins_reject_planted_mistake(name, tmp_path):
-    old, new = MUTATIONS[name]
+
+def _run_pins_on_mutant(old, new, pins, tmp_path):
     src = open(SRC).read()
-    assert src.count(old) >= 1, f"mutation anchor for {name} no longer in the oracle source"
+    assert src.count(old) >= 1, f"mutation anchor {old!r} no longer in the oracle source"
     mutated = tmp_path / "mutant.c"
     mutated.write_text(src.replace(old, new, 1))
     lib = oracle.compile_library(str(mutated), str(tmp_path / "libmutant.so"))
     env = dict(os.environ, PHX_ORACLE_LIB=lib, OMP_NUM_THREADS="2")
-    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
-                        os.path.join(ROOT, "tests", "test_oracle_pins.py")],
-                       cwd=ROOT, env=env, capture_output=True, text=True, timeout=300)
+    return subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                           os.path.join(ROOT, "tests", pins)],
+                          cwd=ROOT, env=env, capture_output=True, text=True, timeout=300)
+
+
+@pytest.mark.parametrize("name", sorted(NOISE_MUTATIONS))
+def test_noise_pins_reject_planted_mistake(name, tmp_path):
+    old, new = NOISE_MUTATIONS[name]
+    r = _run_pins_on_mutant(old, new, "test_oracle_noise_pins.py", tmp_path)
+    assert r.returncode != 0, f"noise pins passed with planted mistake {name}:\n{r.stdout[-2000:]}"
+
+
+@pytest.mark.parametrize("name", sorted(MUTATIONS))
+def test_pins_reject_planted_mistake(name, tmp_path):
+    old, new = MUTATIONS[name]
+    r = _run_pins_on_mutant(old, new, "test_oracle_pins.py", tmp_path)
     assert r.returncode != 0, f"pins passed with planted mistake {name}:\n{r.stdout[-2000:]}"
