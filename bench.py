@@ -64,13 +64,16 @@ def copy_bandwidth_gbps(torch, nbytes=COPY_BYTES, reps=20):
     return 2.0 * nbytes * reps / dt / 1e9
 
 
-def cpu_baseline(ph, psi, n0, P, steps: int) -> dict:
+def cpu_baseline(ph, psi, n0, P, steps: int, noise: float = 0.0) -> dict:
     import oracle
     op = oracle.Physics(**{k: getattr(ph, k) for k in (
         "nx", "ny", "dx", "dy", "bc_x", "bc_y", "components", "reservoir", "hbar", "mass", "g",
         "g_x", "g_r", "R", "gamma_c", "gamma_r", "delta_lt")})
     t0 = time.perf_counter()
-    oracle.rk4(op, psi, n0, None, P, dt=ph.dt, steps=steps)
+    if noise > 0:
+        oracle.rk4_noise(op, psi, n0, None, P, dt=ph.dt, steps=steps, nu=noise, seed=1)
+    else:
+        oracle.rk4(op, psi, n0, None, P, dt=ph.dt, steps=steps)
     dt = time.perf_counter() - t0
     return {"value": ph.nx * ph.ny * steps / dt, "unit": "UP/s", "cores": oracle.num_threads(),
             "kind": "oracle",
@@ -90,6 +93,8 @@ def main():
     ap.add_argument("--kernel", choices=["auto", "stage", "step"], default="auto",
                     help="RK4 kernel family (auto: whole-step kernel)")
     ap.add_argument("--no-tune", action="store_true", help="skip the tile-shape search before timing")
+    ap.add_argument("--noise", type=float, default=0.0,
+                    help="intensity nu of the truncated-Wigner Wiener noise (0 = the deterministic workload)")
     ap.add_argument("--tile", type=int, nargs=2, metavar=("WX", "ROWS"), default=None,
                     help="force this tile shape (no search)")
     args = ap.parse_args()
@@ -114,13 +119,17 @@ def main():
     workload = (f"driven-dissipative GP + reservoir, {args.n}x{args.n}, periodic, "
                 f"{'complex64 psi + float32 n' if real_bytes == 4 else 'complex128 psi + float64 n'}, "
                 f"ring pump 2 P_th (radius 20, width 3), RK4 dt {ph.dt}")
+    # the step kernel's counter record is the deterministic workload's: the noise is a separate pass
+    step_workload = workload
+    if args.noise > 0:
+        workload += f", Wiener noise nu {args.noise}"
     cdt, rdt = phx.torch_dtypes(precision)
     dev = torch.device("cuda:0")
     psi = torch.from_numpy(psi0).to(dtype=cdt, device=dev).contiguous()
     n = torch.from_numpy(n0).to(dtype=rdt, device=dev).contiguous()
     Pd = torch.from_numpy(P).to(dtype=rdt, device=dev).contiguous()
     family = {"auto": phx.PHX_KERNEL_AUTO, "stage": phx.PHX_KERNEL_STAGE, "step": phx.PHX_KERNEL_STEP}[args.kernel]
-    cfg = phx.config_from_physics(ph, precision=precision, kernel=family)
+    cfg = phx.config_from_physics(ph, precision=precision, kernel=family, noise=args.noise, seed=1)
     if args.tile:
         cfg.tile_wx, cfg.tile_rows = args.tile
     solver = phx.Solver(cfg, psi, n, None, Pd)
@@ -149,6 +158,7 @@ def main():
     step_model = bytemodel.rk4_whole_step(real_bytes, reservoir=True, has_v=False)
     per_launch = {f"rk4_stage{s}": stage_model[f"stage{s}"] for s in range(1, 5)}
     per_launch["rk4_step"] = step_model["step"]
+    per_launch["wiener_noise"] = bytemodel.wiener_noise(real_bytes, reservoir=True)
     kernels = {}
     for name, t in times.items():
         if name not in per_launch:
@@ -161,25 +171,27 @@ def main():
     d = kernels[dom]
     # counter measurements of the whole-step kernel are kept per region shape
     shape_key = dom if dom != "rk4_step" or tune is None else f"rk4_step_{tune['tile_wx']}x{tune['tile_rows']}"
-    traffic = measured_traffic(shape_key, workload)
+    traffic = measured_traffic(shape_key, step_workload)
     roofline = {"bound": "hbm", "achieved": round(d["GBps"], 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                 "frac": round(d["GBps"] / HBM_PEAK_GBPS, 4), "traffic": traffic,
                 "kernel": shape_key, "bytes_per_launch": d["bytes_per_launch"],
                 "avg_launch_us": round(d["avg_us"], 2)}
     family_name = "whole-step (1 launch per step)" if dom == "rk4_step" else "stage-fused (4 launches per step)"
     step_bytes = step_model["step"] if dom == "rk4_step" else stage_model["step"]
+    if args.noise > 0:
+        step_bytes += per_launch["wiener_noise"]
     step_gbps = step_bytes * cells * args.steps / wall / 1e9
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(ph, psi0, n0, P, args.cpu_steps)
+        cpu = cpu_baseline(ph, psi0, n0, P, args.cpu_steps, args.noise)
 
     line = {
         "metric": METRIC, "value": value, "unit": "UP/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32" if real_bytes == 4 else "f64",
         "data": "synthetic",
-        "config": {"workload": workload, "grid": [args.n, args.n], "integrator": "rk4",
+        "config": {"workload": workload, "grid": [args.n, args.n], "integrator": "rk4", "noise": args.noise,
                    "kernel_family": family_name,
                    "tile": None if tune is None else [tune["tile_wx"], tune["tile_rows"]]},
         "roofline": roofline,

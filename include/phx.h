@@ -122,7 +122,12 @@ typedef struct phx_fields {
  *   max_density = max rho_s
  *   steady_res_density   = ||2 Re(psi* dpsi/dt)||_2 / ||rho||_2   (d rho/dt residual)
  *   steady_res_reservoir = ||dn/dt||_2 / ||P||_2 (0 without reservoir or pump)
- *   nonfinite = number of non-finite entries in psi and n. */
+ *   nonfinite = number of non-finite entries in psi and n
+ *   norm_renorm[s] = norm[s] - nu Nx Ny / 2: the renormalized density of the truncated
+ *               Wigner form (Sec. 5) integrated over the grid, A sum (rho_s - nu/(2A)),
+ *               i.e. minus the share nu/(2A) per cell that the noise alone holds in a
+ *               lossy empty cell (half a quantum per mode); equals norm[s] without noise
+ *               (0 for an absent second component). */
 typedef struct phx_obs {
     double norm[2];
     double reservoir;
@@ -130,6 +135,7 @@ typedef struct phx_obs {
     double max_density;
     double steady_res_density, steady_res_reservoir;
     int64_t nonfinite;
+    double norm_renorm[2];
 } phx_obs;
 
 /* Integrator progress of a handle. */

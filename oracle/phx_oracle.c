@@ -448,20 +448,22 @@ void orc_philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
     out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
 }
 
-/* Two standard normal numbers for (cell q of component s, step) and a 64-bit seed:
- * Philox4x32-10 of the counter (q, s, step low word, step high word) with the key
- * (seed low word, seed high word); its first two words x0, x1 give the uniforms
- * u = (x + 1/2) 2^-32 in (0, 1), and the Box-Muller transform (Box & Muller, Ann.
- * Math. Statist. 29 (1958) 610) gives r cos(2 pi u2), r sin(2 pi u2) with
- * r = sqrt(-2 ln u1). */
+/* Two standard normal numbers for (cell q of component s, step) and a 64-bit seed.
+ * One Philox4x32-10 call serves the two cells 2p and 2p + 1: the counter is
+ * (p = q / 2, s, step low word, step high word), the key (seed low word, seed high
+ * word); cell 2p takes output words (x0, x1), cell 2p + 1 words (x2, x3).  The two
+ * words become uniforms u = (x + 1/2) 2^-32 in (0, 1), and the Box-Muller transform
+ * (Box & Muller, Ann. Math. Statist. 29 (1958) 610) gives r cos(2 pi u2),
+ * r sin(2 pi u2) with r = sqrt(-2 ln u1). */
 void orc_gauss_pair(uint32_t q, uint32_t s, int64_t step, uint64_t seed, double out[2])
 {
-    const uint32_t ctr[4] = {q, s, (uint32_t)(uint64_t)step, (uint32_t)((uint64_t)step >> 32)};
+    const uint32_t ctr[4] = {q >> 1, s, (uint32_t)(uint64_t)step, (uint32_t)((uint64_t)step >> 32)};
     const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
     uint32_t x[4];
     orc_philox(ctr, key, x);
-    const double u1 = ((double)x[0] + 0.5) / 4294967296.0;
-    const double u2 = ((double)x[1] + 0.5) / 4294967296.0;
+    const uint32_t *w = x + 2 * (q & 1);
+    const double u1 = ((double)w[0] + 0.5) / 4294967296.0;
+    const double u2 = ((double)w[1] + 0.5) / 4294967296.0;
     const double r = sqrt(-2.0 * log(u1));
     const double two_pi = 6.283185307179586476925286766559;
     out[0] = r * cos(two_pi * u2);
@@ -478,6 +480,7 @@ void orc_noise(const orc_params *p, cplx *psi, const double *n, double dt, doubl
     const size_t N = cells(p);
     const double dV = p->dx * p->dy;
     for (int s = 0; s < p->components; ++s) {
+#pragma omp parallel for schedule(static) if (N >= 16384)
         for (size_t q = 0; q < N; ++q) {
             const double nn = p->reservoir ? n[(size_t)s * N + q] : 0.0;
             const double var = nu * (p->R * nn + p->gamma_c) * dt / (4.0 * dV);

@@ -559,6 +559,8 @@ phx_status phx_observables(phx_handle* h, phx_obs* out)
     out->steady_res_density = q[O_RHO2] > 0 ? sqrt(q[O_DRHO2]) / sqrt(q[O_RHO2]) : 0.0;
     out->steady_res_reservoir = (c.reservoir && q[O_P2] > 0) ? sqrt(q[O_FN2]) / sqrt(q[O_P2]) : 0.0;
     out->nonfinite = (int64_t)q[O_NONFINITE];
+    const double vacuum = 0.5 * c.noise * (double)c.nx * (double)c.ny;  // nu/(2A) per cell, times A
+    for (int s = 0; s < c.components; ++s) out->norm_renorm[s] = out->norm[s] - vacuum;
     poll_flag(h);
     return PHX_OK;
 }

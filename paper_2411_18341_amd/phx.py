@@ -58,11 +58,12 @@ class phx_obs(ctypes.Structure):
                 ("e_int", ctypes.c_double), ("e_cross", ctypes.c_double), ("e_tetm", ctypes.c_double),
                 ("e_res", ctypes.c_double), ("max_density", ctypes.c_double),
                 ("steady_res_density", ctypes.c_double), ("steady_res_reservoir", ctypes.c_double),
-                ("nonfinite", ctypes.c_int64)]
+                ("nonfinite", ctypes.c_int64), ("norm_renorm", ctypes.c_double * 2)]
 
     def as_dict(self):
-        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "norm"}
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k not in ("norm", "norm_renorm")}
         d["norm"] = (self.norm[0], self.norm[1])
+        d["norm_renorm"] = (self.norm_renorm[0], self.norm_renorm[1])
         return d
 
 

@@ -7,10 +7,11 @@ into HBM bytes per launch for each kernel, scaled by what the same counters read
 for a plain device copy of known size that ran in the same process.
 
     python -m paper_2411_18341_amd.profiling stats <kernel_stats.csv> <command...>
-    python -m paper_2411_18341_amd.profiling traffic <fetch.csv> <write.csv> <copy_bytes> <out.json> <workload>
+    python -m paper_2411_18341_amd.profiling traffic <fetch.csv> <write.csv> <copy_bytes> <out.json> <workload> [sources...]
 
 (`traffic` adds its kernels to <out.json> when that file holds a measurement of the
-same kernel sources and workload, else replaces it.)
+same kernel sources and workload, else replaces it; the sources default to the RK4
+kernels' files.)
 """
 from __future__ import annotations
 
@@ -30,9 +31,11 @@ KERNEL_SOURCES = ["paper_2411_18341_amd/csrc/rk4.hip", "paper_2411_18341_amd/csr
                   "paper_2411_18341_amd/csrc/step_body.h", "paper_2411_18341_amd/csrc/stream_body.h"]
 
 
-def kernel_source_hash() -> str:
+def kernel_source_hash(sources=None) -> str:
+    """Hash of the kernel sources a counter record was taken on (default: the RK4
+    kernels' sources)."""
     h = hashlib.sha256()
-    for p in KERNEL_SOURCES:
+    for p in (KERNEL_SOURCES if sources is None else sources):
         path = os.path.join(ROOT, p)
         if os.path.exists(path):
             with open(path, "rb") as f:
@@ -56,7 +59,8 @@ def kernel_kind(name: str) -> str:
         return f"rk4_step_1x{m.group(1)}"
     named = {"rk4_step_kernel": "rk4_step", "batch_step_kernel": "batch_step", "dp_restart_kernel": "dp_restart",
              "dp_err_sum_kernel": "dp_error", "obs_pass1": "obs_pass1", "obs_pass2": "obs_pass2",
-             "conv_fwd_kernel": "conv_fwd", "conv_bwd_weight_kernel": "conv_bwd_weight"}
+             "conv_fwd_kernel": "conv_fwd", "conv_bwd_weight_kernel": "conv_bwd_weight",
+             "wiener_noise_kernel": "wiener_noise"}
     for k, v in named.items():
         if k in name:
             return v
@@ -96,7 +100,7 @@ def read_counter(path: str, counter: str):
     return {k: list(v.values()) for k, v in per.items()}
 
 
-def traffic_summary(fetch_csv: str, write_csv: str, copy_bytes: float, workload: str):
+def traffic_summary(fetch_csv: str, write_csv: str, copy_bytes: float, workload: str, sources=None):
     """Bytes per launch (read, write, total) per kernel, each counter scaled by
     copy_bytes over the counter's mean reading for the copy kernel (a copy reads
     and writes copy_bytes each)."""
@@ -123,7 +127,7 @@ def traffic_summary(fetch_csv: str, write_csv: str, copy_bytes: float, workload:
         kernels[kernel_kind(k)] = {"read_bytes": rd, "write_bytes": wb, "bytes_per_launch": rd + wb,
                                    "dispatches": len(fr), "fetch_kib_raw": sum(fr) / len(fr),
                                    "write_kib_raw": sum(wr) / len(wr)}
-    return {"workload": workload, "source_hash": kernel_source_hash(), "fetch_scale": f_scale,
+    return {"workload": workload, "source_hash": kernel_source_hash(sources), "fetch_scale": f_scale,
             "write_scale": w_scale, "copy_bytes": copy_bytes, "kernels": kernels}
 
 
@@ -132,7 +136,7 @@ def main(argv):
         sys.stdout.write(stats_summary(argv[1], " ".join(argv[2:])))
     elif argv[0] == "traffic":
         # merges into an existing file taken on the same sources and workload
-        t = traffic_summary(argv[1], argv[2], float(argv[3]), argv[5])
+        t = traffic_summary(argv[1], argv[2], float(argv[3]), argv[5], argv[6:] or None)
         if os.path.exists(argv[4]):
             with open(argv[4]) as f:
                 old = json.load(f)

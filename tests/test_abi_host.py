@@ -42,7 +42,7 @@ int main(void) {
   printf("phx_config %zu\n", sizeof(phx_config)); F(phx_config, dx) F(phx_config, bc_x) F(phx_config, hbar)
   F(phx_config, delta_lt) F(phx_config, dt) F(phx_config, dt_max) F(phx_config, kernel) F(phx_config, tile_rows) F(phx_config, graph_steps) F(phx_config, noise) F(phx_config, seed)
   printf("phx_fields %zu\n", sizeof(phx_fields)); F(phx_fields, workspace_bytes)
-  printf("phx_obs %zu\n", sizeof(phx_obs)); F(phx_obs, energy) F(phx_obs, max_density) F(phx_obs, nonfinite)
+  printf("phx_obs %zu\n", sizeof(phx_obs)); F(phx_obs, energy) F(phx_obs, max_density) F(phx_obs, nonfinite) F(phx_obs, norm_renorm)
   printf("phx_info %zu\n", sizeof(phx_info)); F(phx_info, steps_rejected) F(phx_info, nonfinite)
   printf("phx_timing %zu\n", sizeof(phx_timing)); F(phx_timing, launches) F(phx_timing, ms_total)
   printf("phx_tune_result %zu\n", sizeof(phx_tune_result)); F(phx_tune_result, best_us) F(phx_tune_result, default_us)

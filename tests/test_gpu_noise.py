@@ -161,3 +161,40 @@ def test_noise_4096_increment_sampled():
     var = np.mean(np.abs(inc) ** 2)
     exp_var = np.mean(2 * scale * (ph.R * g_n[0].ravel().astype(np.float64) + ph.gamma_c))
     assert var == pytest.approx(exp_var, rel=0.01)
+
+
+RK4_POLY = [1.0, 1.0, 1.0 / 2, 1.0 / 6, 1.0 / 24]
+
+
+@pytest.mark.parametrize("family", FAMILIES)
+def test_vacuum_occupation_and_renormalized_density(family):
+    """A lossy linear field (g = R = 0, constant V) driven by the noise from psi = 0 on a
+    512^2 periodic grid.  Plane waves are orthonormal eigenmodes of the stencil and keep
+    the per-cell white noise white, so after m steps the mean of |psi|^2 is exactly
+    mean_k D (1 - |lambda_k|^(2m)) / (1 - |lambda_k|^2), D = nu gamma dt / (2 dV) and
+    lambda_k the RK4 amplification of mode k (a property at any size; 262144 modes make
+    its statistical error 0.2 %).  For m gamma dt >> 1 that is nu / (2 dV) per cell up to
+    O(gamma dt), so the renormalized norm, norm - nu Nx Ny / 2, goes to ~0."""
+    n, d, gam, nu, dt, V0 = 512, 0.5, 1.0, 1.0, 0.01, 0.4
+    ph = inputs.Physics(nx=n, ny=n, dx=d, dy=d, gamma_c=gam, dt=dt)
+    psi = np.zeros((1, n, n), np.complex128)
+    V = np.full((n, n), V0)
+    run = GpuRun(ph, psi, None, V, None, precision=C64, kernel=family, noise=nu, seed=77)
+    m_grid = np.arange(n)
+    kap1 = 4.0 / d ** 2 * np.sin(np.pi * m_grid / n) ** 2
+    kap = kap1[None, :] + kap1[:, None]
+    z = dt * (-1j * (0.5 * kap + V0) - gam / 2)
+    lam2 = np.abs(sum(c * z ** j for j, c in enumerate(RK4_POLY))) ** 2
+    D = nu * gam * dt / (2 * d * d)
+    done = 0
+    for m in (200, 400, 600, 800):
+        run.step(m - done)
+        done = m
+        obs = run.observables()
+        got = obs["norm"][0] / (n * n * d * d)
+        want = np.mean(D * (1 - lam2 ** m) / (1 - lam2))
+        print(f"m={m}: mean |psi|^2 {got:.6f}, exact {want:.6f}")
+        assert got == pytest.approx(want, rel=0.012)
+        assert obs["norm_renorm"][0] == pytest.approx(obs["norm"][0] - nu * n * n / 2, rel=1e-12)
+    assert abs(obs["norm_renorm"][0]) < 0.02 * nu * n * n / 2
+    run.close()

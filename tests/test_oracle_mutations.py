@@ -44,7 +44,9 @@ NOISE_MUTATIONS = {
     "philox_rounds": ("round < 10; ++round", "round < 7; ++round"),
     "philox_word_order": ("n0 = hi1 ^ c1 ^ k0, n1 = lo1, n2 = hi0 ^ c3 ^ k1, n3 = lo0",
                           "n0 = hi0 ^ c1 ^ k0, n1 = lo0, n2 = hi1 ^ c3 ^ k1, n3 = lo1"),
-    "counter_component_cell_swapped": ("ctr[4] = {q, s,", "ctr[4] = {s, q,"),
+    "counter_component_cell_swapped": ("ctr[4] = {q >> 1, s,", "ctr[4] = {s, q >> 1,"),
+    "pair_shares_words": ("const uint32_t *w = x + 2 * (q & 1);", "const uint32_t *w = x;"),
+    "pair_index_not_halved": ("ctr[4] = {q >> 1, s,", "ctr[4] = {q, s,"),
     "box_muller_radius": ("sqrt(-2.0 * log(u1))", "sqrt(-log(u1))"),
     "box_muller_same_angle": ("out[1] = r * sin(two_pi * u2);", "out[1] = r * cos(two_pi * u2);"),
     "noise_cell_area": ("nu * (p->R * nn + p->gamma_c) * dt / (4.0 * dV)", "nu * (p->R * nn + p->gamma_c) * dt / (4.0)"),

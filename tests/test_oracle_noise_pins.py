@@ -34,16 +34,18 @@ def test_philox_known_answers(ctr, key, out):
     assert oracle.philox(ctr, key) == out
 
 
-def test_gauss_pair_counter_layout():
-    """Cell index, component, step (low, high word) form the counter and the seed
-    (low, high word) the key: the third known-answer vector read that way gives the
-    uniforms (x + 1/2) 2^-32 of its first two output words, and Box-Muller of them."""
+@pytest.mark.parametrize("odd", [0, 1])
+def test_gauss_pair_counter_layout(odd):
+    """Cell pair index q // 2, component, step (low, high word) form the counter and
+    the seed (low, high word) the key; the even cell of the pair takes output words
+    0 and 1, the odd cell words 2 and 3.  The third known-answer vector read that way
+    gives the uniforms (x + 1/2) 2^-32 of those words, and Box-Muller of them."""
     ctr, key, out = PHILOX_KAT[2]
     step = ctr[2] | (ctr[3] << 32)
     seed = key[0] | (key[1] << 32)
-    g = oracle.gauss_pair(ctr[0], ctr[1], step, seed)
-    u1 = (out[0] + 0.5) / 2.0 ** 32
-    u2 = (out[1] + 0.5) / 2.0 ** 32
+    g = oracle.gauss_pair(2 * ctr[0] + odd, ctr[1], step, seed)
+    u1 = (out[2 * odd] + 0.5) / 2.0 ** 32
+    u2 = (out[2 * odd + 1] + 0.5) / 2.0 ** 32
     r = math.sqrt(-2.0 * math.log(u1))
     assert g[0] == pytest.approx(r * math.cos(2 * math.pi * u2), rel=1e-14, abs=1e-15)
     assert g[1] == pytest.approx(r * math.sin(2 * math.pi * u2), rel=1e-14, abs=1e-15)
