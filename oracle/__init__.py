@@ -65,6 +65,7 @@ class _Params(ctypes.Structure):
         ("g", ctypes.c_double), ("g_x", ctypes.c_double), ("g_r", ctypes.c_double),
         ("R", ctypes.c_double), ("gamma_c", ctypes.c_double), ("gamma_r", ctypes.c_double),
         ("delta_lt", ctypes.c_double),
+        ("E", ctypes.c_void_p), ("omega", ctypes.c_double), ("t0", ctypes.c_double),
     ]
 
 
@@ -138,11 +139,21 @@ class Physics:
     gamma_c: float = 0.0
     gamma_r: float = 0.0
     delta_lt: float = 0.0
+    E: object = None        # coherent drive profile E_s(r), [components][ny][nx] complex, or None
+    omega: float = 0.0      # drive frequency: E_s(r, t) = E_s(r) exp(-i omega t)
+    t0: float = 0.0         # time at the start of a call
 
     def _c(self) -> _Params:
+        e = None
+        if self.E is not None:
+            e = np.ascontiguousarray(np.asarray(self.E, dtype=np.complex128)).reshape(
+                self.components, self.ny, self.nx)
+            self._e_keep = e  # the library reads it during the call
         return _Params(self.nx, self.ny, self.dx, self.dy, self.bc_x, self.bc_y, self.components,
                        int(bool(self.reservoir)), self.hbar, self.mass, self.g, self.g_x, self.g_r,
-                       self.R, self.gamma_c, self.gamma_r, self.delta_lt)
+                       self.R, self.gamma_c, self.gamma_r, self.delta_lt,
+                       None if e is None else e.ctypes.data_as(ctypes.c_void_p), float(self.omega),
+                       float(self.t0))
 
 
 def _cplx(a, shape):

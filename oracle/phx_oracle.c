@@ -22,6 +22,8 @@
  *     Wanner, Solving ODEs I, Sec. II.4.
  *   - Complex Wiener noise dW of Eq. (PULSE_psi) with the correlations of Sec. 5
  *     (truncated Wigner), drawn from Philox4x32-10 and the Box-Muller transform.
+ *   - Coherent drive E_+- of Eq. (PULSE_psi), a term -(i/hbar) E_s(r, t) in d psi_s/dt,
+ *     with E_s(r, t) = E_s(r) exp(-i omega t) evaluated at each stage's own time.
  *
  * Readings where the paper is silent (each is also listed in the design notes):
  *   - f in Eqs. (rk4_K1)-(rk4_K4) is the time derivative d psi/dt = -(i/hbar) H psi.
@@ -57,6 +59,10 @@ typedef struct {
     int32_t reservoir;  /* 0 or 1 */
     double hbar, mass;
     double g, g_x, g_r, R, gamma_c, gamma_r, delta_lt;
+    /* coherent drive E_s(r, t) = E[s][q] exp(-i omega t) (Eq. PULSE_psi); E NULL = none */
+    const cplx *E;
+    double omega;
+    double t0;          /* time at the start of the call (RK4 step k starts at t0 + k dt) */
 } orc_params;
 
 /* Observables, each a plain sum over the grid times the cell area dx*dy. */
@@ -149,6 +155,17 @@ void orc_rhs(const orc_params *p, const cplx *psi, const double *n, const double
     }
 }
 
+/* Right-hand side at time t: orc_rhs plus the coherent drive -(i/hbar) E_s(r) e^{-i omega t}. */
+static void rhs_at(const orc_params *p, const cplx *psi, const double *n, const double *V,
+                   const double *P, double t, cplx *f_psi, double *f_n)
+{
+    orc_rhs(p, psi, n, V, P, f_psi, f_n);
+    if (!p->E) return;
+    const size_t M = cells(p) * (size_t)p->components;
+    const cplx phase = cexp(-I * p->omega * t);
+    for (size_t q = 0; q < M; ++q) f_psi[q] += -(I / p->hbar) * (p->E[q] * phase);
+}
+
 /* ------------------------------------------------------------------------ RK4 */
 
 static void *xmalloc(size_t bytes)
@@ -173,16 +190,17 @@ void orc_rk4(const orc_params *p, cplx *psi, double *n, const double *V, const d
         k[s] = xmalloc(M * sizeof(cplx));
         kn[s] = xmalloc((Mn ? Mn : 1) * sizeof(double));
     }
-    const double a[4] = {0.0, 0.5, 0.5, 1.0}; /* stage argument offsets, Eqs. rk4_K2-K4 */
+    const double a[4] = {0.0, 0.5, 0.5, 1.0}; /* stage argument and time offsets, Eqs. rk4_K2-K4 */
     for (int64_t step = 0; step < n_steps; ++step) {
+        const double t = p->t0 + (double)step * dt;
         for (int s = 0; s < 4; ++s) {
             if (s == 0) {
-                orc_rhs(p, psi, n, V, P, k[0], kn[0]);
+                rhs_at(p, psi, n, V, P, t, k[0], kn[0]);
                 continue;
             }
             for (size_t q = 0; q < M; ++q) y[q] = psi[q] + a[s] * dt * k[s - 1][q];
             for (size_t q = 0; q < Mn; ++q) yn[q] = n[q] + a[s] * dt * kn[s - 1][q];
-            orc_rhs(p, y, yn, V, P, k[s], kn[s]);
+            rhs_at(p, y, yn, V, P, t + a[s] * dt, k[s], kn[s]);
         }
         for (size_t q = 0; q < M; ++q)
             psi[q] = psi[q] + (1.0 / 6.0) * (k[0][q] + 2.0 * k[1][q] + 2.0 * k[2][q] + k[3][q]) * dt;
@@ -211,10 +229,13 @@ static const double DP_B[7] = {35.0 / 384.0, 0.0, 500.0 / 1113.0, 125.0 / 192.0,
 /* embedded fourth-order weights */
 static const double DP_BHAT[7] = {5179.0 / 57600.0, 0.0, 7571.0 / 16695.0, 393.0 / 640.0,
                                   -92097.0 / 339200.0, 187.0 / 2100.0, 1.0 / 40.0};
+/* stage times (nodes) of the same tableau */
+static const double DP_C[7] = {0.0, 1.0 / 5.0, 3.0 / 10.0, 4.0 / 5.0, 8.0 / 9.0, 1.0, 1.0};
 
 /* One Dormand-Prince step of size dt from (psi, n), written to (psi_out, n_out), with
  * the embedded error e = y5 - y4 = dt sum_j (b_j - bhat_j) K_j written to (e_psi, e_n).
- * Seven stage evaluations; the seventh is f(y5).  Any output may alias nothing. */
+ * Seven stage evaluations; the seventh is f(y5); stage s is evaluated at time
+ * p->t0 + c_s dt.  Any output may alias nothing. */
 void orc_dopri5_step(const orc_params *p, const cplx *psi, const double *n, const double *V,
                      const double *P, double dt, cplx *psi_out, double *n_out, cplx *e_psi,
                      double *e_n)
@@ -239,7 +260,7 @@ void orc_dopri5_step(const orc_params *p, const cplx *psi, const double *n, cons
             for (int j = 0; j < s; ++j) acc += DP_A[s][j] * kn[j][q];
             yn[q] = n[q] + dt * acc;
         }
-        orc_rhs(p, y, yn, V, P, k[s], kn[s]);
+        rhs_at(p, y, yn, V, P, p->t0 + DP_C[s] * dt, k[s], kn[s]);
     }
     for (size_t q = 0; q < M; ++q) {
         cplx acc = 0.0, err = 0.0;
@@ -313,7 +334,9 @@ void orc_dopri5(const orc_params *p, cplx *psi, double *n, const double *V, cons
     while (done < n_accept) {
         const double dt = ctrl->dt;
         if (!(dt >= dt_min)) { ctrl->status = -5; break; }
-        orc_dopri5_step(p, psi, n, V, P, dt, y5, n5, e, en);
+        orc_params pt = *p;  /* the attempt starts at the time reached */
+        pt.t0 = ctrl->t;
+        orc_dopri5_step(&pt, psi, n, V, P, dt, y5, n5, e, en);
         const double err = orc_error_norm(p, psi, n, y5, n5, e, en, rtol, atol);
         if (hist && h < hist_cap) { hist[2 * h] = dt; hist[2 * h + 1] = err; ++h; }
         const double fmaxf = ctrl->last_rejected ? 1.0 : 5.0;
@@ -344,7 +367,8 @@ void orc_dopri5(const orc_params *p, cplx *psi, double *n, const double *V, cons
 /* Discrete observables.  The kinetic energy is the sum over all grid links of
  * (hbar^2/2m)|forward difference|^2; with a zero boundary the links to the ghost
  * cells on both sides count, so that e_kin = -(hbar^2/2m) dxdy sum Re(psi* Lap psi)
- * holds exactly (summation by parts).  e_tetm = dxdy sum 2 Re(psi_+* J_+ psi_-). */
+ * holds exactly (summation by parts).  e_tetm = dxdy sum 2 Re(psi_+* J_+ psi_-).
+ * The steady residuals use the right-hand side at time p->t0 (drive included). */
 void orc_observables(const orc_params *p, const cplx *psi, const double *n, const double *V,
                      const double *P, orc_obs *o)
 {
@@ -355,7 +379,7 @@ void orc_observables(const orc_params *p, const cplx *psi, const double *n, cons
     memset(o, 0, sizeof(*o));
     cplx *fp = xmalloc(N * C * sizeof(cplx));
     double *fn = xmalloc((p->reservoir ? N * C : 1) * sizeof(double));
-    orc_rhs(p, psi, n, V, P, fp, fn);
+    rhs_at(p, psi, n, V, P, p->t0, fp, fn);
     double s_kin = 0, s_pot = 0, s_int = 0, s_cross = 0, s_tetm = 0, s_res = 0, s_nr = 0;
     double s_drho2 = 0, s_rho2 = 0, s_fn2 = 0, s_p2 = 0;
     for (int c = 0; c < C; ++c) {
@@ -497,7 +521,9 @@ void orc_rk4_noise(const orc_params *p, cplx *psi, double *n, const double *V, c
                    int64_t n_steps, double nu, uint64_t seed, int64_t step0)
 {
     for (int64_t k = 0; k < n_steps; ++k) {
-        orc_rk4(p, psi, n, V, P, dt, 1);
+        orc_params pk = *p;  /* step k starts at t0 + k dt (drive phase) */
+        pk.t0 = p->t0 + (double)k * dt;
+        orc_rk4(&pk, psi, n, V, P, dt, 1);
         orc_noise(p, psi, n, dt, nu, seed, step0 + k);
     }
 }

@@ -57,6 +57,20 @@ NOISE_MUTATIONS = {
 }
 
 
+# Mistakes in the coherent drive, checked by the drive pins.
+DRIVE_MUTATIONS = {
+    "drive_sign": ("f_psi[q] += -(I / p->hbar) * (p->E[q] * phase);", "f_psi[q] += (I / p->hbar) * (p->E[q] * phase);"),
+    "drive_phase_sign": ("cexp(-I * p->omega * t)", "cexp(I * p->omega * t)"),
+    "drive_hbar_dropped": ("-(I / p->hbar) * (p->E[q] * phase)", "-(I) * (p->E[q] * phase)"),
+    "rk4_stage_time": ("rhs_at(p, y, yn, V, P, t + a[s] * dt, k[s], kn[s]);", "rhs_at(p, y, yn, V, P, t, k[s], kn[s]);"),
+    "rk4_step_time": ("const double t = p->t0 + (double)step * dt;", "const double t = p->t0;"),
+    "dp_node": ("3.0 / 10.0, 4.0 / 5.0, 8.0 / 9.0", "3.0 / 10.0, 4.0 / 5.0, 7.0 / 9.0"),
+    "dp_attempt_time": ("pt.t0 = ctrl->t;", "pt.t0 = p->t0;"),
+    "observables_undriven": ("rhs_at(p, psi, n, V, P, p->t0, fp, fn);", "orc_rhs(p, psi, n, V, P, fp, fn);"),
+    "noisy_loop_drive_time": ("pk.t0 = p->t0 + (double)k * dt;", "pk.t0 = p->t0;"),
+}
+
+
 def _run_pins_on_mutant(old, new, pins, tmp_path):
     src = open(SRC).read()
     assert src.count(old) >= 1, f"mutation anchor {old!r} no longer in the oracle source"
@@ -74,6 +88,13 @@ def test_noise_pins_reject_planted_mistake(name, tmp_path):
     old, new = NOISE_MUTATIONS[name]
     r = _run_pins_on_mutant(old, new, "test_oracle_noise_pins.py", tmp_path)
     assert r.returncode != 0, f"noise pins passed with planted mistake {name}:\n{r.stdout[-2000:]}"
+
+
+@pytest.mark.parametrize("name", sorted(DRIVE_MUTATIONS))
+def test_drive_pins_reject_planted_mistake(name, tmp_path):
+    old, new = DRIVE_MUTATIONS[name]
+    r = _run_pins_on_mutant(old, new, "test_oracle_drive_pins.py", tmp_path)
+    assert r.returncode != 0, f"drive pins passed with planted mistake {name}:\n{r.stdout[-2000:]}"
 
 
 @pytest.mark.parametrize("name", sorted(MUTATIONS))
