@@ -98,6 +98,15 @@ typedef struct phx_config {
                                (j nx + i, component, step low word, step high word) under the
                                key (seed low word, seed high word), u = (x + 1/2) 2^-32; the
                                step index is phx_info.steps_accepted before the step        */
+    double drive_omega;     /* frequency omega of the coherent drive                        */
+    int32_t drive;          /* 1: add the coherent drive of Eq. (PULSE_psi), the term
+                               -(i/hbar) E_s(r) exp(-i omega t) in d psi_s/dt, with the profile
+                               E_s(r) from phx_fields.E, evaluated at every stage's own time
+                               (RK4: t + {0, 1/2, 1/2, 1} dt; Dormand-Prince: its nodes c_s);
+                               t is phx_info.t (a step taken k steps after the last
+                               phx_set_info or phx_create starts at t_set + k dt).  Stage-fused
+                               RK4 and RK45 (PHX_KERNEL_AUTO picks the stage-fused family;
+                               the whole-step kernel and batches: PHX_EUNSUPPORTED).  0: none */
 } phx_config;
 
 /* Caller-owned device arrays bound to a handle (borrowed until phx_destroy). */
@@ -108,6 +117,8 @@ typedef struct phx_fields {
     const void *P;          /* [components][ny][nx] real pump (required with reservoir)  */
     void *workspace;        /* scratch of at least phx_workspace_bytes, 256-B aligned    */
     size_t workspace_bytes;
+    const void *E;          /* [components][ny][nx] complex drive profile E_s(r), read only;
+                               required with cfg.drive = 1, NULL otherwise                  */
 } phx_fields;
 
 /* Observables of the current state, all accumulated in double precision over the

@@ -106,6 +106,7 @@ def _load():
         lib.orc_dopri5.argtypes = [P(_Params), vp, vp, vp, vp, ctypes.c_double, ctypes.c_double,
                                    ctypes.c_double, ctypes.c_double, ctypes.c_int64, P(_Ctrl),
                                    vp, ctypes.c_int64]
+        lib.orc_rhs_t.argtypes = [P(_Params), vp, vp, vp, vp, vp, vp]
         lib.orc_observables.argtypes = [P(_Params), vp, vp, vp, vp, P(_Obs)]
         u32p = P(ctypes.c_uint32)
         lib.orc_philox.argtypes = [u32p, u32p, u32p]
@@ -184,7 +185,8 @@ def _shapes(ph: Physics):
 
 
 def rhs(ph: Physics, psi, n=None, V=None, P=None):
-    """Time derivative (f_psi, f_n) of the coupled state at every cell."""
+    """Time derivative (f_psi, f_n) of the coupled state at every cell (with the
+    drive, when set, at time ph.t0)."""
     lib = _load()
     sp, sn, sv = _shapes(ph)
     psi = _cplx(psi, sp)
@@ -193,7 +195,7 @@ def rhs(ph: Physics, psi, n=None, V=None, P=None):
     V = _real(V, sv, False)
     fp = np.zeros(sp, np.complex128)
     fn = np.zeros(sn, np.float64) if ph.reservoir else None
-    lib.orc_rhs(ctypes.byref(ph._c()), _ptr(psi), _ptr(n), _ptr(V), _ptr(P), _ptr(fp), _ptr(fn))
+    lib.orc_rhs_t(ctypes.byref(ph._c()), _ptr(psi), _ptr(n), _ptr(V), _ptr(P), _ptr(fp), _ptr(fn))
     return fp, fn
 
 

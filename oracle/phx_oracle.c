@@ -166,6 +166,13 @@ static void rhs_at(const orc_params *p, const cplx *psi, const double *n, const 
     for (size_t q = 0; q < M; ++q) f_psi[q] += -(I / p->hbar) * (p->E[q] * phase);
 }
 
+/* Right-hand side at time p->t0 (the drive's phase); orc_rhs without a drive. */
+void orc_rhs_t(const orc_params *p, const cplx *psi, const double *n, const double *V,
+               const double *P, cplx *f_psi, double *f_n)
+{
+    rhs_at(p, psi, n, V, P, p->t0, f_psi, f_n);
+}
+
 /* ------------------------------------------------------------------------ RK4 */
 
 static void *xmalloc(size_t bytes)

@@ -35,6 +35,8 @@ static const double DP_B[7] = {35.0 / 384.0, 0.0, 500.0 / 1113.0, 125.0 / 192.0,
                                -2187.0 / 6784.0, 11.0 / 84.0, 0.0};
 static const double DP_BHAT[7] = {5179.0 / 57600.0, 0.0, 7571.0 / 16695.0, 393.0 / 640.0,
                                   -92097.0 / 339200.0, 187.0 / 2100.0, 1.0 / 40.0};
+// nodes: stage s is evaluated at t + c_s dt (the coherent drive's phase)
+static const double DP_C[7] = {0.0, 1.0 / 5.0, 3.0 / 10.0, 4.0 / 5.0, 8.0 / 9.0, 1.0, 1.0};
 
 template <typename R>
 struct DpArgs {
@@ -53,6 +55,8 @@ struct DpArgs {
     R ce[7];                      // dt (b_j - bhat_j)
     double rtol, atol;
     double* partials;             // stage 7: one double per workgroup
+    const C* E;                   // drive profile, or NULL
+    C drive_ph;                   // exp(-i omega t_s) at this stage's time
 };
 
 __device__ __forceinline__ double wave_sum_d(double v)
@@ -98,6 +102,10 @@ __global__ __launch_bounds__(256) void dp_stage_kernel(const DpArgs<R> a)
             C f[COMPS];
             R rho[COMPS];
             rhs_cell<R, COMPS, HASV>(a.c, U, M, D, nn, v, f, rho);
+            if (a.E) {
+#pragma unroll
+                for (int s = 0; s < COMPS; ++s) add_drive(f[s], a.E[s * cs + idx], a.drive_ph, a.c.inv_hbar);
+            }
 #pragma unroll
             for (int s = 0; s < COMPS; ++s) {
                 const int o = s * cs + idx;
@@ -318,6 +326,12 @@ static phx_status dp_attempt(phx_handle* h, double dt, bool need_k1, double* err
     a.rtol = c.rtol;
     a.atol = c.atol;
     a.partials = b.partials;
+    a.E = c.drive ? (const C*)h->f.E : nullptr;
+    auto set_phasor = [&](int s) {  // exp(-i omega t_s) at the time of stage s (1..7)
+        if (!c.drive) return;
+        const double th = c.drive_omega * (h->info.t + DP_C[s - 1] * dt);
+        a.drive_ph = C{(R)cos(th), (R)-sin(th)};
+    };
     const int cells = c.nx * c.ny * c.components;
     hipEvent_t t0 = nullptr;
     hipError_t e = hipSuccess;
@@ -331,6 +345,7 @@ static phx_status dp_attempt(phx_handle* h, double dt, bool need_k1, double* err
     if (need_k1) {
         a.y = (const C*)h->cur;
         a.yn = (const R*)h->cur_n;
+        set_phasor(1);
         e = timing_begin(h, &t0);
         if (e == hipSuccess) e = launch_dp<R>(1, res, hv, a, h->stream);
         if (e == hipSuccess) e = timing_end(h, t0, K_DP_S1);
@@ -353,6 +368,7 @@ static phx_status dp_attempt(phx_handle* h, double dt, bool need_k1, double* err
             a.y_out = (C*)(s == 6 ? h->other : b.ys[(s - 1) & 1]);
             a.yn_out = res ? (R*)(s == 6 ? h->other_n : b.yns[(s - 1) & 1]) : nullptr;
         }
+        set_phasor(s);
         e = timing_begin(h, &t0);
         if (e == hipSuccess) e = launch_dp<R>(s, res, hv, a, h->stream);
         if (e == hipSuccess) e = timing_end(h, t0, K_DP_S1 + s - 1);

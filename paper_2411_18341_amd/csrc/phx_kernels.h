@@ -51,6 +51,17 @@ __device__ __forceinline__ int xcd_tile(int b, int nb)
     return (x < r) ? x * (q + 1) + l : r * (q + 1) + (x - r) * q + l;
 }
 
+// Coherent drive of Eq. (PULSE_psi): adds -(i/hbar) E ph to f, with E the cell's
+// drive profile value and ph = exp(-i omega t) the phasor of the stage's time.
+template <typename C, typename R>
+__device__ __forceinline__ void add_drive(C& f, const C e, const C ph, R inv_hbar)
+{
+    const R zx = e.x * ph.x - e.y * ph.y;
+    const R zy = e.x * ph.y + e.y * ph.x;
+    f.x += inv_hbar * zy;
+    f.y -= inv_hbar * zx;
+}
+
 // ------------------------------------------------------------- launch API
 // Tile geometry of the stencil kernels: a workgroup of 4 waves covers wx*64
 // columns and (4/wx)*rows rows; each wave marches `rows` rows of its 64 columns.
@@ -76,6 +87,8 @@ struct Rk4Args {
     C* acc; R* accn;
     C* psi_io; R* n_io;         // stage 4: state, updated in place
     unsigned int* flag;         // set to 1 when stage 4 produces a non-finite value
+    const C* E;                 // drive profile [comps][ny][nx], or NULL
+    const C* drive_ph;          // phasors exp(-i omega t_s) of the four stage times
 };
 
 template <typename R>
@@ -104,6 +117,8 @@ struct ObsArgs {
     const C* psi; const R* n; const R* V; const R* P;
     double* partials;          // [blocks][OBS_SLOTS]
     double* out;               // [OBS_SLOTS]
+    const C* E;                // drive profile, or NULL
+    C drive_ph;                // exp(-i omega t) at the handle's time
 };
 
 template <typename R>

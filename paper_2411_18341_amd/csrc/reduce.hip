@@ -85,6 +85,10 @@ __global__ __launch_bounds__(256) void obs_pass1(const ObsArgs<R> a, double delt
             C f[COMPS];
             R rho[COMPS];
             rhs_cell<R, COMPS, HASV>(a.c, U, M, D, nn, v, f, rho);
+            if (a.E) {
+#pragma unroll
+                for (int s = 0; s < COMPS; ++s) add_drive(f[s], a.E[s * cs + idx], a.drive_ph, a.c.inv_hbar);
+            }
 #pragma unroll
             for (int s = 0; s < COMPS; ++s) {
                 const C p = M[s].c;

@@ -55,6 +55,11 @@ __global__ __launch_bounds__(256) void rk4_stage_kernel(const Rk4Args<R> a)
         C f[COMPS];
         R rho[COMPS];
         rhs_cell<R, COMPS, HASV>(a.c, U, M, D, nn, v, f, rho);
+        if (a.E) {  // uniform over the launch
+            const C ph = a.drive_ph[STAGE - 1];
+#pragma unroll
+            for (int s = 0; s < COMPS; ++s) add_drive(f[s], a.E[s * cs + idx], ph, a.c.inv_hbar);
+        }
 #pragma unroll
         for (int s = 0; s < COMPS; ++s) {
             const int o = s * cs + idx;

@@ -33,7 +33,9 @@ struct Layout {
     size_t alt;         // second state buffer for psi (whole-step RK4, Dormand-Prince)
     size_t alt_n;       // second state buffer for n (whole-step RK4)
     size_t alt2, alt2_n;  // third state buffer (whole-step RK4: the tuner's trial launches)
-    size_t noise;       // step index of the next Wiener increment (uint64; noise on only)
+    size_t noise;       // uint64 index of the next step, read by the noise and the drive
+                        // (allocated when either is on)
+    size_t drive_ph;    // RK4 with drive: the four stage phasors of the current step
     int family;         // PHX_KERNEL_STAGE or PHX_KERNEL_STEP for RK4
     size_t err;         // Dormand-Prince error partials
     int obs_blocks;
@@ -74,6 +76,9 @@ struct phx_handle {
     phx::StepShapeId step_shape;  // whole-step RK4 region shape in use
     phx::TilePlan stage_tiles;    // stage-fused RK4 tile plan in use
     int step_parity;              // whole-step family: buffer holding the state (0 = caller's)
+    // coherent drive: time and step index of the last phx_create / phx_set_info
+    double drive_t0;
+    int64_t drive_k0;
     int fsal;               // index of the buffer that holds K1 of the current state
     bool k1_valid;
     // hipGraph of graph_steps RK4 steps, captured on cap_stream, replayed on stream
@@ -123,4 +128,8 @@ template <typename R> hipError_t launch_noise(const phx_handle* h, void* psi, co
                                               hipStream_t s);
 hipError_t advance_noise_step(const phx_handle* h, int64_t by, hipStream_t s);
 hipError_t set_noise_step(const phx_handle* h, int64_t value, hipStream_t s);
+// Drive phasors exp(-i omega t_s) of the four RK4 stage times of the step with index
+// base + offset, written to the workspace (one thread; graph-replay safe).
+template <typename R> hipError_t launch_drive_phasors(const phx_handle* h, int64_t offset, hipStream_t s);
+bool uses_step_index(const phx_config& c);
 }  // namespace phx

@@ -72,6 +72,10 @@ phx_status validate_config(const phx_config* c)
         if (!isfinite(x)) return fail(PHX_EINVAL, "equation parameters must be finite");
     if (!finite_pos(c->dt)) return fail(PHX_EINVAL, "dt must be finite and > 0");
     if (!isfinite(c->noise) || c->noise < 0.0) return fail(PHX_EINVAL, "noise must be finite and >= 0");
+    if (c->drive != 0 && c->drive != 1) return fail(PHX_EINVAL, "drive must be 0 or 1");
+    if (!isfinite(c->drive_omega)) return fail(PHX_EINVAL, "drive_omega must be finite");
+    if (c->drive && c->integrator == PHX_RK4 && c->kernel == PHX_KERNEL_STEP)
+        return fail(PHX_EUNSUPPORTED, "the whole-step kernel does not take a drive (use the stage-fused family)");
     if (c->noise > 0.0 && c->integrator != PHX_RK4)
         return fail(PHX_EUNSUPPORTED, "Wiener noise is implemented for RK4 only");
     if (c->integrator == PHX_RK4) {
@@ -91,6 +95,8 @@ phx_status validate_config(const phx_config* c)
     return PHX_OK;
 }
 
+bool uses_step_index(const phx_config& c) { return c.noise > 0.0 || (c.drive && c.integrator == PHX_RK4); }
+
 Layout make_layout(const phx_config& c)
 {
     Layout L{};
@@ -105,7 +111,8 @@ Layout make_layout(const phx_config& c)
     L.tiles = plan_tiles(c.nx, c.ny, stage_tiles ? c.tile_wx : 0, stage_tiles ? c.tile_rows : 0);
     L.obs_blocks = L.tiles.tiles < 1024 ? L.tiles.tiles : 1024;
     L.partials = take((size_t)L.obs_blocks * OBS_SLOTS * sizeof(double));
-    if (c.noise > 0.0) L.noise = take(sizeof(uint64_t));
+    if (uses_step_index(c)) L.noise = take(sizeof(uint64_t));
+    if (c.drive && c.integrator == PHX_RK4) L.drive_ph = take(4 * 2 * rs);
     if (c.integrator == PHX_RK4) {
         L.family = rk4_family(c);
         if (L.family == PHX_KERNEL_STEP) {
@@ -155,7 +162,7 @@ bool valid_step_shape(int precision, int waves, int rows)
 // written once) for one component, the stage-fused kernels otherwise or on request.
 int rk4_family(const phx_config& c)
 {
-    if (c.kernel == PHX_KERNEL_STAGE) return PHX_KERNEL_STAGE;
+    if (c.kernel == PHX_KERNEL_STAGE || c.drive) return PHX_KERNEL_STAGE;
     if (c.components == 1) return PHX_KERNEL_STEP;
     return PHX_KERNEL_STAGE;
 }
@@ -240,7 +247,9 @@ phx_status phx_create(const phx_config* cfg, const phx_fields* f, void* stream,
     if (!f) return fail(PHX_EINVAL, "fields is NULL");
     if (!f->psi) return fail(PHX_EINVAL, "psi is NULL");
     if (cfg->reservoir && (!f->n || !f->P)) return fail(PHX_EINVAL, "reservoir needs n and P");
-    const void* ptrs[] = {f->psi, f->n, f->V, f->P, f->workspace};
+    if (cfg->drive ? !f->E : f->E != nullptr)
+        return fail(PHX_EINVAL, cfg->drive ? "drive needs the profile E" : "E given without drive");
+    const void* ptrs[] = {f->psi, f->n, f->V, f->P, f->workspace, f->E};
     for (const void* p : ptrs)
         if (p && !aligned(p)) return fail(PHX_EINVAL, "device pointers must be 256-byte aligned");
     const Layout L = make_layout(*cfg);
@@ -259,7 +268,9 @@ phx_status phx_create(const phx_config* cfg, const phx_fields* f, void* stream,
     hipError_t e = hipHostMalloc((void**)&h->host, (OBS_SLOTS + 2) * sizeof(double), hipHostMallocDefault);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&h->flag_ready, hipEventDisableTiming);
     if (e == hipSuccess) e = hipMemsetAsync(h->ws + L.flag, 0, 256, h->stream);
-    if (e == hipSuccess && cfg->noise > 0.0) e = set_noise_step(h, 0, h->stream);
+    if (e == hipSuccess && uses_step_index(*cfg)) e = set_noise_step(h, 0, h->stream);
+    h->drive_t0 = 0.0;
+    h->drive_k0 = 0;
     if (e != hipSuccess) {
         if (h->host) (void)hipHostFree(h->host);
         if (h->flag_ready) (void)hipEventDestroy(h->flag_ready);
@@ -329,10 +340,14 @@ phx_status rk4_stage_launches(phx_handle* h, int64_t n, hipStream_t stream)
     a.n = n0;
     a.psi_io = psi;
     a.n_io = n0;
+    a.E = c.drive ? (const C*)h->f.E : nullptr;
+    a.drive_ph = c.drive ? (const C*)(h->ws + L.drive_ph) : nullptr;
     const R half_dt = (R)(0.5 * c.dt), full_dt = (R)c.dt;
     a.dt6 = (R)(c.dt / 6.0);
     const bool res = c.reservoir != 0, hv = h->f.V != nullptr;
     for (int64_t k = 0; k < n; ++k) {
+        if (c.drive && launch_drive_phasors<R>(h, k, stream) != hipSuccess)
+            return fail(PHX_EHIP, "drive phasor launch failed");
         // stage 1: argument = state; stage s reads y written by stage s-1
         const C* yin[4] = {psi, Y[0], Y[1], Y[0]};
         const R* ynin[4] = {n0, YN[0], YN[1], YN[0]};
@@ -359,8 +374,8 @@ phx_status rk4_stage_launches(phx_handle* h, int64_t n, hipStream_t stream)
             if (e != hipSuccess) return fail(PHX_EHIP, "noise launch: %s", hipGetErrorString(e));
         }
     }
-    if (c.noise > 0.0 && n > 0 && advance_noise_step(h, n, stream) != hipSuccess)
-        return fail(PHX_EHIP, "noise step advance launch failed");
+    if (uses_step_index(c) && n > 0 && advance_noise_step(h, n, stream) != hipSuccess)
+        return fail(PHX_EHIP, "step index advance launch failed");
     return PHX_OK;
 }
 
@@ -524,6 +539,11 @@ static phx_status observables_t(phx_handle* h)
     a.P = (const R*)h->f.P;
     a.partials = (double*)(h->ws + h->L.partials);
     a.out = (double*)(h->ws + h->L.obs);
+    if (c.drive) {  // the residual's right-hand side at the handle's time
+        a.E = (const typename cvec<R>::type*)h->f.E;
+        const double th = c.drive_omega * h->info.t;
+        a.drive_ph = typename cvec<R>::type{(R)cos(th), (R)-sin(th)};
+    }
     hipEvent_t t0 = nullptr;
     hipError_t e = timing_begin(h, &t0);
     if (e == hipSuccess) e = launch_observables<R>(a, h->L.obs_blocks, h->stream);
@@ -589,8 +609,14 @@ phx_status phx_set_info(phx_handle* h, const phx_info* in)
         HIP_OR_FAIL(hipMemsetAsync(h->ws + h->L.flag, 0, 256, h->stream));
         h->flag_pending = false;
     }
-    // the next Wiener increment continues the restored run's sequence
-    if (h->cfg.noise > 0.0) HIP_OR_FAIL(set_noise_step(h, in->steps_accepted, h->stream));
+    // the next Wiener increment continues the restored run's sequence; the drive's
+    // clock restarts at (t, steps_accepted), which captured graphs hold as arguments
+    if (uses_step_index(h->cfg)) HIP_OR_FAIL(set_noise_step(h, in->steps_accepted, h->stream));
+    if (h->cfg.drive) {
+        h->drive_t0 = in->t;
+        h->drive_k0 = in->steps_accepted;
+        h->graph_dirty = true;
+    }
     h->info = *in;
     return PHX_OK;
 }

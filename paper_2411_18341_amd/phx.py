@@ -43,13 +43,14 @@ class phx_config(ctypes.Structure):
         ("kernel", ctypes.c_int32), ("tile_wx", ctypes.c_int32), ("tile_rows", ctypes.c_int32),
         ("graph_steps", ctypes.c_int32),
         ("noise", ctypes.c_double), ("seed", ctypes.c_uint64),
+        ("drive_omega", ctypes.c_double), ("drive", ctypes.c_int32),
     ]
 
 
 class phx_fields(ctypes.Structure):
     _fields_ = [("psi", ctypes.c_void_p), ("n", ctypes.c_void_p), ("V", ctypes.c_void_p),
                 ("P", ctypes.c_void_p), ("workspace", ctypes.c_void_p),
-                ("workspace_bytes", ctypes.c_size_t)]
+                ("workspace_bytes", ctypes.c_size_t), ("E", ctypes.c_void_p)]
 
 
 class phx_obs(ctypes.Structure):
@@ -284,13 +285,14 @@ def make_config(nx, ny, dx, dy=None, *, bc_x=PHX_BC_PERIODIC, bc_y=PHX_BC_PERIOD
                 g_x=0.0, g_r=0.0, R=0.0, gamma_c=0.0, gamma_r=0.0, delta_lt=0.0, dt=1e-3,
                 rtol=1e-6, atol=1e-6, dt_min=1e-12, dt_max=float("inf"),
                 kernel=PHX_KERNEL_AUTO, tile_wx=0, tile_rows=0, graph_steps=0, noise=0.0,
-                seed=0) -> phx_config:
+                seed=0, drive=False, drive_omega=0.0) -> phx_config:
     return phx_config(int(nx), int(ny), float(dx), float(dx if dy is None else dy), int(bc_x), int(bc_y),
                       int(components), int(bool(reservoir)), int(precision), int(integrator),
                       float(hbar), float(mass), float(g), float(g_x), float(g_r), float(R),
                       float(gamma_c), float(gamma_r), float(delta_lt), float(dt), float(rtol),
                       float(atol), float(dt_min), float(dt_max), int(kernel), int(tile_wx),
-                      int(tile_rows), int(graph_steps), float(noise), int(seed) & (2 ** 64 - 1))
+                      int(tile_rows), int(graph_steps), float(noise), int(seed) & (2 ** 64 - 1),
+                      float(drive_omega), int(bool(drive)))
 
 
 def config_from_physics(ph, **kw) -> phx_config:
@@ -355,22 +357,24 @@ class Solver:
     PHX_C128); n, P: real [components, ny, nx] when the reservoir is on; V: real
     [ny, nx] or None.  The tensors are updated in place by `step`."""
 
-    def __init__(self, cfg: phx_config, psi, n=None, V=None, P=None, stream=None):
+    def __init__(self, cfg: phx_config, psi, n=None, V=None, P=None, stream=None, E=None):
         import torch
         cdt, rdt = torch_dtypes(cfg.precision)
         shape = (cfg.components, cfg.ny, cfg.nx)
         if psi.dtype != cdt or tuple(psi.shape) != shape or not psi.is_contiguous() or not psi.is_cuda:
             raise ValueError(f"psi must be a contiguous {cdt} CUDA tensor of shape {shape}")
+        if E is not None and (E.dtype != cdt or tuple(E.shape) != shape or not E.is_contiguous() or not E.is_cuda):
+            raise ValueError(f"E must be a contiguous {cdt} CUDA tensor of shape {shape}")
         for name, t, shp in (("n", n, shape), ("P", P, shape), ("V", V, (cfg.ny, cfg.nx))):
             if t is not None and (t.dtype != rdt or tuple(t.shape) != shp or not t.is_contiguous() or not t.is_cuda):
                 raise ValueError(f"{name} must be a contiguous {rdt} CUDA tensor of shape {shp}")
         self.cfg = cfg
-        self.psi, self.n, self.V, self.P = psi, n, V, P
+        self.psi, self.n, self.V, self.P, self.E = psi, n, V, P, E
         nbytes = phx_workspace_bytes(cfg)
         self.workspace = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=psi.device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(psi.device)
         ptr = lambda t: None if t is None else t.data_ptr()
-        self.fields = phx_fields(ptr(psi), ptr(n), ptr(V), ptr(P), self.workspace.data_ptr(), nbytes)
+        self.fields = phx_fields(ptr(psi), ptr(n), ptr(V), ptr(P), self.workspace.data_ptr(), nbytes, ptr(E))
         self.handle = phx_create(cfg, self.fields, self.stream.cuda_stream)
 
     def step(self, n_steps: int = 1) -> dict:

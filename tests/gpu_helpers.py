@@ -40,7 +40,7 @@ def oracle_physics(ph):
 class GpuRun:
     """A solver handle over device copies of the given host arrays."""
 
-    def __init__(self, ph, psi, n=None, V=None, P=None, precision=C128, **cfg_kw):
+    def __init__(self, ph, psi, n=None, V=None, P=None, precision=C128, E=None, **cfg_kw):
         import torch
         self.torch = torch
         cdt, rdt = phx.torch_dtypes(precision)
@@ -52,8 +52,11 @@ class GpuRun:
         self.n = t(n, rdt, shape) if ph.reservoir else None
         self.P = t(P, rdt, shape) if ph.reservoir else None
         self.V = t(V, rdt, (ph.ny, ph.nx))
+        self.E = t(E, cdt, shape)
+        if E is not None:
+            cfg_kw.setdefault("drive", True)
         self.cfg = phx.config_from_physics(ph, precision=precision, **cfg_kw)
-        self.solver = phx.Solver(self.cfg, self.psi, self.n, self.V, self.P)
+        self.solver = phx.Solver(self.cfg, self.psi, self.n, self.V, self.P, E=self.E)
 
     def step(self, k):
         return self.solver.step(k)

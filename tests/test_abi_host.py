@@ -40,7 +40,7 @@ def _c_layout():
 #define F(T, m) printf(#T "." #m " %zu\n", offsetof(T, m));
 int main(void) {
   printf("phx_config %zu\n", sizeof(phx_config)); F(phx_config, dx) F(phx_config, bc_x) F(phx_config, hbar)
-  F(phx_config, delta_lt) F(phx_config, dt) F(phx_config, dt_max) F(phx_config, kernel) F(phx_config, tile_rows) F(phx_config, graph_steps) F(phx_config, noise) F(phx_config, seed)
+  F(phx_config, delta_lt) F(phx_config, dt) F(phx_config, dt_max) F(phx_config, kernel) F(phx_config, tile_rows) F(phx_config, graph_steps) F(phx_config, noise) F(phx_config, seed) F(phx_config, drive_omega) F(phx_config, drive)
   printf("phx_fields %zu\n", sizeof(phx_fields)); F(phx_fields, workspace_bytes)
   printf("phx_obs %zu\n", sizeof(phx_obs)); F(phx_obs, energy) F(phx_obs, max_density) F(phx_obs, nonfinite) F(phx_obs, norm_renorm)
   printf("phx_info %zu\n", sizeof(phx_info)); F(phx_info, steps_rejected) F(phx_info, nonfinite)
@@ -48,7 +48,7 @@ int main(void) {
   printf("phx_tune_result %zu\n", sizeof(phx_tune_result)); F(phx_tune_result, best_us) F(phx_tune_result, default_us)
   printf("phx_instance %zu\n", sizeof(phx_instance)); F(phx_instance, offset)
   printf("phx_batch_desc %zu\n", sizeof(phx_batch_desc)); F(phx_batch_desc, params) F(phx_batch_desc, psi)
-  F(phx_batch_desc, workspace_bytes)
+  F(phx_batch_desc, workspace_bytes) F(phx_fields, E)
   return 0; }
 '''
     return prog
@@ -103,6 +103,7 @@ def test_workspace_bytes_scale_with_precision_and_reservoir():
     ("reservoir", 2), ("precision", 5), ("integrator", 9), ("hbar", 0.0), ("mass", -1.0),
     ("g", float("inf")), ("dt", 0.0), ("dt", 1.0), ("kernel", 7),
     ("tile_wx", 3), ("tile_rows", 5), ("tile_rows", 65), ("noise", -1.0), ("noise", float("nan")),
+    ("drive", 2), ("drive_omega", float("inf")),
 ])
 def test_invalid_config_rejected(field, value):
     cfg = good_config()
@@ -123,6 +124,18 @@ def test_noise_config_validation():
     with pytest.raises(phx.PhxError) as e:
         phx.phx_workspace_bytes(good_config(noise=1.0, integrator=phx.PHX_RK45))
     assert e.value.status == phx.PHX_EUNSUPPORTED
+
+
+def test_drive_config_validation():
+    """Coherent drive: the stage-fused family (AUTO picks it, an explicit whole-step
+    request is unsupported); RK4 adds the step-index slot and four stage phasors."""
+    stage = phx.phx_workspace_bytes(good_config(kernel=phx.PHX_KERNEL_STAGE))
+    assert phx.phx_workspace_bytes(good_config(drive=True, drive_omega=1.5)) == stage + 256 + 256
+    with pytest.raises(phx.PhxError) as e:
+        phx.phx_workspace_bytes(good_config(drive=True, kernel=phx.PHX_KERNEL_STEP))
+    assert e.value.status == phx.PHX_EUNSUPPORTED
+    rk45 = phx.phx_workspace_bytes(good_config(integrator=phx.PHX_RK45))
+    assert phx.phx_workspace_bytes(good_config(integrator=phx.PHX_RK45, drive=True)) == rk45
 
 
 def test_rk45_tolerance_validation():
