@@ -95,6 +95,9 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="skip the tile-shape search before timing")
     ap.add_argument("--noise", type=float, default=0.0,
                     help="intensity nu of the truncated-Wigner Wiener noise (0 = the deterministic workload)")
+    ap.add_argument("--drive", type=float, default=None, metavar="OMEGA",
+                    help="add a coherent drive of frequency OMEGA (a Gaussian spot, amplitude 0.8, width 30); "
+                         "runs on the stage-fused kernels")
     ap.add_argument("--tile", type=int, nargs=2, metavar=("WX", "ROWS"), default=None,
                     help="force this tile shape (no search)")
     args = ap.parse_args()
@@ -123,16 +126,23 @@ def main():
     step_workload = workload
     if args.noise > 0:
         workload += f", Wiener noise nu {args.noise}"
+    E = None
+    if args.drive is not None:
+        workload += f", coherent drive omega {args.drive} (Gaussian spot 0.8, width 30)"
+        X, Y = inputs.coords(args.n, args.n, ph.dx, ph.dy)
+        E = torch.from_numpy((0.8 * np.exp(-(X * X + Y * Y) / (2 * 30.0 ** 2)))[None]).to(
+            dtype=phx.torch_dtypes(precision)[0], device="cuda:0").contiguous()
     cdt, rdt = phx.torch_dtypes(precision)
     dev = torch.device("cuda:0")
     psi = torch.from_numpy(psi0).to(dtype=cdt, device=dev).contiguous()
     n = torch.from_numpy(n0).to(dtype=rdt, device=dev).contiguous()
     Pd = torch.from_numpy(P).to(dtype=rdt, device=dev).contiguous()
     family = {"auto": phx.PHX_KERNEL_AUTO, "stage": phx.PHX_KERNEL_STAGE, "step": phx.PHX_KERNEL_STEP}[args.kernel]
-    cfg = phx.config_from_physics(ph, precision=precision, kernel=family, noise=args.noise, seed=1)
+    cfg = phx.config_from_physics(ph, precision=precision, kernel=family, noise=args.noise, seed=1,
+                                  drive=E is not None, drive_omega=args.drive or 0.0)
     if args.tile:
         cfg.tile_wx, cfg.tile_rows = args.tile
-    solver = phx.Solver(cfg, psi, n, None, Pd)
+    solver = phx.Solver(cfg, psi, n, None, Pd, E=E)
     if args.tile:
         tune = {"tile_wx": args.tile[0], "tile_rows": args.tile[1]}
     else:
@@ -154,7 +164,7 @@ def main():
 
     cells = args.n * args.n
     value = cells * args.steps / wall
-    stage_model = bytemodel.rk4_stage_fused(real_bytes, reservoir=True, has_v=False)
+    stage_model = bytemodel.rk4_stage_fused(real_bytes, reservoir=True, has_v=False, drive=E is not None)
     step_model = bytemodel.rk4_whole_step(real_bytes, reservoir=True, has_v=False)
     per_launch = {f"rk4_stage{s}": stage_model[f"stage{s}"] for s in range(1, 5)}
     per_launch["rk4_step"] = step_model["step"]
@@ -171,7 +181,8 @@ def main():
     d = kernels[dom]
     # counter measurements of the whole-step kernel are kept per region shape
     shape_key = dom if dom != "rk4_step" or tune is None else f"rk4_step_{tune['tile_wx']}x{tune['tile_rows']}"
-    traffic = measured_traffic(shape_key, step_workload)
+    # the drive changes what the stage kernels read: its counter record is a separate file
+    traffic = measured_traffic(shape_key, step_workload) if args.drive is None else None
     roofline = {"bound": "hbm", "achieved": round(d["GBps"], 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                 "frac": round(d["GBps"] / HBM_PEAK_GBPS, 4), "traffic": traffic,
                 "kernel": shape_key, "bytes_per_launch": d["bytes_per_launch"],
@@ -192,6 +203,7 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f32" if real_bytes == 4 else "f64",
         "data": "synthetic",
         "config": {"workload": workload, "grid": [args.n, args.n], "integrator": "rk4", "noise": args.noise,
+                   "drive_omega": args.drive,
                    "kernel_family": family_name,
                    "tile": None if tune is None else [tune["tile_wx"], tune["tile_rows"]]},
         "roofline": roofline,

@@ -21,13 +21,16 @@ def paper_unfused_rk4(real_bytes: int) -> dict:
     return {"reads": reads, "writes": writes, "bytes_per_point": 2 * (reads + writes) * real_bytes}
 
 
-def rk4_stage_fused(real_bytes: int, reservoir: bool, has_v: bool, components: int = 1) -> dict:
+def rk4_stage_fused(real_bytes: int, reservoir: bool, has_v: bool, components: int = 1,
+                    drive: bool = False) -> dict:
     """Bytes per point of the four stage-fused RK4 launches (stage 1..4) and of
     one whole step.  Complex arrays are 2*real_bytes per component, real arrays
-    real_bytes per component, V real_bytes (shared by the components)."""
+    real_bytes per component, V real_bytes (shared by the components); with the
+    coherent drive every stage also reads the complex drive profile."""
     c = 2 * real_bytes * components
     r = real_bytes * components if reservoir else 0
     v = real_bytes if has_v else 0
+    v += c if drive else 0                     # the drive profile is read like V
     p = r                                      # pump, read by every stage with the reservoir
     s1 = (c + r + p + v) + (2 * c + 2 * r)     # read y=psi,n,P,V; write y2,acc (+n parts)
     s23 = (3 * c + 3 * r + p + v) + (2 * c + 2 * r)  # read y,psi,acc (+n parts),P,V; write y,acc

@@ -17,7 +17,8 @@ With --batch it first measures the batched workload of 256 driven instances on
 grids of 128..1024 (one persistent launch per step) against stepping the same
 instances with one solver each; with --spinor the 4096^2 two-component workload
 with RK4 and with Dormand-Prince; with --noise the 4096^2 driven workload with the
-truncated-Wigner noise on and off.
+truncated-Wigner noise on and off; with --drive the stage-fused kernels with and without
+the coherent drive.
 """
 from __future__ import annotations
 
@@ -217,6 +218,52 @@ def measure_noise(n: int = 4096, nu: float = 1.0, steps: int = 300, warmup: int 
     return out
 
 
+def measure_drive(n: int = 4096, omega: float = 1.3, steps: int = 100, warmup: int = 10, timed_steps: int = 20):
+    """The driven workload (complex64, n x n) on the stage-fused kernels with and
+    without a coherent drive (a Gaussian spot of amplitude 0.8): point updates per
+    second of whole steps (graph replays), and per stage kernel the mean launch time
+    with its algorithmic bandwidth (the drive adds one complex read per stage)."""
+    import numpy as np
+    import torch
+    ph, psi0, n0, P = inputs.driven(n)
+    X, Y = inputs.coords(n, n, ph.dx, ph.dy)
+    E0 = (0.8 * np.exp(-(X * X + Y * Y) / (2 * 30.0 ** 2)))[None].astype(np.complex64)
+    dev = torch.device("cuda:0")
+    out = {"n": n, "omega": omega}
+    for label, drive in (("undriven", False), ("driven", True)):
+        psi = torch.from_numpy(psi0).to(dtype=torch.complex64, device=dev).contiguous()
+        nn = torch.from_numpy(n0).to(dtype=torch.float32, device=dev).contiguous()
+        Pd = torch.from_numpy(P).to(dtype=torch.float32, device=dev).contiguous()
+        Ed = torch.from_numpy(E0).to(device=dev).contiguous() if drive else None
+        cfg = phx.config_from_physics(ph, precision=phx.PHX_C64, kernel=phx.PHX_KERNEL_STAGE, drive=drive,
+                                      drive_omega=omega)
+        solver = phx.Solver(cfg, psi, nn, None, Pd, E=Ed)
+        try:
+            tune = solver.autotune(reps=5, use_cache=False)
+            solver.step(warmup)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            solver.step(steps)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            solver.set_timing(True)
+            solver.step(timed_steps)
+            torch.cuda.synchronize()
+            times = solver.kernel_times()
+        finally:
+            solver.close()
+        model = bytemodel.rk4_stage_fused(4, reservoir=True, has_v=False, drive=drive)
+        ks = {}
+        for k, v in times.items():
+            us = v["ms_total"] / v["launches"] * 1e3
+            ks[k] = {"avg_us": us}
+            if k.startswith("rk4_stage"):
+                ks[k]["algorithmic_GBps"] = model["stage" + k[-1]] * n * n / (us * 1e-6) / 1e9
+        out[label] = {"tile": [tune["tile_wx"], tune["tile_rows"]], "UPs": n * n * steps / wall,
+                      "us_per_step": wall / steps * 1e6, "step_bytes_per_point": model["step"], "kernels": ks}
+    return out
+
+
 def table(rows) -> str:
     out = ["| N | family | tile | steps | µs/step | G UP/s | algorithmic GB/s | mean launch µs per kernel |",
            "|---|---|---|---|---|---|---|---|"]
@@ -235,7 +282,14 @@ def main():
     ap.add_argument("--batch", action="store_true", help="also measure the 256-instance batched workload")
     ap.add_argument("--spinor", action="store_true", help="also measure the 4096^2 spinor workload (RK4, RK45)")
     ap.add_argument("--noise", action="store_true", help="also measure the 4096^2 driven workload with Wiener noise")
+    ap.add_argument("--drive", action="store_true", help="also measure the stage-fused kernels with a coherent drive")
     args = ap.parse_args()
+    if args.drive:
+        r = measure_drive()
+        print(json.dumps({"drive": r}), flush=True)
+        if args.out:
+            with open(args.out + ".drive.json", "w") as f:
+                json.dump(r, f, indent=1)
     if args.noise:
         r = measure_noise()
         print(json.dumps({"noise": r}), flush=True)
