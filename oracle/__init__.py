@@ -107,6 +107,7 @@ def _load():
                                    ctypes.c_double, ctypes.c_double, ctypes.c_int64, P(_Ctrl),
                                    vp, ctypes.c_int64]
         lib.orc_rhs_t.argtypes = [P(_Params), vp, vp, vp, vp, vp, vp]
+        lib.orc_rk4_imag.argtypes = [P(_Params), vp, vp, ctypes.c_double, ctypes.c_int64]
         lib.orc_observables.argtypes = [P(_Params), vp, vp, vp, vp, P(_Obs)]
         u32p = P(ctypes.c_uint32)
         lib.orc_philox.argtypes = [u32p, u32p, u32p]
@@ -325,6 +326,19 @@ def rk4_noise(ph: Physics, psi, n=None, V=None, P=None, dt=1e-3, steps=1, nu=1.0
     lib.orc_rk4_noise(ctypes.byref(ph._c()), _ptr(psi), _ptr(n), _ptr(V), _ptr(P), float(dt), int(steps),
                       float(nu), int(seed), int(step0))
     return psi, n
+
+
+def rk4_imag(ph: Physics, psi, V=None, dt=1e-3, steps=1):
+    """`steps` imaginary-time RK4 steps, each restoring the norm psi had at the call's
+    start; returns the new psi.  The conservative equation only."""
+    if ph.reservoir or ph.gamma_c or ph.R or ph.E is not None:
+        raise ValueError("imaginary time needs the conservative equation")
+    lib = _load()
+    sp, _, sv = _shapes(ph)
+    psi = _cplx(psi, sp)
+    V = _real(V, sv, False)
+    lib.orc_rk4_imag(ctypes.byref(ph._c()), _ptr(psi), _ptr(V), float(dt), int(steps))
+    return psi
 
 
 def num_threads() -> int:

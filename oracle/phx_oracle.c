@@ -24,6 +24,8 @@
  *     (truncated Wigner), drawn from Philox4x32-10 and the Box-Muller transform.
  *   - Coherent drive E_+- of Eq. (PULSE_psi), a term -(i/hbar) E_s(r, t) in d psi_s/dt,
  *     with E_s(r, t) = E_s(r) exp(-i omega t) evaluated at each stage's own time.
+ *   - Imaginary-time propagation (named in Sec. 6): t -> -i tau, RK4 steps of
+ *     d psi/d tau = -(1/hbar) H psi, each followed by restoring the norm.
  *
  * Readings where the paper is silent (each is also listed in the design notes):
  *   - f in Eqs. (rk4_K1)-(rk4_K4) is the time derivative d psi/dt = -(i/hbar) H psi.
@@ -216,6 +218,46 @@ void orc_rk4(const orc_params *p, cplx *psi, double *n, const double *V, const d
     }
     for (int s = 0; s < 4; ++s) { free(k[s]); free(kn[s]); }
     free(y); free(yn);
+}
+
+/* Total norm dxdy sum |psi|^2 over all components. */
+static double total_norm(const orc_params *p, const cplx *psi)
+{
+    const size_t M = cells(p) * (size_t)p->components;
+    double s = 0.0;
+    for (size_t q = 0; q < M; ++q) s += creal(psi[q]) * creal(psi[q]) + cimag(psi[q]) * cimag(psi[q]);
+    return p->dx * p->dy * s;
+}
+
+/* n_steps imaginary-time steps (t -> -i tau) of the conservative equation (no
+ * reservoir, gamma_c = R = 0, no drive): classical RK4 on d psi/d tau = -(1/hbar) H psi,
+ * whose right-hand side is -i times the real-time one, and after every step psi is
+ * scaled by sqrt(N0 / N) so that its total norm N returns to the value N0 it had when
+ * the call began. */
+void orc_rk4_imag(const orc_params *p, cplx *psi, const double *V, double dt, int64_t n_steps)
+{
+    const size_t M = cells(p) * (size_t)p->components;
+    cplx *k[4], *y = xmalloc(M * sizeof(cplx));
+    for (int s = 0; s < 4; ++s) k[s] = xmalloc(M * sizeof(cplx));
+    const double a[4] = {0.0, 0.5, 0.5, 1.0};
+    const double N0 = total_norm(p, psi);
+    for (int64_t step = 0; step < n_steps; ++step) {
+        for (int s = 0; s < 4; ++s) {
+            const cplx *arg = psi;
+            if (s > 0) {
+                for (size_t q = 0; q < M; ++q) y[q] = psi[q] + a[s] * dt * k[s - 1][q];
+                arg = y;
+            }
+            orc_rhs(p, arg, NULL, V, NULL, k[s], NULL);
+            for (size_t q = 0; q < M; ++q) k[s][q] *= -I;
+        }
+        for (size_t q = 0; q < M; ++q)
+            psi[q] = psi[q] + (1.0 / 6.0) * (k[0][q] + 2.0 * k[1][q] + 2.0 * k[2][q] + k[3][q]) * dt;
+        const double scale = sqrt(N0 / total_norm(p, psi));
+        for (size_t q = 0; q < M; ++q) psi[q] *= scale;
+    }
+    for (int s = 0; s < 4; ++s) free(k[s]);
+    free(y);
 }
 
 /* ------------------------------------------------------- Dormand-Prince 5(4) */

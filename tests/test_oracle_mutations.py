@@ -71,6 +71,18 @@ DRIVE_MUTATIONS = {
 }
 
 
+# Mistakes in the imaginary-time propagation, checked by its pins.
+IMAG_MUTATIONS = {
+    "imag_rotation_sign": ("k[s][q] *= -I;", "k[s][q] *= I;"),
+    "imag_rotation_dropped": ("k[s][q] *= -I;", "k[s][q] *= 1.0;"),
+    "imag_norm_target": ("const double scale = sqrt(N0 / total_norm(p, psi));",
+                         "const double scale = sqrt(1.0 / total_norm(p, psi));"),
+    "imag_weights": ("(k[0][q] + 2.0 * k[1][q] + 2.0 * k[2][q] + k[3][q]) * dt;\n        const double scale",
+                     "(k[0][q] + 2.0 * k[1][q] + k[2][q] + 2.0 * k[3][q]) * dt;\n        const double scale"),
+    "imag_stage_argument": ("                arg = y;", "                arg = psi;"),
+}
+
+
 def _run_pins_on_mutant(old, new, pins, tmp_path):
     src = open(SRC).read()
     assert src.count(old) >= 1, f"mutation anchor {old!r} no longer in the oracle source"
@@ -95,6 +107,13 @@ def test_drive_pins_reject_planted_mistake(name, tmp_path):
     old, new = DRIVE_MUTATIONS[name]
     r = _run_pins_on_mutant(old, new, "test_oracle_drive_pins.py", tmp_path)
     assert r.returncode != 0, f"drive pins passed with planted mistake {name}:\n{r.stdout[-2000:]}"
+
+
+@pytest.mark.parametrize("name", sorted(IMAG_MUTATIONS))
+def test_imag_pins_reject_planted_mistake(name, tmp_path):
+    old, new = IMAG_MUTATIONS[name]
+    r = _run_pins_on_mutant(old, new, "test_oracle_imag_pins.py", tmp_path)
+    assert r.returncode != 0, f"imaginary-time pins passed with planted mistake {name}:\n{r.stdout[-2000:]}"
 
 
 @pytest.mark.parametrize("name", sorted(MUTATIONS))
