@@ -107,6 +107,14 @@ typedef struct phx_config {
                                phx_set_info or phx_create starts at t_set + k dt).  Stage-fused
                                RK4 and RK45 (PHX_KERNEL_AUTO picks the stage-fused family;
                                the whole-step kernel and batches: PHX_EUNSUPPORTED).  0: none */
+    int32_t imag_time;      /* 1: imaginary-time propagation (t -> -i tau, named in Sec. 6)
+                               of the conservative equation (reservoir, gamma_c, R, noise and
+                               drive all off, else PHX_EINVAL): RK4 steps of
+                               d psi/d tau = -(1/hbar) H psi on the stage-fused kernels, each
+                               followed by scaling psi so that its total norm
+                               dx dy sum_s,cells |psi_s|^2 equals the value it had when the
+                               phx_step call began (deterministic FP64 reduction on the
+                               device).  dt is the tau step; RK4 only.  0: real time         */
 } phx_config;
 
 /* Caller-owned device arrays bound to a handle (borrowed until phx_destroy). */
@@ -208,7 +216,7 @@ const char *phx_last_error(void);
  * Per-kernel GPU time of a handle's own launches, measured with HIP events
  * recorded on the handle's stream around every kernel launch while timing is on
  * (the per-kernel view of Sec. 4.4).  Kernel kinds are named, e.g. "rk4_stage2". */
-#define PHX_MAX_KERNEL_KINDS 16
+#define PHX_MAX_KERNEL_KINDS 24
 typedef struct phx_timing {
     int32_t count;                          /* kinds with at least one launch            */
     int32_t reserved;

@@ -133,6 +133,7 @@ static phx_status validate_batch(const phx_batch_desc* d)
         if (s != PHX_OK) return s;
         if (c.noise != 0.0) return fail(PHX_EUNSUPPORTED, "Wiener noise is not implemented for batches");
         if (c.drive != 0) return fail(PHX_EUNSUPPORTED, "the coherent drive is not implemented for batches");
+        if (c.imag_time != 0) return fail(PHX_EUNSUPPORTED, "imaginary time is not implemented for batches");
         if (c.reservoir != res) return fail(PHX_EINVAL, "all params must share the reservoir flag");
     }
     std::vector<std::pair<int64_t, int64_t>> spans;

@@ -89,6 +89,7 @@ struct Rk4Args {
     unsigned int* flag;         // set to 1 when stage 4 produces a non-finite value
     const C* E;                 // drive profile [comps][ny][nx], or NULL
     const C* drive_ph;          // phasors exp(-i omega t_s) of the four stage times
+    int imag;                   // 1: imaginary time, the derivative is -i f
 };
 
 template <typename R>

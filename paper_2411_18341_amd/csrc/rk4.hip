@@ -60,6 +60,10 @@ __global__ __launch_bounds__(256) void rk4_stage_kernel(const Rk4Args<R> a)
 #pragma unroll
             for (int s = 0; s < COMPS; ++s) add_drive(f[s], a.E[s * cs + idx], ph, a.c.inv_hbar);
         }
+        if (a.imag) {  // t -> -i tau: d psi/d tau = -i (d psi/dt)
+#pragma unroll
+            for (int s = 0; s < COMPS; ++s) f[s] = C{f[s].y, -f[s].x};
+        }
 #pragma unroll
         for (int s = 0; s < COMPS; ++s) {
             const int o = s * cs + idx;

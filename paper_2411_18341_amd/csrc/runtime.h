@@ -36,6 +36,8 @@ struct Layout {
     size_t noise;       // uint64 index of the next step, read by the noise and the drive
                         // (allocated when either is on)
     size_t drive_ph;    // RK4 with drive: the four stage phasors of the current step
+    size_t imag;        // imaginary time: [0] target norm of the call, [1] restoring scale
+    size_t imag_partials;  // imaginary time: per-workgroup norm partials
     int family;         // PHX_KERNEL_STAGE or PHX_KERNEL_STEP for RK4
     size_t err;         // Dormand-Prince error partials
     int obs_blocks;
@@ -101,7 +103,7 @@ namespace phx {
 // Kernel kinds for phx_kernel_times; names in kernel_kind_name().
 enum KernelKind {
     K_RK4_S1 = 0, K_RK4_S2, K_RK4_S3, K_RK4_S4, K_OBS, K_DP_S1, K_DP_S2, K_DP_S3, K_DP_S4,
-    K_DP_S5, K_DP_S6, K_DP_S7, K_DP_ERR, K_BATCH, K_RK4_STEP, K_NOISE, K_KINDS_
+    K_DP_S5, K_DP_S6, K_DP_S7, K_DP_ERR, K_BATCH, K_RK4_STEP, K_NOISE, K_IMAG_NORM, K_IMAG_SCALE, K_KINDS_
 };
 const char* kernel_kind_name(int k);
 // Timing brackets around one launch (no-ops unless timing is on).
@@ -132,4 +134,9 @@ hipError_t set_noise_step(const phx_handle* h, int64_t value, hipStream_t s);
 // base + offset, written to the workspace (one thread; graph-replay safe).
 template <typename R> hipError_t launch_drive_phasors(const phx_handle* h, int64_t offset, hipStream_t s);
 bool uses_step_index(const phx_config& c);
+// Imaginary time: deterministic total norm of psi into the target (mode 0) or the
+// restoring scale (mode 1), and the pointwise scale pass.
+int imag_norm_blocks(int64_t M);
+template <typename R> hipError_t launch_imag_norm(const phx_handle* h, const void* psi, int mode, hipStream_t s);
+template <typename R> hipError_t launch_imag_scale(const phx_handle* h, void* psi, hipStream_t s);
 }  // namespace phx

@@ -74,17 +74,28 @@ phx_status validate_config(const phx_config* c)
     if (!isfinite(c->noise) || c->noise < 0.0) return fail(PHX_EINVAL, "noise must be finite and >= 0");
     if (c->drive != 0 && c->drive != 1) return fail(PHX_EINVAL, "drive must be 0 or 1");
     if (!isfinite(c->drive_omega)) return fail(PHX_EINVAL, "drive_omega must be finite");
+    if (c->imag_time != 0 && c->imag_time != 1) return fail(PHX_EINVAL, "imag_time must be 0 or 1");
+    if (c->imag_time) {
+        if (c->reservoir || c->gamma_c != 0.0 || c->R != 0.0 || c->noise != 0.0 || c->drive)
+            return fail(PHX_EINVAL, "imaginary time needs the conservative equation "
+                                    "(no reservoir, gamma_c = R = 0, no noise, no drive)");
+        if (c->integrator != PHX_RK4) return fail(PHX_EUNSUPPORTED, "imaginary time is implemented for RK4 only");
+        if (c->kernel == PHX_KERNEL_STEP)
+            return fail(PHX_EUNSUPPORTED, "imaginary time runs on the stage-fused kernels");
+    }
     if (c->drive && c->integrator == PHX_RK4 && c->kernel == PHX_KERNEL_STEP)
         return fail(PHX_EUNSUPPORTED, "the whole-step kernel does not take a drive (use the stage-fused family)");
     if (c->noise > 0.0 && c->integrator != PHX_RK4)
         return fail(PHX_EUNSUPPORTED, "Wiener noise is implemented for RK4 only");
     if (c->integrator == PHX_RK4) {
         // Largest |lambda| of the kinetic term on the grid: (hbar/2m) 4 (1/dx^2 + 1/dy^2);
-        // RK4 is unstable on the imaginary axis beyond |lambda dt| = 2 sqrt(2).
+        // RK4 is unstable on the imaginary axis beyond |lambda dt| = 2 sqrt(2), and on
+        // the negative real axis (imaginary time) beyond 2.785.
         const double lam = c->hbar / (2.0 * c->mass) * 4.0 * (1.0 / (c->dx * c->dx) + 1.0 / (c->dy * c->dy));
-        if (lam * c->dt > 2.0 * sqrt(2.0))
+        const double bound = c->imag_time ? 2.78 : 2.0 * sqrt(2.0);
+        if (lam * c->dt > bound)
             return fail(PHX_EINVAL, "dt=%g exceeds the RK4 stability bound %g of the kinetic term",
-                        c->dt, 2.0 * sqrt(2.0) / lam);
+                        c->dt, bound / lam);
     } else {
         if (!(c->rtol >= 0.0) || !(c->atol >= 0.0) || !isfinite(c->rtol) || !isfinite(c->atol) ||
             c->rtol + c->atol <= 0.0)
@@ -113,6 +124,10 @@ Layout make_layout(const phx_config& c)
     L.partials = take((size_t)L.obs_blocks * OBS_SLOTS * sizeof(double));
     if (uses_step_index(c)) L.noise = take(sizeof(uint64_t));
     if (c.drive && c.integrator == PHX_RK4) L.drive_ph = take(4 * 2 * rs);
+    if (c.imag_time) {
+        L.imag = take(2 * sizeof(double));
+        L.imag_partials = take((size_t)imag_norm_blocks(c.nx * (int64_t)c.ny * c.components) * sizeof(double));
+    }
     if (c.integrator == PHX_RK4) {
         L.family = rk4_family(c);
         if (L.family == PHX_KERNEL_STEP) {
@@ -162,7 +177,7 @@ bool valid_step_shape(int precision, int waves, int rows)
 // written once) for one component, the stage-fused kernels otherwise or on request.
 int rk4_family(const phx_config& c)
 {
-    if (c.kernel == PHX_KERNEL_STAGE || c.drive) return PHX_KERNEL_STAGE;
+    if (c.kernel == PHX_KERNEL_STAGE || c.drive || c.imag_time) return PHX_KERNEL_STAGE;
     if (c.components == 1) return PHX_KERNEL_STEP;
     return PHX_KERNEL_STAGE;
 }
@@ -342,6 +357,7 @@ phx_status rk4_stage_launches(phx_handle* h, int64_t n, hipStream_t stream)
     a.n_io = n0;
     a.E = c.drive ? (const C*)h->f.E : nullptr;
     a.drive_ph = c.drive ? (const C*)(h->ws + L.drive_ph) : nullptr;
+    a.imag = c.imag_time;
     const R half_dt = (R)(0.5 * c.dt), full_dt = (R)c.dt;
     a.dt6 = (R)(c.dt / 6.0);
     const bool res = c.reservoir != 0, hv = h->f.V != nullptr;
@@ -365,6 +381,16 @@ phx_status rk4_stage_launches(phx_handle* h, int64_t n, hipStream_t stream)
             if (e == hipSuccess) e = launch_rk4_stage<R>(s + 1, res, hv, a, stream);
             if (e == hipSuccess) e = timing_end(h, t0, K_RK4_S1 + s);
             if (e != hipSuccess) return fail(PHX_EHIP, "RK4 stage %d launch: %s", s + 1, hipGetErrorString(e));
+        }
+        if (c.imag_time) {  // restore the call's starting norm
+            hipEvent_t t0 = nullptr;
+            hipError_t e = timing_begin(h, &t0);
+            if (e == hipSuccess) e = launch_imag_norm<R>(h, psi, 1, stream);
+            if (e == hipSuccess) e = timing_end(h, t0, K_IMAG_NORM);
+            if (e == hipSuccess) e = timing_begin(h, &t0);
+            if (e == hipSuccess) e = launch_imag_scale<R>(h, psi, stream);
+            if (e == hipSuccess) e = timing_end(h, t0, K_IMAG_SCALE);
+            if (e != hipSuccess) return fail(PHX_EHIP, "imaginary-time norm launch: %s", hipGetErrorString(e));
         }
         if (c.noise > 0.0) {
             hipEvent_t t0 = nullptr;
@@ -495,6 +521,11 @@ phx_status phx_step(phx_handle* h, int64_t n_steps, phx_info* out)
     }
     if (n_steps > 0) {
         phx_status s;
+        if (h->cfg.imag_time) {  // the norm every step of this call returns to
+            const hipError_t e = h->cfg.precision == PHX_C64 ? launch_imag_norm<float>(h, h->f.psi, 0, h->stream)
+                                                             : launch_imag_norm<double>(h, h->f.psi, 0, h->stream);
+            if (e != hipSuccess) return fail(PHX_EHIP, "imaginary-time norm launch: %s", hipGetErrorString(e));
+        }
         if (h->L.family == PHX_KERNEL_STEP)
             s = h->cfg.precision == PHX_C64 ? rk4_fused_steps<float>(h, n_steps) : rk4_fused_steps<double>(h, n_steps);
         else
@@ -630,7 +661,7 @@ const char* kernel_kind_name(int k)
     static const char* names[K_KINDS_] = {
         "rk4_stage1", "rk4_stage2", "rk4_stage3", "rk4_stage4", "observables",
         "dp_stage1", "dp_stage2", "dp_stage3", "dp_stage4", "dp_stage5", "dp_stage6",
-        "dp_stage7", "dp_error", "batch_stage", "rk4_step", "wiener_noise"};
+        "dp_stage7", "dp_error", "batch_stage", "rk4_step", "wiener_noise", "imag_norm", "imag_scale"};
     return (k >= 0 && k < K_KINDS_) ? names[k] : "unknown";
 }
 

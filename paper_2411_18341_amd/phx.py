@@ -43,7 +43,7 @@ class phx_config(ctypes.Structure):
         ("kernel", ctypes.c_int32), ("tile_wx", ctypes.c_int32), ("tile_rows", ctypes.c_int32),
         ("graph_steps", ctypes.c_int32),
         ("noise", ctypes.c_double), ("seed", ctypes.c_uint64),
-        ("drive_omega", ctypes.c_double), ("drive", ctypes.c_int32),
+        ("drive_omega", ctypes.c_double), ("drive", ctypes.c_int32), ("imag_time", ctypes.c_int32),
     ]
 
 
@@ -77,7 +77,7 @@ class phx_info(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
-PHX_MAX_KERNEL_KINDS = 16
+PHX_MAX_KERNEL_KINDS = 24
 
 
 class phx_timing(ctypes.Structure):
@@ -285,14 +285,14 @@ def make_config(nx, ny, dx, dy=None, *, bc_x=PHX_BC_PERIODIC, bc_y=PHX_BC_PERIOD
                 g_x=0.0, g_r=0.0, R=0.0, gamma_c=0.0, gamma_r=0.0, delta_lt=0.0, dt=1e-3,
                 rtol=1e-6, atol=1e-6, dt_min=1e-12, dt_max=float("inf"),
                 kernel=PHX_KERNEL_AUTO, tile_wx=0, tile_rows=0, graph_steps=0, noise=0.0,
-                seed=0, drive=False, drive_omega=0.0) -> phx_config:
+                seed=0, drive=False, drive_omega=0.0, imag_time=False) -> phx_config:
     return phx_config(int(nx), int(ny), float(dx), float(dx if dy is None else dy), int(bc_x), int(bc_y),
                       int(components), int(bool(reservoir)), int(precision), int(integrator),
                       float(hbar), float(mass), float(g), float(g_x), float(g_r), float(R),
                       float(gamma_c), float(gamma_r), float(delta_lt), float(dt), float(rtol),
                       float(atol), float(dt_min), float(dt_max), int(kernel), int(tile_wx),
                       int(tile_rows), int(graph_steps), float(noise), int(seed) & (2 ** 64 - 1),
-                      float(drive_omega), int(bool(drive)))
+                      float(drive_omega), int(bool(drive)), int(bool(imag_time)))
 
 
 def config_from_physics(ph, **kw) -> phx_config:

@@ -40,7 +40,7 @@ def _c_layout():
 #define F(T, m) printf(#T "." #m " %zu\n", offsetof(T, m));
 int main(void) {
   printf("phx_config %zu\n", sizeof(phx_config)); F(phx_config, dx) F(phx_config, bc_x) F(phx_config, hbar)
-  F(phx_config, delta_lt) F(phx_config, dt) F(phx_config, dt_max) F(phx_config, kernel) F(phx_config, tile_rows) F(phx_config, graph_steps) F(phx_config, noise) F(phx_config, seed) F(phx_config, drive_omega) F(phx_config, drive)
+  F(phx_config, delta_lt) F(phx_config, dt) F(phx_config, dt_max) F(phx_config, kernel) F(phx_config, tile_rows) F(phx_config, graph_steps) F(phx_config, noise) F(phx_config, seed) F(phx_config, drive_omega) F(phx_config, drive) F(phx_config, imag_time)
   printf("phx_fields %zu\n", sizeof(phx_fields)); F(phx_fields, workspace_bytes)
   printf("phx_obs %zu\n", sizeof(phx_obs)); F(phx_obs, energy) F(phx_obs, max_density) F(phx_obs, nonfinite) F(phx_obs, norm_renorm)
   printf("phx_info %zu\n", sizeof(phx_info)); F(phx_info, steps_rejected) F(phx_info, nonfinite)
@@ -103,7 +103,7 @@ def test_workspace_bytes_scale_with_precision_and_reservoir():
     ("reservoir", 2), ("precision", 5), ("integrator", 9), ("hbar", 0.0), ("mass", -1.0),
     ("g", float("inf")), ("dt", 0.0), ("dt", 1.0), ("kernel", 7),
     ("tile_wx", 3), ("tile_rows", 5), ("tile_rows", 65), ("noise", -1.0), ("noise", float("nan")),
-    ("drive", 2), ("drive_omega", float("inf")),
+    ("drive", 2), ("drive_omega", float("inf")), ("imag_time", 2),
 ])
 def test_invalid_config_rejected(field, value):
     cfg = good_config()
@@ -136,6 +136,26 @@ def test_drive_config_validation():
     assert e.value.status == phx.PHX_EUNSUPPORTED
     rk45 = phx.phx_workspace_bytes(good_config(integrator=phx.PHX_RK45))
     assert phx.phx_workspace_bytes(good_config(integrator=phx.PHX_RK45, drive=True)) == rk45
+
+
+def test_imag_time_config_validation():
+    """Imaginary time: the conservative equation on the stage-fused kernels; RK4's
+    stability bound on the negative real axis (2.78) replaces the imaginary-axis one."""
+    stage = phx.phx_workspace_bytes(good_config(kernel=phx.PHX_KERNEL_STAGE))
+    assert phx.phx_workspace_bytes(good_config(imag_time=True)) == stage + 256 + 256
+    for bad in (dict(reservoir=True), dict(gamma_c=0.1), dict(R=0.1), dict(noise=1.0), dict(drive=True)):
+        with pytest.raises(phx.PhxError) as e:
+            phx.phx_workspace_bytes(good_config(imag_time=True, **bad))
+        assert e.value.status == phx.PHX_EINVAL, bad
+    for bad in (dict(integrator=phx.PHX_RK45), dict(kernel=phx.PHX_KERNEL_STEP)):
+        with pytest.raises(phx.PhxError) as e:
+            phx.phx_workspace_bytes(good_config(imag_time=True, **bad))
+        assert e.value.status == phx.PHX_EUNSUPPORTED, bad
+    lam = 0.5 * 4 * (2 / 0.1 ** 2)  # hbar/2m * 4 (1/dx^2 + 1/dy^2)
+    phx.phx_workspace_bytes(good_config(dt=2.7 / lam))                 # real time: bound 2.83
+    phx.phx_workspace_bytes(good_config(dt=2.75 / lam, imag_time=True))
+    with pytest.raises(phx.PhxError):
+        phx.phx_workspace_bytes(good_config(dt=2.8 / lam, imag_time=True))
 
 
 def test_rk45_tolerance_validation():
