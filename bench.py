@@ -64,13 +64,15 @@ def copy_bandwidth_gbps(torch, nbytes=COPY_BYTES, reps=20):
     return 2.0 * nbytes * reps / dt / 1e9
 
 
-def cpu_baseline(ph, psi, n0, P, steps: int, noise: float = 0.0) -> dict:
+def cpu_baseline(ph, psi, n0, P, steps: int, noise: float = 0.0, imag: bool = False, V=None) -> dict:
     import oracle
     op = oracle.Physics(**{k: getattr(ph, k) for k in (
         "nx", "ny", "dx", "dy", "bc_x", "bc_y", "components", "reservoir", "hbar", "mass", "g",
         "g_x", "g_r", "R", "gamma_c", "gamma_r", "delta_lt")})
     t0 = time.perf_counter()
-    if noise > 0:
+    if imag:
+        oracle.rk4_imag(op, psi, V=V, dt=ph.dt, steps=steps)
+    elif noise > 0:
         oracle.rk4_noise(op, psi, n0, None, P, dt=ph.dt, steps=steps, nu=noise, seed=1)
     else:
         oracle.rk4(op, psi, n0, None, P, dt=ph.dt, steps=steps)
@@ -98,6 +100,9 @@ def main():
     ap.add_argument("--drive", type=float, default=None, metavar="OMEGA",
                     help="add a coherent drive of frequency OMEGA (a Gaussian spot, amplitude 0.8, width 30); "
                          "runs on the stage-fused kernels")
+    ap.add_argument("--imag", action="store_true",
+                    help="imaginary-time propagation of the trapped scalar GP (dx 0.01, dtau 5e-5) instead of "
+                         "the driven workload; runs on the stage-fused kernels")
     ap.add_argument("--tile", type=int, nargs=2, metavar=("WX", "ROWS"), default=None,
                     help="force this tile shape (no search)")
     args = ap.parse_args()
@@ -118,10 +123,18 @@ def main():
     precision = phx.PHX_C64 if args.precision == "c64" else phx.PHX_C128
     real_bytes = 4 if precision == phx.PHX_C64 else 8
 
-    ph, psi0, n0, P = inputs.driven(args.n)
-    workload = (f"driven-dissipative GP + reservoir, {args.n}x{args.n}, periodic, "
-                f"{'complex64 psi + float32 n' if real_bytes == 4 else 'complex128 psi + float64 n'}, "
-                f"ring pump 2 P_th (radius 20, width 3), RK4 dt {ph.dt}")
+    V0 = None
+    if args.imag:
+        ph, psi0, V0 = inputs.conservative(args.n, dx=0.01)
+        ph.dt = 5e-5
+        n0 = P = None
+        workload = (f"imaginary-time ground state of the scalar GP (g 1) in a harmonic trap, {args.n}x{args.n}, "
+                    f"zero boundary, {'complex64' if real_bytes == 4 else 'complex128'}, dx 0.01, RK4 dtau {ph.dt}")
+    else:
+        ph, psi0, n0, P = inputs.driven(args.n)
+        workload = (f"driven-dissipative GP + reservoir, {args.n}x{args.n}, periodic, "
+                    f"{'complex64 psi + float32 n' if real_bytes == 4 else 'complex128 psi + float64 n'}, "
+                    f"ring pump 2 P_th (radius 20, width 3), RK4 dt {ph.dt}")
     # the step kernel's counter record is the deterministic workload's: the noise is a separate pass
     step_workload = workload
     if args.noise > 0:
@@ -135,14 +148,15 @@ def main():
     cdt, rdt = phx.torch_dtypes(precision)
     dev = torch.device("cuda:0")
     psi = torch.from_numpy(psi0).to(dtype=cdt, device=dev).contiguous()
-    n = torch.from_numpy(n0).to(dtype=rdt, device=dev).contiguous()
-    Pd = torch.from_numpy(P).to(dtype=rdt, device=dev).contiguous()
+    n = None if n0 is None else torch.from_numpy(n0).to(dtype=rdt, device=dev).contiguous()
+    Pd = None if P is None else torch.from_numpy(P).to(dtype=rdt, device=dev).contiguous()
+    Vd = None if V0 is None else torch.from_numpy(V0).to(dtype=rdt, device=dev).contiguous()
     family = {"auto": phx.PHX_KERNEL_AUTO, "stage": phx.PHX_KERNEL_STAGE, "step": phx.PHX_KERNEL_STEP}[args.kernel]
     cfg = phx.config_from_physics(ph, precision=precision, kernel=family, noise=args.noise, seed=1,
-                                  drive=E is not None, drive_omega=args.drive or 0.0)
+                                  drive=E is not None, drive_omega=args.drive or 0.0, imag_time=args.imag)
     if args.tile:
         cfg.tile_wx, cfg.tile_rows = args.tile
-    solver = phx.Solver(cfg, psi, n, None, Pd, E=E)
+    solver = phx.Solver(cfg, psi, n, Vd, Pd, E=E)
     if args.tile:
         tune = {"tile_wx": args.tile[0], "tile_rows": args.tile[1]}
     else:
@@ -164,11 +178,14 @@ def main():
 
     cells = args.n * args.n
     value = cells * args.steps / wall
-    stage_model = bytemodel.rk4_stage_fused(real_bytes, reservoir=True, has_v=False, drive=E is not None)
-    step_model = bytemodel.rk4_whole_step(real_bytes, reservoir=True, has_v=False)
+    res = not args.imag
+    stage_model = bytemodel.rk4_stage_fused(real_bytes, reservoir=res, has_v=args.imag, drive=E is not None)
+    step_model = bytemodel.rk4_whole_step(real_bytes, reservoir=res, has_v=args.imag)
     per_launch = {f"rk4_stage{s}": stage_model[f"stage{s}"] for s in range(1, 5)}
     per_launch["rk4_step"] = step_model["step"]
     per_launch["wiener_noise"] = bytemodel.wiener_noise(real_bytes, reservoir=True)
+    per_launch["imag_norm"] = bytemodel.imag_norm(real_bytes)["norm"]
+    per_launch["imag_scale"] = bytemodel.imag_norm(real_bytes)["scale"]
     kernels = {}
     for name, t in times.items():
         if name not in per_launch:
@@ -181,8 +198,9 @@ def main():
     d = kernels[dom]
     # counter measurements of the whole-step kernel are kept per region shape
     shape_key = dom if dom != "rk4_step" or tune is None else f"rk4_step_{tune['tile_wx']}x{tune['tile_rows']}"
-    # the drive changes what the stage kernels read: its counter record is a separate file
-    traffic = measured_traffic(shape_key, step_workload) if args.drive is None else None
+    # the drive and imaginary time change what the stage kernels read: their counter records
+    # are separate files
+    traffic = measured_traffic(shape_key, step_workload) if args.drive is None and not args.imag else None
     roofline = {"bound": "hbm", "achieved": round(d["GBps"], 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                 "frac": round(d["GBps"] / HBM_PEAK_GBPS, 4), "traffic": traffic,
                 "kernel": shape_key, "bytes_per_launch": d["bytes_per_launch"],
@@ -191,11 +209,13 @@ def main():
     step_bytes = step_model["step"] if dom == "rk4_step" else stage_model["step"]
     if args.noise > 0:
         step_bytes += per_launch["wiener_noise"]
+    if args.imag:
+        step_bytes += per_launch["imag_norm"] + per_launch["imag_scale"]
     step_gbps = step_bytes * cells * args.steps / wall / 1e9
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(ph, psi0, n0, P, args.cpu_steps, args.noise)
+        cpu = cpu_baseline(ph, psi0, n0, P, args.cpu_steps, args.noise, args.imag, V0)
 
     line = {
         "metric": METRIC, "value": value, "unit": "UP/s", "n_gpus": 1, "steps": args.steps,
@@ -203,7 +223,7 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f32" if real_bytes == 4 else "f64",
         "data": "synthetic",
         "config": {"workload": workload, "grid": [args.n, args.n], "integrator": "rk4", "noise": args.noise,
-                   "drive_omega": args.drive,
+                   "drive_omega": args.drive, "imag_time": args.imag,
                    "kernel_family": family_name,
                    "tile": None if tune is None else [tune["tile_wx"], tune["tile_rows"]]},
         "roofline": roofline,

@@ -75,3 +75,10 @@ def wiener_noise(real_bytes: int, reservoir: bool, components: int = 1) -> int:
     """Bytes per point of the Wiener-increment pass: every complex value is read and
     written once, the reservoir (the amplitude's n) is read once."""
     return components * (4 * real_bytes + (real_bytes if reservoir else 0))
+
+
+def imag_norm(real_bytes: int, components: int = 1) -> dict:
+    """Bytes per point of the imaginary-time norm restoration: the partial sums read
+    the complex state once, the scale pass reads and writes it once."""
+    c = 2 * real_bytes * components
+    return {"norm": c, "scale": 2 * c}

@@ -38,12 +38,22 @@ __global__ __launch_bounds__(256) void norm_partials_kernel(const typename phx::
 {
     const int64_t lo = (int64_t)blockIdx.x * chunk;
     const int64_t hi = lo + chunk < M ? lo + chunk : M;
-    double s = 0.0;
-    for (int64_t q = lo + threadIdx.x; q < hi; q += 256) {
-        const double x = psi[q].x, y = psi[q].y;
-        s += x * x + y * y;
+    // four independent loads and sums per iteration keep enough reads in flight;
+    // the combination order is fixed, so the result does not depend on timing
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int64_t q = lo + threadIdx.x;
+    for (; q + 768 < hi; q += 1024) {
+        const auto a = psi[q], b = psi[q + 256], c = psi[q + 512], d = psi[q + 768];
+        s0 += (double)a.x * a.x + (double)a.y * a.y;
+        s1 += (double)b.x * b.x + (double)b.y * b.y;
+        s2 += (double)c.x * c.x + (double)c.y * c.y;
+        s3 += (double)d.x * d.x + (double)d.y * d.y;
     }
-    s = block_sum_256(s);
+    for (; q < hi; q += 256) {
+        const auto a = psi[q];
+        s0 += (double)a.x * a.x + (double)a.y * a.y;
+    }
+    double s = block_sum_256((s0 + s1) + (s2 + s3));
     if (threadIdx.x == 0) partials[blockIdx.x] = s;
 }
 
