@@ -264,6 +264,9 @@ typedef struct phx_instance {
     int32_t param_index;    /* index into phx_batch_desc.params                         */
     int32_t reserved;       /* must be 0                                                */
     int64_t offset;         /* element offset of this instance in psi, n, P and V       */
+    uint64_t seed;          /* Wiener-noise key of this instance (used when its params
+                               have noise > 0): it draws what a single-grid handle with
+                               this seed draws                                           */
 } phx_instance;
 
 typedef struct phx_batch_desc {
@@ -280,6 +283,9 @@ typedef struct phx_batch_desc {
     const void *V;          /* packed real potential [total_cells], or NULL for V = 0   */
     void *workspace;        /* scratch of at least phx_batch_workspace_bytes, 256-B aligned */
     size_t workspace_bytes;
+    int64_t step0;          /* noise step index of the first step of this call (step k of
+                               the call draws index step0 + k, like a single-grid handle
+                               whose steps_accepted is step0); the caller advances it      */
 } phx_batch_desc;
 
 /* Workspace bytes phx_batch_step needs for this descriptor (host-only). */

@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <vector>
 
+#include "philox.h"
 #include "runtime.h"
 #include "step_body.h"
 
@@ -23,7 +24,38 @@ struct BatchInst {
     int64_t offset;      // element offset in the packed arrays
     Coef<R> c;
     R half_dt, dt, dt6;
+    // Wiener noise: amplitude^2 = noise_a n + noise_b, key, first cell pair of this
+    // instance in the concatenated pair list of the noise pass
+    R noise_a, noise_b;
+    uint32_t key0, key1;
+    int64_t pair0;
 };
+
+// Wiener increments of one batched step: one thread per cell pair of every instance
+// (pairs concatenated in instance order), the same counters and transform as a
+// single-grid handle with the instance's seed.
+template <typename R, bool RES>
+__global__ __launch_bounds__(256) void batch_noise_kernel(const BatchInst<R>* __restrict__ inst, int count,
+                                                          int64_t total_pairs, typename cvec<R>::type* psi,
+                                                          const R* n, uint64_t step)
+{
+    const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (g >= total_pairs) return;
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (inst[mid].pair0 <= g) lo = mid; else hi = mid - 1;
+    }
+    const BatchInst<R>& I = inst[lo];
+    if (I.noise_a == (R)0 && I.noise_b == (R)0) return;
+    const int64_t p = g - I.pair0;
+    const int64_t q = 2 * p;
+    const int64_t cells = (int64_t)I.nx * I.ny;
+    const noise::Philox4 x = noise::philox4x32_10((uint32_t)p, 0u, (uint32_t)step, (uint32_t)(step >> 32), I.key0,
+                                                  I.key1);
+    const int64_t k = I.offset + q;
+    noise::noise_pair<R, RES>(psi + k, RES ? n + k : nullptr, q + 1 < cells, (k & 1) == 0, I.noise_a, I.noise_b, x);
+}
 
 template <typename R, bool RES, bool HASV, bool GHOSTS, int WAVES, int ROWS>
 __global__ __launch_bounds__(WAVES * 64) void batch_step_kernel(
@@ -120,6 +152,7 @@ static phx_status validate_batch(const phx_batch_desc* d)
     if (!d->instances || !d->params || d->n_params < 1) return fail(PHX_EINVAL, "instances and params required");
     if (d->check_finite != 0 && d->check_finite != 1) return fail(PHX_EINVAL, "check_finite must be 0 or 1");
     if (d->total_cells < 1 || d->total_cells >= ((int64_t)1 << 40)) return fail(PHX_EINVAL, "bad total_cells");
+    if (d->step0 < 0) return fail(PHX_EINVAL, "step0 must be >= 0");
     const int res = d->params[0].reservoir;
     for (int k = 0; k < d->n_params; ++k) {
         phx_config c = d->params[k];
@@ -131,7 +164,6 @@ static phx_status validate_batch(const phx_batch_desc* d)
         c.tile_wx = c.tile_rows = 0;
         phx_status s = validate_config(&c);
         if (s != PHX_OK) return s;
-        if (c.noise != 0.0) return fail(PHX_EUNSUPPORTED, "Wiener noise is not implemented for batches");
         if (c.drive != 0) return fail(PHX_EUNSUPPORTED, "the coherent drive is not implemented for batches");
         if (c.imag_time != 0) return fail(PHX_EUNSUPPORTED, "imaginary time is not implemented for batches");
         if (c.reservoir != res) return fail(PHX_EINVAL, "all params must share the reservoir flag");
@@ -179,7 +211,8 @@ static phx_status batch_run(const phx_batch_desc* d, int64_t n, hipStream_t stre
     const int res = d->params[0].reservoir;
     std::vector<BatchInst<R>> table(d->count);
     int tile0 = 0;
-    bool ghosts = false;
+    int64_t pairs = 0;
+    bool ghosts = false, noisy = false;
     for (int k = 0; k < d->count; ++k) {
         const phx_instance& I = d->instances[k];
         phx_config c = d->params[I.param_index];
@@ -199,6 +232,14 @@ static phx_status batch_run(const phx_batch_desc* d, int64_t n, hipStream_t stre
         b.dt6 = (R)(c.dt / 6.0);
         tile0 += b.tiles_x * ((I.ny + BW * BR - 9) / (BW * BR - 8));
         ghosts = ghosts || c.bc_x == PHX_BC_ZERO || c.bc_y == PHX_BC_ZERO;
+        const double scale = c.noise * c.dt / (4.0 * c.dx * c.dy);  // as the single-grid pass forms it
+        b.noise_a = (R)(scale * c.R);
+        b.noise_b = (R)(scale * c.gamma_c);
+        b.key0 = (uint32_t)I.seed;
+        b.key1 = (uint32_t)(I.seed >> 32);
+        b.pair0 = pairs;
+        pairs += ((int64_t)I.nx * I.ny + 1) / 2;
+        noisy = noisy || c.noise > 0.0;
     }
     const int total = tile0;
     hipError_t e = hipMemcpyAsync(ws + L.table, table.data(), table.size() * sizeof(BatchInst<R>),
@@ -239,6 +280,19 @@ static phx_status batch_run(const phx_batch_desc* d, int64_t n, hipStream_t stre
                             S[cur ^ 1], SN[cur ^ 1], d->V, d->P, flag, stream);
         if (e != hipSuccess) return fail(PHX_EHIP, "batch step launch: %s", hipGetErrorString(e));
         cur ^= 1;
+        if (noisy) {
+            using C = typename cvec<R>::type;
+            const unsigned blocks = (unsigned)((pairs + 255) / 256);
+            const uint64_t step = (uint64_t)(d->step0 + k);
+            if (res)
+                batch_noise_kernel<R, true><<<blocks, 256, 0, stream>>>(dtab, d->count, pairs, (C*)S[cur],
+                                                                        (const R*)SN[cur], step);
+            else
+                batch_noise_kernel<R, false><<<blocks, 256, 0, stream>>>(dtab, d->count, pairs, (C*)S[cur],
+                                                                         nullptr, step);
+            e = hipGetLastError();
+            if (e != hipSuccess) return fail(PHX_EHIP, "batch noise launch: %s", hipGetErrorString(e));
+        }
     }
     if (d->check_finite) {
         unsigned int v = 0;

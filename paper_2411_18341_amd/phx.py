@@ -101,7 +101,7 @@ class phx_tune_result(ctypes.Structure):
 
 class phx_instance(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("param_index", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("offset", ctypes.c_int64)]
+                ("reserved", ctypes.c_int32), ("offset", ctypes.c_int64), ("seed", ctypes.c_uint64)]
 
 
 class phx_batch_desc(ctypes.Structure):
@@ -111,7 +111,7 @@ class phx_batch_desc(ctypes.Structure):
                 ("total_cells", ctypes.c_int64),
                 ("psi", ctypes.c_void_p), ("n", ctypes.c_void_p), ("P", ctypes.c_void_p),
                 ("V", ctypes.c_void_p), ("workspace", ctypes.c_void_p),
-                ("workspace_bytes", ctypes.c_size_t)]
+                ("workspace_bytes", ctypes.c_size_t), ("step0", ctypes.c_int64)]
 
 
 class phx_cnn_config(ctypes.Structure):
@@ -441,7 +441,7 @@ class Batch:
     psi[offsets[k] : offsets[k] + nx*ny] (row-major), likewise n, P, V."""
 
     def __init__(self, grids, params, param_index=None, precision=PHX_C64, device="cuda:0",
-                 with_v=False, check_finite=False):
+                 with_v=False, check_finite=False, seeds=None):
         import torch
         self.torch = torch
         self.grids = [(int(a), int(b)) for a, b in grids]
@@ -460,8 +460,10 @@ class Batch:
         self.P = torch.zeros(o, dtype=rdt, device=device) if res else None
         self.V = torch.zeros(o, dtype=rdt, device=device) if with_v else None
         pidx = param_index if param_index is not None else [0] * len(self.grids)
+        sd = seeds if seeds is not None else [0] * len(self.grids)
         self._inst = (phx_instance * len(self.grids))(*[
-            phx_instance(nx, ny, int(p), 0, off) for (nx, ny), p, off in zip(self.grids, pidx, offs)])
+            phx_instance(nx, ny, int(p), 0, off, int(s) & (2 ** 64 - 1))
+            for (nx, ny), p, off, s in zip(self.grids, pidx, offs, sd)])
         self._params = (phx_config * len(params))(*params)
         ptr = lambda t: None if t is None else t.data_ptr()
         self.desc = phx_batch_desc(len(self.grids), precision, self._inst, self._params, len(params),
@@ -486,8 +488,10 @@ class Batch:
         return t[:len(self.grids) * nx * ny].view(len(self.grids) * ny, nx)
 
     def step(self, n_steps: int, stream=None):
+        """n_steps batched steps; the noise step index (desc.step0) runs on across calls."""
         s = stream if stream is not None else self.torch.cuda.current_stream(self.psi.device)
         phx_batch_step(self.desc, n_steps, s.cuda_stream)
+        self.desc.step0 += n_steps
 
 
 # ------------------------------------------------------------ learned corrector

@@ -46,9 +46,9 @@ int main(void) {
   printf("phx_info %zu\n", sizeof(phx_info)); F(phx_info, steps_rejected) F(phx_info, nonfinite)
   printf("phx_timing %zu\n", sizeof(phx_timing)); F(phx_timing, launches) F(phx_timing, ms_total)
   printf("phx_tune_result %zu\n", sizeof(phx_tune_result)); F(phx_tune_result, best_us) F(phx_tune_result, default_us)
-  printf("phx_instance %zu\n", sizeof(phx_instance)); F(phx_instance, offset)
+  printf("phx_instance %zu\n", sizeof(phx_instance)); F(phx_instance, offset) F(phx_instance, seed)
   printf("phx_batch_desc %zu\n", sizeof(phx_batch_desc)); F(phx_batch_desc, params) F(phx_batch_desc, psi)
-  F(phx_batch_desc, workspace_bytes) F(phx_fields, E)
+  F(phx_batch_desc, workspace_bytes) F(phx_fields, E) F(phx_batch_desc, step0)
   return 0; }
 '''
     return prog

@@ -198,3 +198,53 @@ def test_vacuum_occupation_and_renormalized_density(family):
         assert obs["norm_renorm"][0] == pytest.approx(obs["norm"][0] - nu * n * n / 2, rel=1e-12)
     assert abs(obs["norm_renorm"][0]) < 0.02 * nu * n * n / 2
     run.close()
+
+
+@pytest.mark.parametrize("precision", [C64, C128])
+def test_batch_noise_parity(precision):
+    """Noisy ensembles in one batched launch per step: instances of different sizes,
+    each with its own seed, one parameter set without noise; two calls (the noise step
+    index runs on through the descriptor).  Every instance equals the oracle's noisy
+    run with its seed, and instance 0 equals a single-grid handle with that seed bit
+    for bit (the same region kernel and the same increments)."""
+    import torch
+    grids = [(97, 61), (64, 64), (33, 70), (128, 40), (51, 50)]
+    pidx = [0, 0, 1, 0, 0]
+    seeds = [11, 12, 13, (1 << 40) + 5, 99]
+    nu = 0.8
+    ph0 = workload("driven", 8, 8, (0, 0))[0]
+    cfgs = [phx.config_from_physics(ph0, precision=precision, noise=nu),
+            phx.config_from_physics(ph0, precision=precision)]
+    b = phx.Batch(grids, cfgs, pidx, precision=precision, seeds=seeds)
+    cases = []
+    for k, (nx, ny) in enumerate(grids):
+        ph, psi, n, V, P = workload("driven", nx, ny, (0, 0), seed=20 + k)
+        q = quantize(precision, psi, n, None, P)
+        b.view(b.psi, k).copy_(torch.from_numpy(q[0][0]).to(b.psi.dtype))
+        b.view(b.n, k).copy_(torch.from_numpy(q[1][0]).to(b.n.dtype))
+        b.view(b.P, k).copy_(torch.from_numpy(q[3][0]).to(b.P.dtype))
+        cases.append((ph, q))
+    b.step(3)
+    b.step(2)
+    torch.cuda.synchronize()
+    assert b.desc.step0 == 5
+    for k, (ph, q) in enumerate(cases):
+        g_psi = b.view(b.psi, k).cpu().numpy().astype(np.complex128)[None]
+        g_n = b.view(b.n, k).cpu().numpy().astype(np.float64)[None]
+        knu = nu if pidx[k] == 0 else 0.0
+        o_psi, o_n = oracle.rk4_noise(oracle_physics(ph), q[0], q[1], None, q[3], dt=ph.dt, steps=5, nu=knu,
+                                      seed=seeds[k], step0=0)
+        e_psi, e_n = rel_l2(g_psi, o_psi), rel_l2(g_n, o_n)
+        print(f"batch instance {k} {grids[k]} nu={knu}: psi {e_psi:.3e} n {e_n:.3e}")
+        assert e_psi <= TOL[precision] and e_n <= TOL[precision]
+    ph, q = cases[0]
+    single = GpuRun(ph, *q, precision=precision, noise=nu, seed=seeds[0], kernel=phx.PHX_KERNEL_STEP,
+                    tile_wx=8, tile_rows=4)
+    single.step(5)
+    s_psi, s_n = single.state()
+    single.close()
+    assert np.array_equal(s_psi[0], b.view(b.psi, 0).cpu().numpy().astype(np.complex128))
+    assert np.array_equal(s_n[0], b.view(b.n, 0).cpu().numpy().astype(np.float64))
+    b_noisy = b.view(b.psi, 2).cpu().numpy()
+    d_psi, _ = oracle.rk4(oracle_physics(cases[2][0]), *cases[2][1], dt=ph.dt, steps=5)
+    assert rel_l2(b_noisy.astype(np.complex128)[None], d_psi) <= TOL[precision]  # the nu = 0 instance
