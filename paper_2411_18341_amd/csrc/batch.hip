@@ -24,33 +24,27 @@ struct BatchInst {
     int64_t offset;      // element offset in the packed arrays
     Coef<R> c;
     R half_dt, dt, dt6;
-    // Wiener noise: amplitude^2 = noise_a n + noise_b, key, first cell pair of this
-    // instance in the concatenated pair list of the noise pass
+    // Wiener noise: amplitude^2 = noise_a n + noise_b, key, first workgroup of this
+    // instance in the noise pass (each instance's cell pairs fill whole workgroups)
     R noise_a, noise_b;
     uint32_t key0, key1;
-    int64_t pair0;
+    int block0;
 };
 
-// Wiener increments of one batched step: one thread per cell pair of every instance
-// (pairs concatenated in instance order), the same counters and transform as a
-// single-grid handle with the instance's seed.
+// Wiener increments of one batched step: one thread per cell pair, each instance's
+// pairs in whole workgroups (block_inst maps a workgroup to its instance), the same
+// counters and transform as a single-grid handle with the instance's seed.
 template <typename R, bool RES>
-__global__ __launch_bounds__(256) void batch_noise_kernel(const BatchInst<R>* __restrict__ inst, int count,
-                                                          int64_t total_pairs, typename cvec<R>::type* psi,
-                                                          const R* n, uint64_t step)
+__global__ __launch_bounds__(256) void batch_noise_kernel(const BatchInst<R>* __restrict__ inst,
+                                                          const int* __restrict__ block_inst,
+                                                          typename cvec<R>::type* psi, const R* n, uint64_t step)
 {
-    const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (g >= total_pairs) return;
-    int lo = 0, hi = count - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (inst[mid].pair0 <= g) lo = mid; else hi = mid - 1;
-    }
-    const BatchInst<R>& I = inst[lo];
+    const BatchInst<R>& I = inst[block_inst[blockIdx.x]];
     if (I.noise_a == (R)0 && I.noise_b == (R)0) return;
-    const int64_t p = g - I.pair0;
+    const int64_t p = (int64_t)(blockIdx.x - I.block0) * 256 + threadIdx.x;
     const int64_t q = 2 * p;
     const int64_t cells = (int64_t)I.nx * I.ny;
+    if (q >= cells) return;
     const noise::Philox4 x = noise::philox4x32_10((uint32_t)p, 0u, (uint32_t)step, (uint32_t)(step >> 32), I.key0,
                                                   I.key1);
     const int64_t k = I.offset + q;
@@ -125,8 +119,11 @@ static hipError_t launch_batch(bool res, bool hv, bool ghosts, int grid, const B
 }
 
 struct BatchLayout {
-    size_t table, alt, alt_n, flag, total;
+    size_t table, block_inst, alt, alt_n, flag, total;
 };
+
+// Workgroups of the noise pass: each instance's cell pairs in whole workgroups of 256.
+static int64_t noise_blocks_bound(const phx_batch_desc& d) { return d.total_cells / 512 + d.count + 1; }
 
 static BatchLayout batch_layout(const phx_batch_desc& d)
 {
@@ -137,6 +134,7 @@ static BatchLayout batch_layout(const phx_batch_desc& d)
     auto take = [&](size_t b) { size_t o = off; off += align_up(b); return o; };
     L.flag = take(256);
     L.table = take((size_t)d.count * inst_bytes);
+    L.block_inst = take((size_t)noise_blocks_bound(d) * sizeof(int));
     L.alt = take((size_t)d.total_cells * 2 * rs);
     const bool res = d.params && d.n_params > 0 && d.params[0].reservoir;
     L.alt_n = res ? take((size_t)d.total_cells * rs) : 0;
@@ -211,7 +209,7 @@ static phx_status batch_run(const phx_batch_desc* d, int64_t n, hipStream_t stre
     const int res = d->params[0].reservoir;
     std::vector<BatchInst<R>> table(d->count);
     int tile0 = 0;
-    int64_t pairs = 0;
+    std::vector<int> block_inst;
     bool ghosts = false, noisy = false;
     for (int k = 0; k < d->count; ++k) {
         const phx_instance& I = d->instances[k];
@@ -237,13 +235,17 @@ static phx_status batch_run(const phx_batch_desc* d, int64_t n, hipStream_t stre
         b.noise_b = (R)(scale * c.gamma_c);
         b.key0 = (uint32_t)I.seed;
         b.key1 = (uint32_t)(I.seed >> 32);
-        b.pair0 = pairs;
-        pairs += ((int64_t)I.nx * I.ny + 1) / 2;
+        b.block0 = (int)block_inst.size();
+        const int64_t nb = (((int64_t)I.nx * I.ny + 1) / 2 + 255) / 256;
+        block_inst.insert(block_inst.end(), (size_t)nb, k);
         noisy = noisy || c.noise > 0.0;
     }
     const int total = tile0;
     hipError_t e = hipMemcpyAsync(ws + L.table, table.data(), table.size() * sizeof(BatchInst<R>),
                                   hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess && noisy)
+        e = hipMemcpyAsync(ws + L.block_inst, block_inst.data(), block_inst.size() * sizeof(int),
+                           hipMemcpyHostToDevice, stream);
     if (e == hipSuccess) e = hipMemsetAsync(ws + L.flag, 0, 256, stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);  // the host table may go out of scope
     if (e != hipSuccess) return fail(PHX_EHIP, "batch table upload: %s", hipGetErrorString(e));
@@ -282,14 +284,14 @@ static phx_status batch_run(const phx_batch_desc* d, int64_t n, hipStream_t stre
         cur ^= 1;
         if (noisy) {
             using C = typename cvec<R>::type;
-            const unsigned blocks = (unsigned)((pairs + 255) / 256);
+            const unsigned blocks = (unsigned)block_inst.size();
+            const int* bi = (const int*)(ws + L.block_inst);
             const uint64_t step = (uint64_t)(d->step0 + k);
             if (res)
-                batch_noise_kernel<R, true><<<blocks, 256, 0, stream>>>(dtab, d->count, pairs, (C*)S[cur],
-                                                                        (const R*)SN[cur], step);
+                batch_noise_kernel<R, true><<<blocks, 256, 0, stream>>>(dtab, bi, (C*)S[cur], (const R*)SN[cur],
+                                                                        step);
             else
-                batch_noise_kernel<R, false><<<blocks, 256, 0, stream>>>(dtab, d->count, pairs, (C*)S[cur],
-                                                                         nullptr, step);
+                batch_noise_kernel<R, false><<<blocks, 256, 0, stream>>>(dtab, bi, (C*)S[cur], nullptr, step);
             e = hipGetLastError();
             if (e != hipSuccess) return fail(PHX_EHIP, "batch noise launch: %s", hipGetErrorString(e));
         }

@@ -18,7 +18,7 @@ grids of 128..1024 (one persistent launch per step) against stepping the same
 instances with one solver each; with --spinor the 4096^2 two-component workload
 with RK4 and with Dormand-Prince; with --noise the 4096^2 driven workload with the
 truncated-Wigner noise on and off; with --drive the stage-fused kernels with and without
-the coherent drive.
+the coherent drive; with --ensemble a batched noisy Monte Carlo ensemble.
 """
 from __future__ import annotations
 
@@ -264,6 +264,31 @@ def measure_drive(n: int = 4096, omega: float = 1.3, steps: int = 100, warmup: i
     return out
 
 
+def measure_ensemble(count: int = 128, n: int = 256, nu: float = 1.0, steps: int = 400, warmup: int = 20):
+    """A Monte Carlo ensemble of the truncated-Wigner form: `count` copies of the
+    driven workload on n x n grids (complex64), each with its own noise seed, stepped
+    by one batched launch per step plus one noise pass over all instances; against the
+    same batch without noise.  Reports point updates per second of the ensemble."""
+    import torch
+    ph, psi0, n0, P = inputs.driven(n)
+    out = {"count": count, "n": n, "nu": nu}
+    for label, noise in (("deterministic", 0.0), ("noisy", nu)):
+        cfg = phx.config_from_physics(ph, precision=phx.PHX_C64, noise=noise)
+        b = phx.Batch([(n, n)] * count, [cfg], precision=phx.PHX_C64, seeds=list(range(1000, 1000 + count)))
+        for k in range(count):
+            b.view(b.psi, k).copy_(torch.from_numpy(psi0[0]).to(torch.complex64))
+            b.view(b.n, k).copy_(torch.from_numpy(n0[0]).to(torch.float32))
+            b.view(b.P, k).copy_(torch.from_numpy(P[0]).to(torch.float32))
+        b.step(warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b.step(steps)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        out[label] = {"UPs": count * n * n * steps / wall, "us_per_step": wall / steps * 1e6}
+    return out
+
+
 def table(rows) -> str:
     out = ["| N | family | tile | steps | µs/step | G UP/s | algorithmic GB/s | mean launch µs per kernel |",
            "|---|---|---|---|---|---|---|---|"]
@@ -283,7 +308,14 @@ def main():
     ap.add_argument("--spinor", action="store_true", help="also measure the 4096^2 spinor workload (RK4, RK45)")
     ap.add_argument("--noise", action="store_true", help="also measure the 4096^2 driven workload with Wiener noise")
     ap.add_argument("--drive", action="store_true", help="also measure the stage-fused kernels with a coherent drive")
+    ap.add_argument("--ensemble", action="store_true", help="also measure a batched noisy ensemble (128 x 256^2)")
     args = ap.parse_args()
+    if args.ensemble:
+        r = measure_ensemble()
+        print(json.dumps({"ensemble": r}), flush=True)
+        if args.out:
+            with open(args.out + ".ensemble.json", "w") as f:
+                json.dump(r, f, indent=1)
     if args.drive:
         r = measure_drive()
         print(json.dumps({"drive": r}), flush=True)
