@@ -6,7 +6,9 @@
 // norms come from the same deterministic two-pass FP64 reduction: fixed contiguous
 // chunks per workgroup, a fixed lane and wave order inside it, then one workgroup
 // over the partials in index order.  The scale lives in device memory, so the step
-// sequence can be captured and replayed as a graph.  Passes: the partial sums read
+// sequence can be captured and replayed as a graph.  The streaming whole-step kernel
+// instead writes one partial per wave and applies the scale to its next input; the
+// finish kernel and the final scale pass are shared.  Passes: the partial sums read
 // psi (8 B/pt complex64), the scale reads and writes it (16 B/pt); both are bound by
 // HBM.
 #include <hip/hip_runtime.h>
@@ -57,7 +59,8 @@ __global__ __launch_bounds__(256) void norm_partials_kernel(const typename phx::
     if (threadIdx.x == 0) partials[blockIdx.x] = s;
 }
 
-// mode 0: slots[0] = N (the target of the call); mode 1: slots[1] = sqrt(slots[0] / N).
+// mode 0: slots[0] = N (the target of the call) and slots[1] = 1; mode 1:
+// slots[1] = sqrt(slots[0] / N).
 __global__ __launch_bounds__(256) void norm_finish_kernel(const double* __restrict__ partials, int blocks,
                                                           double cell_area, int mode, double* __restrict__ slots)
 {
@@ -66,9 +69,10 @@ __global__ __launch_bounds__(256) void norm_finish_kernel(const double* __restri
     s = block_sum_256(s);
     if (threadIdx.x == 0) {
         const double N = cell_area * s;
-        if (mode == 0)
+        if (mode == 0) {
             slots[0] = N;
-        else
+            slots[1] = 1.0;
+        } else
             slots[1] = N > 0.0 ? sqrt(slots[0] / N) : 1.0;
     }
 }
@@ -111,6 +115,13 @@ hipError_t launch_imag_norm(const phx_handle* h, const void* psi, int mode, hipS
                        (const typename cvec<R>::type*)psi, M, chunk, partials);
     hipLaunchKernelGGL(norm_finish_kernel, dim3(1), dim3(256), 0, s, (const double*)partials, blocks, c.dx * c.dy,
                        mode, slots);
+    return hipGetLastError();
+}
+
+hipError_t launch_imag_finish(const phx_handle* h, int count, hipStream_t s)
+{
+    hipLaunchKernelGGL(norm_finish_kernel, dim3(1), dim3(256), 0, s, (const double*)(h->ws + h->L.imag_partials),
+                       count, h->cfg.dx * h->cfg.dy, 1, (double*)(h->ws + h->L.imag));
     return hipGetLastError();
 }
 

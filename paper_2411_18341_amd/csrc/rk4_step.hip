@@ -33,16 +33,28 @@ __global__ __launch_bounds__(WAVES * 64) void rk4_step_kernel(const StepArgs<R> 
 // Streaming form: a workgroup is 4 adjacent strips of one band of B rows (their
 // x-halo columns are read through one L1); a.tiles_x counts strips, a.tiles
 // workgroups.  Waves past the last strip leave at once (the kernel has no barrier).
-template <typename R, bool RES, bool HASV, bool GHOSTS, bool YZERO, int B>
+// IMAG (imaginary time): wave w of tile t writes the FP64 norm partial of its cells
+// to a.imag_partials[4 t + w] (0 for a wave past the last strip), reduced over the
+// lanes in a fixed butterfly order.
+template <typename R, bool RES, bool HASV, bool GHOSTS, bool YZERO, int B, bool IMAG>
 __global__ __launch_bounds__(256) void rk4_stream_kernel(const StepArgs<R> a)
 {
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int t = xcd_tile(blockIdx.x, gridDim.x);
     const int groups_x = (a.tiles_x + 3) / 4;
     const int band = t / groups_x, strip = (t - band * groups_x) * 4 + wave;
-    if (strip >= a.tiles_x) return;
-    if (stream_band<R, RES, HASV, GHOSTS, YZERO, B>(a, strip, band, (band & 1) ? -1 : 1))
+    if (strip >= a.tiles_x) {
+        if (IMAG && (threadIdx.x & 63) == 0) a.imag_partials[4 * t + wave] = 0.0;
+        return;
+    }
+    double nrm = 0.0;
+    if (stream_band<R, RES, HASV, GHOSTS, YZERO, B, IMAG>(a, strip, band, (band & 1) ? -1 : 1, &nrm))
         a.flag[0] = 1u;  // benign race
+    if constexpr (IMAG) {
+#pragma unroll
+        for (int m = 32; m >= 1; m >>= 1) nrm += __shfl_xor(nrm, m, 64);
+        if ((threadIdx.x & 63) == 0) a.imag_partials[4 * t + wave] = nrm;
+    }
 }
 
 // GHOSTS: some boundary is zero, so region cells outside the grid must be held at 0
@@ -53,12 +65,23 @@ static hipError_t launch_step_t(const StepArgs<R>& a, hipStream_t s)
 {
     const bool ghosts = a.bcx == PHX_BC_ZERO || a.bcy == PHX_BC_ZERO;
     if constexpr (WAVES == 1) {
+        if constexpr (!RES) {
+            if (a.imag_partials) {  // imaginary time
+                if (a.bcy == PHX_BC_ZERO)
+                    rk4_stream_kernel<R, RES, HASV, true, true, ROWS, true><<<a.tiles, 256, 0, s>>>(a);
+                else if (ghosts)
+                    rk4_stream_kernel<R, RES, HASV, true, false, ROWS, true><<<a.tiles, 256, 0, s>>>(a);
+                else
+                    rk4_stream_kernel<R, RES, HASV, false, false, ROWS, true><<<a.tiles, 256, 0, s>>>(a);
+                return hipGetLastError();
+            }
+        }
         if (a.bcy == PHX_BC_ZERO)
-            rk4_stream_kernel<R, RES, HASV, true, true, ROWS><<<a.tiles, 256, 0, s>>>(a);
+            rk4_stream_kernel<R, RES, HASV, true, true, ROWS, false><<<a.tiles, 256, 0, s>>>(a);
         else if (ghosts)
-            rk4_stream_kernel<R, RES, HASV, true, false, ROWS><<<a.tiles, 256, 0, s>>>(a);
+            rk4_stream_kernel<R, RES, HASV, true, false, ROWS, false><<<a.tiles, 256, 0, s>>>(a);
         else
-            rk4_stream_kernel<R, RES, HASV, false, false, ROWS><<<a.tiles, 256, 0, s>>>(a);
+            rk4_stream_kernel<R, RES, HASV, false, false, ROWS, false><<<a.tiles, 256, 0, s>>>(a);
     } else {
         if (ghosts)
             rk4_step_kernel<R, RES, HASV, true, WAVES, ROWS><<<a.tiles, WAVES * 64, 0, s>>>(a);
@@ -142,6 +165,10 @@ static StepArgs<R> step_args(const phx_handle* h, const StepShapeId& sh, const v
     a.n_in = (const R*)src_n;
     a.psi_out = (C*)dst;
     a.n_out = (R*)dst_n;
+    if (c.imag_time) {
+        a.imag_slots = (const double*)(h->ws + h->L.imag);
+        a.imag_partials = (double*)(h->ws + h->L.imag_partials);
+    }
     return a;
 }
 
@@ -191,6 +218,12 @@ phx_status rk4_fused_launches(phx_handle* h, int64_t n, hipStream_t s)
         if (e == hipSuccess) e = timing_end(h, t0, K_RK4_STEP);
         if (e != hipSuccess) return fail(PHX_EHIP, "RK4 step kernel launch: %s", hipGetErrorString(e));
         cur ^= 1;
+        if (c.imag_time) {  // the scale that restores the norm, applied by the next step
+            e = timing_begin(h, &t0);
+            if (e == hipSuccess) e = launch_imag_finish(h, 4 * a.tiles, s);
+            if (e == hipSuccess) e = timing_end(h, t0, K_IMAG_NORM);
+            if (e != hipSuccess) return fail(PHX_EHIP, "imaginary-time norm launch: %s", hipGetErrorString(e));
+        }
         if (c.noise > 0.0) {
             e = timing_begin(h, &t0);
             if (e == hipSuccess) e = launch_noise<R>(h, S[cur], SN[cur], k, s);

@@ -139,4 +139,6 @@ bool uses_step_index(const phx_config& c);
 int imag_norm_blocks(int64_t M);
 template <typename R> hipError_t launch_imag_norm(const phx_handle* h, const void* psi, int mode, hipStream_t s);
 template <typename R> hipError_t launch_imag_scale(const phx_handle* h, void* psi, hipStream_t s);
+// Imaginary time, streaming form: the restoring scale from `count` per-wave partials.
+hipError_t launch_imag_finish(const phx_handle* h, int count, hipStream_t s);
 }  // namespace phx

@@ -58,6 +58,8 @@ phx_status validate_config(const phx_config* c)
     if ((c->tile_wx == 0) != (c->tile_rows == 0)) return fail(PHX_EINVAL, "tile_wx and tile_rows: both 0 or both set");
     if (c->tile_wx != 0) {
         if (c->integrator == PHX_RK4 && rk4_family(*c) == PHX_KERNEL_STEP) {
+            if (c->imag_time && c->tile_wx != 1)
+                return fail(PHX_EINVAL, "imaginary time on the whole-step kernel uses the streaming shapes (tile_wx 1)");
             if (!valid_step_shape(c->precision, c->tile_wx, c->tile_rows))
                 return fail(PHX_EINVAL, "tile %d x %d is not a whole-step kernel shape", c->tile_wx, c->tile_rows);
             if (!step_shape_fits(*c, c->tile_wx))
@@ -80,8 +82,6 @@ phx_status validate_config(const phx_config* c)
             return fail(PHX_EINVAL, "imaginary time needs the conservative equation "
                                     "(no reservoir, gamma_c = R = 0, no noise, no drive)");
         if (c->integrator != PHX_RK4) return fail(PHX_EUNSUPPORTED, "imaginary time is implemented for RK4 only");
-        if (c->kernel == PHX_KERNEL_STEP)
-            return fail(PHX_EUNSUPPORTED, "imaginary time runs on the stage-fused kernels");
     }
     if (c->drive && c->integrator == PHX_RK4 && c->kernel == PHX_KERNEL_STEP)
         return fail(PHX_EUNSUPPORTED, "the whole-step kernel does not take a drive (use the stage-fused family)");
@@ -125,8 +125,12 @@ Layout make_layout(const phx_config& c)
     if (uses_step_index(c)) L.noise = take(sizeof(uint64_t));
     if (c.drive && c.integrator == PHX_RK4) L.drive_ph = take(4 * 2 * rs);
     if (c.imag_time) {
+        // partials: one per workgroup of the stage-family reduction, or one per wave of
+        // the streaming kernel (bands of at least 40 rows)
         L.imag = take(2 * sizeof(double));
-        L.imag_partials = take((size_t)imag_norm_blocks(c.nx * (int64_t)c.ny * c.components) * sizeof(double));
+        const int64_t stream_waves = 4 * (int64_t)((c.nx + 56 * 4 - 1) / (56 * 4)) * ((c.ny + 39) / 40);
+        const int64_t blocks = imag_norm_blocks(c.nx * (int64_t)c.ny * c.components);
+        L.imag_partials = take((size_t)(stream_waves > blocks ? stream_waves : blocks) * sizeof(double));
     }
     if (c.integrator == PHX_RK4) {
         L.family = rk4_family(c);
@@ -161,6 +165,7 @@ Layout make_layout(const phx_config& c)
 bool step_shape_fits(const phx_config& c, int waves)
 {
     const double bytes = (double)c.nx * c.ny * c.components * (c.precision == PHX_C64 ? 8.0 : 16.0);
+    if (c.imag_time && waves != 1) return false;  // imaginary time: streaming form only
     return waves != 1 || bytes < 2147483648.0 - 256.0;
 }
 
@@ -177,7 +182,8 @@ bool valid_step_shape(int precision, int waves, int rows)
 // written once) for one component, the stage-fused kernels otherwise or on request.
 int rk4_family(const phx_config& c)
 {
-    if (c.kernel == PHX_KERNEL_STAGE || c.drive || c.imag_time) return PHX_KERNEL_STAGE;
+    if (c.kernel == PHX_KERNEL_STAGE || c.drive) return PHX_KERNEL_STAGE;
+    if (c.imag_time) return (c.components == 1 && step_shape_fits(c, 1)) ? PHX_KERNEL_STEP : PHX_KERNEL_STAGE;
     if (c.components == 1) return PHX_KERNEL_STEP;
     return PHX_KERNEL_STAGE;
 }
@@ -284,6 +290,9 @@ phx_status phx_create(const phx_config* cfg, const phx_fields* f, void* stream,
     if (e == hipSuccess) e = hipEventCreateWithFlags(&h->flag_ready, hipEventDisableTiming);
     if (e == hipSuccess) e = hipMemsetAsync(h->ws + L.flag, 0, 256, h->stream);
     if (e == hipSuccess && uses_step_index(*cfg)) e = set_noise_step(h, 0, h->stream);
+    if (e == hipSuccess && cfg->imag_time)  // valid norm target and scale before any launch
+        e = cfg->precision == PHX_C64 ? launch_imag_norm<float>(h, f->psi, 0, h->stream)
+                                      : launch_imag_norm<double>(h, f->psi, 0, h->stream);
     h->drive_t0 = 0.0;
     h->drive_k0 = 0;
     if (e != hipSuccess) {
@@ -299,6 +308,7 @@ phx_status phx_create(const phx_config* cfg, const phx_fields* f, void* stream,
         const StepShapeId* shapes;
         step_shapes(cfg->precision, &shapes);
         h->step_shape = shapes[0];
+        if (cfg->imag_time) h->step_shape = StepShapeId{1, 40};  // imaginary time: streaming form
         if (cfg->tile_wx != 0 && L.family == PHX_KERNEL_STEP) h->step_shape = StepShapeId{cfg->tile_wx, cfg->tile_rows};
     }
     if (cfg->integrator == PHX_RK45) {
@@ -521,16 +531,24 @@ phx_status phx_step(phx_handle* h, int64_t n_steps, phx_info* out)
     }
     if (n_steps > 0) {
         phx_status s;
-        if (h->cfg.imag_time) {  // the norm every step of this call returns to
-            const hipError_t e = h->cfg.precision == PHX_C64 ? launch_imag_norm<float>(h, h->f.psi, 0, h->stream)
-                                                             : launch_imag_norm<double>(h, h->f.psi, 0, h->stream);
+        const bool c64 = h->cfg.precision == PHX_C64;
+        if (h->cfg.imag_time) {  // the norm every step of this call returns to (scale 1 to start)
+            const hipError_t e = c64 ? launch_imag_norm<float>(h, h->f.psi, 0, h->stream)
+                                     : launch_imag_norm<double>(h, h->f.psi, 0, h->stream);
             if (e != hipSuccess) return fail(PHX_EHIP, "imaginary-time norm launch: %s", hipGetErrorString(e));
         }
         if (h->L.family == PHX_KERNEL_STEP)
-            s = h->cfg.precision == PHX_C64 ? rk4_fused_steps<float>(h, n_steps) : rk4_fused_steps<double>(h, n_steps);
+            s = c64 ? rk4_fused_steps<float>(h, n_steps) : rk4_fused_steps<double>(h, n_steps);
         else
-            s = h->cfg.precision == PHX_C64 ? rk4_run<float>(h, n_steps) : rk4_run<double>(h, n_steps);
+            s = c64 ? rk4_run<float>(h, n_steps) : rk4_run<double>(h, n_steps);
         if (s != PHX_OK) return s;
+        if (h->cfg.imag_time && h->L.family == PHX_KERNEL_STEP) {
+            // the streaming kernel applies each step's restoring scale to its input; the
+            // last one is applied here so that the state ends normalized
+            const hipError_t e = c64 ? launch_imag_scale<float>(h, h->f.psi, h->stream)
+                                     : launch_imag_scale<double>(h, h->f.psi, h->stream);
+            if (e != hipSuccess) return fail(PHX_EHIP, "imaginary-time scale launch: %s", hipGetErrorString(e));
+        }
         HIP_OR_FAIL(hipMemcpyAsync(&h->host[OBS_SLOTS], h->ws + h->L.flag, sizeof(unsigned int),
                                    hipMemcpyDeviceToHost, h->stream));
         HIP_OR_FAIL(hipEventRecord(h->flag_ready, h->stream));

@@ -34,6 +34,10 @@ struct StepArgs {
     C* psi_out; R* n_out;
     const R* V; const R* P;
     unsigned int* flag;
+    // imaginary time (streaming form only): the input is scaled by imag_slots[1]
+    // as it is read, and each wave writes the FP64 norm partial of the cells it stores
+    const double* imag_slots;
+    double* imag_partials;
 };
 
 // value held by lane-1 (lane 0 receives 0) and by lane+1 (lane 63 receives 0):

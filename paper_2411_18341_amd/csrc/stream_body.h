@@ -33,8 +33,9 @@ __device__ __forceinline__ constexpr int slot(int t, int back)
 
 // Right-hand side of one cell from its stage argument p, the neighbour sums lr
 // (x) and ud (y), the reservoir value nn and the per-cell constant kv (see
-// step_stages for the formula).  Returns f and fn.
-template <typename R, bool RES>
+// step_stages for the formula).  Returns f and fn; IMAG (imaginary time, t -> -i tau)
+// returns -i f.
+template <typename R, bool RES, bool IMAG = false>
 __device__ __forceinline__ void cell_rhs(const Coef<R>& c, typename cvec<R>::type p, R lrx, R lry, R udx, R udy,
                                          R nn, R pv, R kv, R& fx, R& fy, R& fn)
 {
@@ -48,6 +49,11 @@ __device__ __forceinline__ void cell_rhs(const Coef<R>& c, typename cvec<R>::typ
     fx = fma(u, p.x, fma(om, p.y, -ty));
     fy = fma(u, p.y, fma(-om, p.x, tx));
     fn = RES ? fma(-fma(c.R_, rho, c.gamma_r), nn, pv) : R(0);
+    if constexpr (IMAG) {
+        const R t = fx;
+        fx = fy;
+        fy = -t;
+    }
 }
 
 // Raw buffer stores (hardware range check: a store at an offset past the buffer's
@@ -93,8 +99,12 @@ __device__ __forceinline__ void buf_store_nt(double2 v, __amdgpu_buffer_rsrc_t r
 // bands walk up, so that neighbouring bands reach the 8 rows they both read at the same
 // time (the second read is an L2 hit).  The stencil is symmetric in y, so the result
 // does not depend on the direction.
-template <typename R, bool RES, bool HASV, bool GHOSTS, bool YZERO, int B>
-__device__ __forceinline__ bool stream_band(const StepArgs<R>& a, int strip, int band, int dir)
+// IMAG: imaginary time (no reservoir): the derivative is rotated by -i, the input is
+// multiplied by the scale a.imag_slots[1] that restores the previous step's norm, and
+// *norm receives this lane's sum of |psi_out|^2 over the cells it stores (FP64).
+template <typename R, bool RES, bool HASV, bool GHOSTS, bool YZERO, int B, bool IMAG = false>
+__device__ __forceinline__ bool stream_band(const StepArgs<R>& a, int strip, int band, int dir,
+                                            double* norm = nullptr)
 {
     using C = typename cvec<R>::type;
     static_assert((B + 8) % 24 == 0, "band rows + 8 must be a multiple of the unroll length");
@@ -109,6 +119,9 @@ __device__ __forceinline__ bool stream_band(const StepArgs<R>& a, int strip, int
     const size_t cells = (size_t)a.nx * a.ny;
     const __amdgpu_buffer_rsrc_t rpo = buffer_of(a.psi_out, cells * sizeof(C));
     const __amdgpu_buffer_rsrc_t rno = buffer_of(a.n_out, RES ? cells * sizeof(R) : 0);
+    static_assert(!(IMAG && RES), "imaginary time has no reservoir");
+    const R sc = IMAG ? (R)a.imag_slots[1] : R(1);
+    double nrm = 0.0;
 
     // 8-row ring of inputs; ghost flags in bit s of gmask
     C sp[8];
@@ -147,7 +160,10 @@ __device__ __forceinline__ bool stream_band(const StepArgs<R>& a, int strip, int
         const bool gh = GHOSTS && (gcol || rw < 0);
         const int idx = gh ? 0 : rw * a.nx + ci0;
         const C v = a.psi_in[idx];
-        sp[s] = gh ? czero<C>() : v;
+        if constexpr (IMAG)
+            sp[s] = gh ? czero<C>() : C{v.x * sc, v.y * sc};
+        else
+            sp[s] = gh ? czero<C>() : v;
         if (RES) {
             const R nv = a.n_in[idx];
             const R pv = a.P[idx];
@@ -188,7 +204,7 @@ __device__ __forceinline__ bool stream_band(const StepArgs<R>& a, int strip, int
                 const C up = sp[slot<8>(u, 2)], dn = sp[slot<8>(u, 0)];
                 const R lrx = lane_prev(cur.x) + lane_next(cur.x);
                 const R lry = lane_prev(cur.y) + lane_next(cur.y);
-                cell_rhs<R, RES>(c, cur, lrx, lry, up.x + dn.x, up.y + dn.y, sn[s0], sP[s0], sk[s0], fx, fy, fn);
+                cell_rhs<R, RES, IMAG>(c, cur, lrx, lry, up.x + dn.x, up.y + dn.y, sn[s0], sP[s0], sk[s0], fx, fy, fn);
                 const bool g = GHOSTS && ((gmask >> s0) & 1u);
                 acc[slot<4>(u, 1)] = C{fx, fy};
                 accn[slot<4>(u, 1)] = fn;
@@ -203,7 +219,7 @@ __device__ __forceinline__ bool stream_band(const StepArgs<R>& a, int strip, int
                 const R nn = n2[slot<2>(u, 2)];
                 const R lrx = lane_prev(cur.x) + lane_next(cur.x);
                 const R lry = lane_prev(cur.y) + lane_next(cur.y);
-                cell_rhs<R, RES>(c, cur, lrx, lry, up.x + dn.x, up.y + dn.y, nn, sP[s0], sk[s0], fx, fy, fn);
+                cell_rhs<R, RES, IMAG>(c, cur, lrx, lry, up.x + dn.x, up.y + dn.y, nn, sP[s0], sk[s0], fx, fy, fn);
                 const bool g = GHOSTS && ((gmask >> s0) & 1u);
                 C& ac = acc[slot<4>(u, 2)];
                 ac = C{fma(R(2), fx, ac.x), fma(R(2), fy, ac.y)};
@@ -220,7 +236,7 @@ __device__ __forceinline__ bool stream_band(const StepArgs<R>& a, int strip, int
                 const R nn = n3[slot<2>(u, 3)];
                 const R lrx = lane_prev(cur.x) + lane_next(cur.x);
                 const R lry = lane_prev(cur.y) + lane_next(cur.y);
-                cell_rhs<R, RES>(c, cur, lrx, lry, up.x + dn.x, up.y + dn.y, nn, sP[s0], sk[s0], fx, fy, fn);
+                cell_rhs<R, RES, IMAG>(c, cur, lrx, lry, up.x + dn.x, up.y + dn.y, nn, sP[s0], sk[s0], fx, fy, fn);
                 const bool g = GHOSTS && ((gmask >> s0) & 1u);
                 C& ac = acc[slot<4>(u, 3)];
                 ac = C{fma(R(2), fx, ac.x), fma(R(2), fy, ac.y)};
@@ -239,7 +255,7 @@ __device__ __forceinline__ bool stream_band(const StepArgs<R>& a, int strip, int
                 const R nn = n4[slot<2>(u, 4)];
                 const R lrx = lane_prev(cur.x) + lane_next(cur.x);
                 const R lry = lane_prev(cur.y) + lane_next(cur.y);
-                cell_rhs<R, RES>(c, cur, lrx, lry, up.x + dn.x, up.y + dn.y, nn, sP[s0], sk[s0], fx, fy, fn);
+                cell_rhs<R, RES, IMAG>(c, cur, lrx, lry, up.x + dn.x, up.y + dn.y, nn, sP[s0], sk[s0], fx, fy, fn);
                 const C ac = acc[slot<4>(u, 4)];
                 const C p0 = sp[s0];
                 const C y = C{fma(a.dt6, ac.x + fx, p0.x), fma(a.dt6, ac.y + fy, p0.y)};
@@ -248,6 +264,7 @@ __device__ __forceinline__ bool stream_band(const StepArgs<R>& a, int strip, int
                 const bool st = out_col && r >= b0 && r < b0 + B && r < a.ny;
                 const int cell = r * a.nx + gi;
                 buf_store_nt(y, rpo, st ? cell * (int)sizeof(C) : kOutOfRange);
+                if constexpr (IMAG) nrm += st ? (double)y.x * y.x + (double)y.y * y.y : 0.0;
                 bool b = !(isfinite(y.x) && isfinite(y.y));
                 if (RES) {
                     buf_store_nt(yn, rno, st ? cell * (int)sizeof(R) : kOutOfRange);
@@ -257,6 +274,7 @@ __device__ __forceinline__ bool stream_band(const StepArgs<R>& a, int strip, int
             }
         }
     }
+    if constexpr (IMAG) *norm = nrm;
     return bad;
 }
 

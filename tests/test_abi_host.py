@@ -139,18 +139,24 @@ def test_drive_config_validation():
 
 
 def test_imag_time_config_validation():
-    """Imaginary time: the conservative equation on the stage-fused kernels; RK4's
-    stability bound on the negative real axis (2.78) replaces the imaginary-axis one."""
+    """Imaginary time: the conservative equation; one component runs on the streaming
+    whole-step kernel (region shapes rejected), the stage-fused family on request or
+    for the spinor; RK4's stability bound on the negative real axis (2.78) replaces the
+    imaginary-axis one."""
     stage = phx.phx_workspace_bytes(good_config(kernel=phx.PHX_KERNEL_STAGE))
-    assert phx.phx_workspace_bytes(good_config(imag_time=True)) == stage + 256 + 256
-    for bad in (dict(reservoir=True), dict(gamma_c=0.1), dict(R=0.1), dict(noise=1.0), dict(drive=True)):
+    step = phx.phx_workspace_bytes(good_config())
+    assert phx.phx_workspace_bytes(good_config(imag_time=True, kernel=phx.PHX_KERNEL_STAGE)) == stage + 256 + 256
+    assert phx.phx_workspace_bytes(good_config(imag_time=True)) == step + 256 + 256
+    phx.phx_workspace_bytes(good_config(imag_time=True, tile_wx=1, tile_rows=64))
+    phx.phx_workspace_bytes(good_config(imag_time=True, components=2, delta_lt=0.1))   # stage-fused
+    for bad in (dict(reservoir=True), dict(gamma_c=0.1), dict(R=0.1), dict(noise=1.0), dict(drive=True),
+                dict(tile_wx=8, tile_rows=4)):
         with pytest.raises(phx.PhxError) as e:
             phx.phx_workspace_bytes(good_config(imag_time=True, **bad))
         assert e.value.status == phx.PHX_EINVAL, bad
-    for bad in (dict(integrator=phx.PHX_RK45), dict(kernel=phx.PHX_KERNEL_STEP)):
-        with pytest.raises(phx.PhxError) as e:
-            phx.phx_workspace_bytes(good_config(imag_time=True, **bad))
-        assert e.value.status == phx.PHX_EUNSUPPORTED, bad
+    with pytest.raises(phx.PhxError) as e:
+        phx.phx_workspace_bytes(good_config(imag_time=True, integrator=phx.PHX_RK45))
+    assert e.value.status == phx.PHX_EUNSUPPORTED
     lam = 0.5 * 4 * (2 / 0.1 ** 2)  # hbar/2m * 4 (1/dx^2 + 1/dy^2)
     phx.phx_workspace_bytes(good_config(dt=2.7 / lam))                 # real time: bound 2.83
     phx.phx_workspace_bytes(good_config(dt=2.75 / lam, imag_time=True))

@@ -1,9 +1,11 @@
 """GPU parity of imaginary-time propagation (t -> -i tau, named in Sec. 6) against the
 oracle, through the C-ABI.
 
-The stage-fused kernels rotate their derivative by -i, and after every step a
-deterministic FP64 reduction and a scale pass restore the total norm the state had
-when the phx_step call began.  Element-wise parity to relative L2 1e-12 (complex128)
+Both kernel families rotate their derivative by -i.  The stage-fused family restores
+the norm after every step (deterministic FP64 reduction, scale pass); the streaming
+whole-step kernel (one component) writes per-wave norm partials, and the restoring
+scale is applied to the next step's input and, once, at the end of the call.  Both
+keep the total norm the state had when the phx_step call began.  Element-wise parity to relative L2 1e-12 (complex128)
 and 1e-5 (complex64) after 7 steps (scalar with V and g, TE-TM spinor, both boundary
 rules, direct launches and graph replays); the norm is kept at every call; and on a
 512^2 harmonic trap the state converges to the ground state of the discrete
@@ -35,22 +37,62 @@ def case(kind, nx, ny, bc, seed):
     return ph, psi, V
 
 
+@pytest.mark.parametrize("family", [phx.PHX_KERNEL_STAGE, phx.PHX_KERNEL_AUTO])
 @pytest.mark.parametrize("graph_steps", [-1, 2])
 @pytest.mark.parametrize("precision", [C64, C128])
-@pytest.mark.parametrize("kind,bc", [("scalar", (0, 0)), ("scalar", (1, 0)), ("spinor", (1, 1)), ("spinor", (0, 1))])
-def test_imag_parity(kind, bc, precision, graph_steps):
+@pytest.mark.parametrize("kind,bc", [("scalar", (0, 0)), ("scalar", (1, 0)), ("scalar", (0, 1)), ("spinor", (1, 1)),
+                                     ("spinor", (0, 1))])
+def test_imag_parity(kind, bc, precision, graph_steps, family):
     ph, psi, V = case(kind, 93, 58, bc, 3)
     q = quantize(precision, psi, None, V, None)
-    run = GpuRun(ph, q[0], None, q[2], None, precision=precision, imag_time=True, graph_steps=graph_steps)
+    run = GpuRun(ph, q[0], None, q[2], None, precision=precision, imag_time=True, graph_steps=graph_steps,
+                 kernel=family)
     run.step(7)
     g_psi, _ = run.state()
     run.close()
     o_psi = oracle.rk4_imag(oracle_physics(ph), q[0], V=q[2], dt=ph.dt, steps=7)
     e = rel_l2(g_psi, o_psi)
-    print(f"{kind} bc={bc} graph={graph_steps}: psi {e:.3e}")
+    print(f"{kind} bc={bc} graph={graph_steps} family={family}: psi {e:.3e}")
     assert e <= TOL[precision]
     n0 = ph.dx * ph.dy * np.sum(np.abs(q[0]) ** 2)
     assert ph.dx * ph.dy * np.sum(np.abs(g_psi) ** 2) == pytest.approx(n0, rel=TOL[precision])
+
+
+STREAM_SHAPES = {C64: [(1, 40), (1, 64), (1, 88), (1, 112)], C128: [(1, 40), (1, 64)]}
+
+
+@pytest.mark.parametrize("precision", [C64, C128])
+@pytest.mark.parametrize("bc", [(0, 0), (1, 1), (0, 1)])
+def test_imag_streaming_shapes(precision, bc):
+    """Every streaming band height, ragged grids spanning several strips and bands,
+    odd and even step counts over two calls."""
+    for shape in STREAM_SHAPES[precision]:
+        for nx, ny, steps in ((130, 97, 5), (57, 203, 4)):
+            ph, psi, V = case("scalar", nx, ny, bc, 7)
+            q = quantize(precision, psi, None, V, None)
+            run = GpuRun(ph, q[0], None, q[2], None, precision=precision, imag_time=True,
+                         kernel=phx.PHX_KERNEL_STEP, tile_wx=shape[0], tile_rows=shape[1], graph_steps=2)
+            run.step(steps)
+            run.step(3)
+            g_psi, _ = run.state()
+            run.close()
+            o_psi = oracle.rk4_imag(oracle_physics(ph), q[0], V=q[2], dt=ph.dt, steps=steps)
+            o_psi = oracle.rk4_imag(oracle_physics(ph), o_psi, V=q[2], dt=ph.dt, steps=3)
+            e = rel_l2(g_psi, o_psi)
+            assert e <= TOL[precision], (shape, nx, ny, e)
+
+
+def test_imag_autotune_keeps_parity(tmp_path, monkeypatch):
+    monkeypatch.setenv("PHX_TUNE_CACHE", str(tmp_path / "tune.json"))
+    ph, psi, V = case("scalar", 300, 170, (1, 1), 9)
+    run = GpuRun(ph, psi, None, V, None, precision=C128, imag_time=True)
+    r = run.solver.autotune(reps=3, use_cache=False)
+    assert r["tile_wx"] == 1
+    run.step(6)
+    g_psi, _ = run.state()
+    run.close()
+    o_psi = oracle.rk4_imag(oracle_physics(ph), psi, V=V, dt=ph.dt, steps=6)
+    assert rel_l2(g_psi, o_psi) <= TOL[C128]
 
 
 def test_imag_norm_kept_per_call():
