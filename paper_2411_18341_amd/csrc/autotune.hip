@@ -43,7 +43,7 @@ static phx_status tune_step(phx_handle* h, int reps, phx_tune_result* out)
     int timed = 0;
     for (int k = 0; k < n; ++k) {
         const StepShapeId sh = shapes[k];
-        if (!step_shape_fits(h->cfg, sh.waves)) continue;
+        if (!step_shape_allowed(h->cfg, sh)) continue;
         ++timed;
         double us;
         phx_status s = time_launches(h, reps, [&](int k) { return rk4_step_trial<R>(h, sh, k); }, &us);

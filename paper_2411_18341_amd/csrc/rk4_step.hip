@@ -128,9 +128,13 @@ static hipError_t launch_step_shape(const StepShapeId& sh, const StepArgs<R>& a,
 }
 
 template <typename R>
+hipError_t launch_stream_drive(bool reservoir, bool has_v, int rows, const StepArgs<R>& a, hipStream_t s);
+
+template <typename R>
 hipError_t launch_rk4_step(bool reservoir, bool has_v, const StepShapeId& sh, const StepArgs<R>& a,
                            hipStream_t s)
 {
+    if (a.E) return sh.waves == 1 ? launch_stream_drive<R>(reservoir, has_v, sh.rows, a, s) : hipErrorInvalidValue;
     if (reservoir) return has_v ? launch_step_shape<R, true, true>(sh, a, s) : launch_step_shape<R, true, false>(sh, a, s);
     return has_v ? launch_step_shape<R, false, true>(sh, a, s) : launch_step_shape<R, false, false>(sh, a, s);
 }
@@ -168,6 +172,10 @@ static StepArgs<R> step_args(const phx_handle* h, const StepShapeId& sh, const v
     if (c.imag_time) {
         a.imag_slots = (const double*)(h->ws + h->L.imag);
         a.imag_partials = (double*)(h->ws + h->L.imag_partials);
+    }
+    if (c.drive) {
+        a.E = (const C*)h->f.E;
+        a.drive_ph = (const C*)(h->ws + h->L.drive_ph);
     }
     return a;
 }
@@ -212,6 +220,8 @@ phx_status rk4_fused_launches(phx_handle* h, int64_t n, hipStream_t s)
     int cur = h->step_parity;
     for (int64_t k = 0; k < n; ++k) {
         const StepArgs<R> a = step_args<R>(h, sh, S[cur], SN[cur], S[cur ^ 1], SN[cur ^ 1]);
+        if (c.drive && launch_drive_phasors<R>(h, k, s) != hipSuccess)
+            return fail(PHX_EHIP, "drive phasor launch failed");
         hipEvent_t t0 = nullptr;
         hipError_t e = timing_begin(h, &t0);
         if (e == hipSuccess) e = launch_rk4_step<R>(res, hv, sh, a, s);
@@ -232,8 +242,8 @@ phx_status rk4_fused_launches(phx_handle* h, int64_t n, hipStream_t s)
         }
     }
     h->step_parity = cur;
-    if (c.noise > 0.0 && n > 0 && advance_noise_step(h, n, s) != hipSuccess)
-        return fail(PHX_EHIP, "noise step advance launch failed");
+    if (uses_step_index(c) && n > 0 && advance_noise_step(h, n, s) != hipSuccess)
+        return fail(PHX_EHIP, "step index advance launch failed");
     return PHX_OK;
 }
 

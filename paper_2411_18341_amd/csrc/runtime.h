@@ -121,6 +121,10 @@ template <typename R> hipError_t rk4_step_trial(phx_handle* h, const StepShapeId
 template <typename R> hipError_t rk4_stage_trial(phx_handle* h, const TileShape& ts);
 int step_shapes(int precision, const StepShapeId** out);
 bool step_shape_fits(const phx_config& c, int waves);
+// A whole-step shape this configuration can run (size limit of the streaming form;
+// imaginary time and the drive only on streaming shapes, the drive on 40 and 64 rows).
+bool step_shape_allowed(const phx_config& c, const StepShapeId& sh);
+bool drive_stream_rows(int rows);
 int rk4_family(const phx_config& c);
 phx_status step_rk45(phx_handle* h, int64_t n, phx_info* out);
 phx_status set_info_rk45(phx_handle* h, const phx_info* in);

@@ -58,8 +58,11 @@ phx_status validate_config(const phx_config* c)
     if ((c->tile_wx == 0) != (c->tile_rows == 0)) return fail(PHX_EINVAL, "tile_wx and tile_rows: both 0 or both set");
     if (c->tile_wx != 0) {
         if (c->integrator == PHX_RK4 && rk4_family(*c) == PHX_KERNEL_STEP) {
-            if (c->imag_time && c->tile_wx != 1)
-                return fail(PHX_EINVAL, "imaginary time on the whole-step kernel uses the streaming shapes (tile_wx 1)");
+            if ((c->imag_time || c->drive) && c->tile_wx != 1)
+                return fail(PHX_EINVAL, "imaginary time and the drive on the whole-step kernel use the streaming "
+                                        "shapes (tile_wx 1)");
+            if (c->drive && !drive_stream_rows(c->tile_rows))
+                return fail(PHX_EINVAL, "the drive on the whole-step kernel uses bands of 40 or 64 rows");
             if (!valid_step_shape(c->precision, c->tile_wx, c->tile_rows))
                 return fail(PHX_EINVAL, "tile %d x %d is not a whole-step kernel shape", c->tile_wx, c->tile_rows);
             if (!step_shape_fits(*c, c->tile_wx))
@@ -83,8 +86,7 @@ phx_status validate_config(const phx_config* c)
                                     "(no reservoir, gamma_c = R = 0, no noise, no drive)");
         if (c->integrator != PHX_RK4) return fail(PHX_EUNSUPPORTED, "imaginary time is implemented for RK4 only");
     }
-    if (c->drive && c->integrator == PHX_RK4 && c->kernel == PHX_KERNEL_STEP)
-        return fail(PHX_EUNSUPPORTED, "the whole-step kernel does not take a drive (use the stage-fused family)");
+
     if (c->noise > 0.0 && c->integrator != PHX_RK4)
         return fail(PHX_EUNSUPPORTED, "Wiener noise is implemented for RK4 only");
     if (c->integrator == PHX_RK4) {
@@ -165,8 +167,14 @@ Layout make_layout(const phx_config& c)
 bool step_shape_fits(const phx_config& c, int waves)
 {
     const double bytes = (double)c.nx * c.ny * c.components * (c.precision == PHX_C64 ? 8.0 : 16.0);
-    if (c.imag_time && waves != 1) return false;  // imaginary time: streaming form only
+    if ((c.imag_time || c.drive) && waves != 1) return false;  // streaming form only
     return waves != 1 || bytes < 2147483648.0 - 256.0;
+}
+
+bool step_shape_allowed(const phx_config& c, const StepShapeId& sh)
+{
+    if (!step_shape_fits(c, sh.waves)) return false;
+    return !c.drive || drive_stream_rows(sh.rows);
 }
 
 bool valid_step_shape(int precision, int waves, int rows)
@@ -182,8 +190,9 @@ bool valid_step_shape(int precision, int waves, int rows)
 // written once) for one component, the stage-fused kernels otherwise or on request.
 int rk4_family(const phx_config& c)
 {
-    if (c.kernel == PHX_KERNEL_STAGE || c.drive) return PHX_KERNEL_STAGE;
-    if (c.imag_time) return (c.components == 1 && step_shape_fits(c, 1)) ? PHX_KERNEL_STEP : PHX_KERNEL_STAGE;
+    if (c.kernel == PHX_KERNEL_STAGE) return PHX_KERNEL_STAGE;
+    if (c.imag_time || c.drive)  // the streaming form when it fits, else the stage-fused kernels
+        return (c.components == 1 && step_shape_fits(c, 1)) ? PHX_KERNEL_STEP : PHX_KERNEL_STAGE;
     if (c.components == 1) return PHX_KERNEL_STEP;
     return PHX_KERNEL_STAGE;
 }
@@ -288,13 +297,16 @@ phx_status phx_create(const phx_config* cfg, const phx_fields* f, void* stream,
     h->info.dt = cfg->dt;
     hipError_t e = hipHostMalloc((void**)&h->host, (OBS_SLOTS + 2) * sizeof(double), hipHostMallocDefault);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&h->flag_ready, hipEventDisableTiming);
+    h->drive_t0 = 0.0;
+    h->drive_k0 = 0;
     if (e == hipSuccess) e = hipMemsetAsync(h->ws + L.flag, 0, 256, h->stream);
     if (e == hipSuccess && uses_step_index(*cfg)) e = set_noise_step(h, 0, h->stream);
+    if (e == hipSuccess && cfg->drive && cfg->integrator == PHX_RK4)  // valid phasors before any launch
+        e = cfg->precision == PHX_C64 ? launch_drive_phasors<float>(h, 0, h->stream)
+                                      : launch_drive_phasors<double>(h, 0, h->stream);
     if (e == hipSuccess && cfg->imag_time)  // valid norm target and scale before any launch
         e = cfg->precision == PHX_C64 ? launch_imag_norm<float>(h, f->psi, 0, h->stream)
                                       : launch_imag_norm<double>(h, f->psi, 0, h->stream);
-    h->drive_t0 = 0.0;
-    h->drive_k0 = 0;
     if (e != hipSuccess) {
         if (h->host) (void)hipHostFree(h->host);
         if (h->flag_ready) (void)hipEventDestroy(h->flag_ready);
@@ -308,7 +320,7 @@ phx_status phx_create(const phx_config* cfg, const phx_fields* f, void* stream,
         const StepShapeId* shapes;
         step_shapes(cfg->precision, &shapes);
         h->step_shape = shapes[0];
-        if (cfg->imag_time) h->step_shape = StepShapeId{1, 40};  // imaginary time: streaming form
+        if (cfg->imag_time || cfg->drive) h->step_shape = StepShapeId{1, 40};  // streaming form
         if (cfg->tile_wx != 0 && L.family == PHX_KERNEL_STEP) h->step_shape = StepShapeId{cfg->tile_wx, cfg->tile_rows};
     }
     if (cfg->integrator == PHX_RK45) {

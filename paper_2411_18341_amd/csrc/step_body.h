@@ -38,6 +38,10 @@ struct StepArgs {
     // as it is read, and each wave writes the FP64 norm partial of the cells it stores
     const double* imag_slots;
     double* imag_partials;
+    // coherent drive (streaming form only): profile [ny][nx] and the phasors
+    // exp(-i omega t_s) of the four stage times of this step
+    const C* E;
+    const C* drive_ph;
 };
 
 // value held by lane-1 (lane 0 receives 0) and by lane+1 (lane 63 receives 0):

@@ -102,7 +102,9 @@ __device__ __forceinline__ void buf_store_nt(double2 v, __amdgpu_buffer_rsrc_t r
 // IMAG: imaginary time (no reservoir): the derivative is rotated by -i, the input is
 // multiplied by the scale a.imag_slots[1] that restores the previous step's norm, and
 // *norm receives this lane's sum of |psi_out|^2 over the cells it stores (FP64).
-template <typename R, bool RES, bool HASV, bool GHOSTS, bool YZERO, int B, bool IMAG = false>
+// DRIVE: the coherent drive -(i/hbar) E(r) exp(-i omega t_s) joins each stage's
+// derivative; E rides in the input ring, the four stage phasors come from a.drive_ph.
+template <typename R, bool RES, bool HASV, bool GHOSTS, bool YZERO, int B, bool IMAG = false, bool DRIVE = false>
 __device__ __forceinline__ bool stream_band(const StepArgs<R>& a, int strip, int band, int dir,
                                             double* norm = nullptr)
 {
@@ -122,6 +124,21 @@ __device__ __forceinline__ bool stream_band(const StepArgs<R>& a, int strip, int
     static_assert(!(IMAG && RES), "imaginary time has no reservoir");
     const R sc = IMAG ? (R)a.imag_slots[1] : R(1);
     double nrm = 0.0;
+    C ph[4];
+    C sE[8];
+    if constexpr (DRIVE) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) ph[s] = a.drive_ph[s];
+#pragma unroll
+        for (int s = 0; s < 8; ++s) sE[s] = czero<C>();
+    }
+    // adds -(i/hbar) E ph to (fx, fy)
+    auto drive = [&](R& fx, R& fy, const C e, const C p) {
+        const R zx = e.x * p.x - e.y * p.y;
+        const R zy = e.x * p.y + e.y * p.x;
+        fx = fma(c.inv_hbar, zy, fx);
+        fy = fma(-c.inv_hbar, zx, fy);
+    };
 
     // 8-row ring of inputs; ghost flags in bit s of gmask
     C sp[8];
@@ -174,6 +191,10 @@ __device__ __forceinline__ bool stream_band(const StepArgs<R>& a, int strip, int
             const R vv = a.V[idx];
             sk[s] = gh ? kdiag : fma(c.inv_hbar, vv, kdiag);
         }
+        if constexpr (DRIVE) {
+            const C ev = a.E[idx];
+            sE[s] = gh ? czero<C>() : ev;
+        }
         if (GHOSTS) gmask = (gmask & ~(1u << s)) | ((gh ? 1u : 0u) << s);
         const int gn = g + dir;
         int rn;
@@ -205,6 +226,7 @@ __device__ __forceinline__ bool stream_band(const StepArgs<R>& a, int strip, int
                 const R lrx = lane_prev(cur.x) + lane_next(cur.x);
                 const R lry = lane_prev(cur.y) + lane_next(cur.y);
                 cell_rhs<R, RES, IMAG>(c, cur, lrx, lry, up.x + dn.x, up.y + dn.y, sn[s0], sP[s0], sk[s0], fx, fy, fn);
+                if constexpr (DRIVE) drive(fx, fy, sE[s0], ph[0]);
                 const bool g = GHOSTS && ((gmask >> s0) & 1u);
                 acc[slot<4>(u, 1)] = C{fx, fy};
                 accn[slot<4>(u, 1)] = fn;
@@ -220,6 +242,7 @@ __device__ __forceinline__ bool stream_band(const StepArgs<R>& a, int strip, int
                 const R lrx = lane_prev(cur.x) + lane_next(cur.x);
                 const R lry = lane_prev(cur.y) + lane_next(cur.y);
                 cell_rhs<R, RES, IMAG>(c, cur, lrx, lry, up.x + dn.x, up.y + dn.y, nn, sP[s0], sk[s0], fx, fy, fn);
+                if constexpr (DRIVE) drive(fx, fy, sE[s0], ph[1]);
                 const bool g = GHOSTS && ((gmask >> s0) & 1u);
                 C& ac = acc[slot<4>(u, 2)];
                 ac = C{fma(R(2), fx, ac.x), fma(R(2), fy, ac.y)};
@@ -237,6 +260,7 @@ __device__ __forceinline__ bool stream_band(const StepArgs<R>& a, int strip, int
                 const R lrx = lane_prev(cur.x) + lane_next(cur.x);
                 const R lry = lane_prev(cur.y) + lane_next(cur.y);
                 cell_rhs<R, RES, IMAG>(c, cur, lrx, lry, up.x + dn.x, up.y + dn.y, nn, sP[s0], sk[s0], fx, fy, fn);
+                if constexpr (DRIVE) drive(fx, fy, sE[s0], ph[2]);
                 const bool g = GHOSTS && ((gmask >> s0) & 1u);
                 C& ac = acc[slot<4>(u, 3)];
                 ac = C{fma(R(2), fx, ac.x), fma(R(2), fy, ac.y)};
@@ -256,6 +280,7 @@ __device__ __forceinline__ bool stream_band(const StepArgs<R>& a, int strip, int
                 const R lrx = lane_prev(cur.x) + lane_next(cur.x);
                 const R lry = lane_prev(cur.y) + lane_next(cur.y);
                 cell_rhs<R, RES, IMAG>(c, cur, lrx, lry, up.x + dn.x, up.y + dn.y, nn, sP[s0], sk[s0], fx, fy, fn);
+                if constexpr (DRIVE) drive(fx, fy, sE[s0], ph[3]);
                 const C ac = acc[slot<4>(u, 4)];
                 const C p0 = sp[s0];
                 const C y = C{fma(a.dt6, ac.x + fx, p0.x), fma(a.dt6, ac.y + fy, p0.y)};

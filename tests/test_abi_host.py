@@ -127,13 +127,18 @@ def test_noise_config_validation():
 
 
 def test_drive_config_validation():
-    """Coherent drive: the stage-fused family (AUTO picks it, an explicit whole-step
-    request is unsupported); RK4 adds the step-index slot and four stage phasors."""
+    """Coherent drive: one component runs on the streaming whole-step kernel with bands
+    of 40 or 64 rows (region shapes and other bands rejected), the stage-fused family on
+    request or for the spinor; RK4 adds the step-index slot and four stage phasors."""
     stage = phx.phx_workspace_bytes(good_config(kernel=phx.PHX_KERNEL_STAGE))
-    assert phx.phx_workspace_bytes(good_config(drive=True, drive_omega=1.5)) == stage + 256 + 256
-    with pytest.raises(phx.PhxError) as e:
-        phx.phx_workspace_bytes(good_config(drive=True, kernel=phx.PHX_KERNEL_STEP))
-    assert e.value.status == phx.PHX_EUNSUPPORTED
+    step = phx.phx_workspace_bytes(good_config())
+    assert phx.phx_workspace_bytes(good_config(drive=True, drive_omega=1.5)) == step + 256 + 256
+    assert phx.phx_workspace_bytes(good_config(drive=True, kernel=phx.PHX_KERNEL_STAGE)) == stage + 256 + 256
+    phx.phx_workspace_bytes(good_config(drive=True, kernel=phx.PHX_KERNEL_STEP, tile_wx=1, tile_rows=64))
+    for bad in (dict(tile_wx=8, tile_rows=4), dict(tile_wx=1, tile_rows=88)):
+        with pytest.raises(phx.PhxError) as e:
+            phx.phx_workspace_bytes(good_config(drive=True, kernel=phx.PHX_KERNEL_STEP, **bad))
+        assert e.value.status == phx.PHX_EINVAL, bad
     rk45 = phx.phx_workspace_bytes(good_config(integrator=phx.PHX_RK45))
     assert phx.phx_workspace_bytes(good_config(integrator=phx.PHX_RK45, drive=True)) == rk45
 

@@ -48,15 +48,16 @@ def quantize_e(precision, E):
     return E.astype(np.complex64).astype(np.complex128) if precision == C64 else E
 
 
+@pytest.mark.parametrize("family", [phx.PHX_KERNEL_STAGE, phx.PHX_KERNEL_AUTO])
 @pytest.mark.parametrize("graph_steps", [-1, 2])
 @pytest.mark.parametrize("precision", [C64, C128])
-@pytest.mark.parametrize("kind,bc", [("driven", (0, 0)), ("driven_v", (1, 0)), ("spinor_res", (0, 1)),
-                                     ("spinor_res", (1, 1))])
-def test_drive_parity(kind, bc, precision, graph_steps):
+@pytest.mark.parametrize("kind,bc", [("driven", (0, 0)), ("driven_v", (1, 0)), ("driven_v", (0, 1)),
+                                     ("spinor_res", (0, 1)), ("spinor_res", (1, 1))])
+def test_drive_parity(kind, bc, precision, graph_steps, family):
     ph, psi, n, V, P = workload(kind, 97, 61, bc, seed=4)
     q = quantize(precision, psi, n, V, P)
     E = quantize_e(precision, drive_profile(ph, 5))
-    run = GpuRun(ph, *q, precision=precision, E=E, drive_omega=OMEGA, graph_steps=graph_steps)
+    run = GpuRun(ph, *q, precision=precision, E=E, drive_omega=OMEGA, graph_steps=graph_steps, kernel=family)
     assert run.solver.handle is not None
     run.step(7)
     g_psi, g_n = run.state()
@@ -66,16 +67,18 @@ def test_drive_parity(kind, bc, precision, graph_steps):
     assert rel_l2(d_psi, o_psi) > 100 * TOL[precision]  # the drive is visible
     e_psi = rel_l2(g_psi, o_psi)
     e_n = rel_l2(g_n, o_n) if ph.reservoir else 0.0
-    print(f"{kind} bc={bc} graph={graph_steps}: psi {e_psi:.3e} n {e_n:.3e}")
+    print(f"{kind} bc={bc} graph={graph_steps} family={family}: psi {e_psi:.3e} n {e_n:.3e}")
     assert e_psi <= TOL[precision] and e_n <= TOL[precision]
 
 
+@pytest.mark.parametrize("family", [phx.PHX_KERNEL_STAGE, phx.PHX_KERNEL_AUTO])
 @pytest.mark.parametrize("precision", [C64, C128])
-def test_drive_with_noise(precision):
+def test_drive_with_noise(precision, family):
     ph, psi, n, V, P = workload("driven", 90, 70, (0, 0), seed=6)
     q = quantize(precision, psi, n, V, P)
     E = quantize_e(precision, drive_profile(ph, 7))
-    run = GpuRun(ph, *q, precision=precision, E=E, drive_omega=OMEGA, noise=0.7, seed=31, graph_steps=4)
+    run = GpuRun(ph, *q, precision=precision, E=E, drive_omega=OMEGA, noise=0.7, seed=31, graph_steps=4,
+                 kernel=family)
     run.step(9)
     g_psi, g_n = run.state()
     run.close()
@@ -83,13 +86,15 @@ def test_drive_with_noise(precision):
     assert rel_l2(g_psi, o_psi) <= TOL[precision] and rel_l2(g_n, o_n) <= TOL[precision]
 
 
+@pytest.mark.parametrize("family", [phx.PHX_KERNEL_STAGE, phx.PHX_KERNEL_AUTO])
 @pytest.mark.parametrize("graph_steps", [-1, 2])
-def test_drive_after_set_info(graph_steps):
+def test_drive_after_set_info(graph_steps, family):
     """phx_set_info to an arbitrary (t, step) restarts the drive's clock there, also
     for a graph captured before the call."""
     ph, psi, n, V, P = workload("driven_v", 100, 64, (0, 1), seed=9)
     E = drive_profile(ph, 8)
-    run = GpuRun(ph, psi, n, V, P, precision=C128, E=E, drive_omega=OMEGA, graph_steps=graph_steps)
+    run = GpuRun(ph, psi, n, V, P, precision=C128, E=E, drive_omega=OMEGA, graph_steps=graph_steps,
+                 kernel=family)
     run.step(4)  # captures a graph (graph_steps 2) with the old clock
     mid_psi, mid_n = run.state()
     run.solver.set_info(t=37.25, steps_accepted=1000)
@@ -149,12 +154,35 @@ def test_drive_observables_residual(precision):
     assert abs(ou["steady_res_density"] - o["steady_res_density"]) > 10 * tol * o["steady_res_density"]
 
 
+@pytest.mark.parametrize("precision", [C64, C128])
+@pytest.mark.parametrize("rows", [40, 64])
+def test_drive_streaming_shapes(rows, precision):
+    """The driven streaming kernel for both band heights on ragged grids of several
+    strips and bands, both y boundary rules, odd and even step counts over two calls
+    (the phasors follow the device step index)."""
+    for bc, (nx, ny) in (((0, 0), (130, 97)), ((1, 1), (57, 203)), ((0, 1), (200, 131))):
+        ph, psi, n, V, P = workload("driven_v", nx, ny, bc, seed=11)
+        q = quantize(precision, psi, n, V, P)
+        E = quantize_e(precision, drive_profile(ph, 12))
+        run = GpuRun(ph, *q, precision=precision, E=E, drive_omega=OMEGA, kernel=phx.PHX_KERNEL_STEP,
+                     tile_wx=1, tile_rows=rows, graph_steps=2)
+        run.step(5)
+        run.step(4)
+        g_psi, g_n = run.state()
+        run.close()
+        o_psi, o_n = oracle.rk4(oracle_drive(ph, E), *q, dt=ph.dt, steps=9)
+        assert rel_l2(g_psi, o_psi) <= TOL[precision] and rel_l2(g_n, o_n) <= TOL[precision], (bc, rows)
+
+
 def test_drive_family_and_rejections():
     ph, psi, n, V, P = workload("driven", 64, 48, (0, 0))
     E = drive_profile(ph, 1)
-    with pytest.raises(phx.PhxError) as e:
-        GpuRun(ph, psi, n, V, P, precision=C64, E=E, kernel=phx.PHX_KERNEL_STEP)
-    assert e.value.status == phx.PHX_EUNSUPPORTED
+    with pytest.raises(phx.PhxError) as e:  # region shapes take no drive
+        GpuRun(ph, psi, n, V, P, precision=C64, E=E, kernel=phx.PHX_KERNEL_STEP, tile_wx=8, tile_rows=4)
+    assert e.value.status == phx.PHX_EINVAL
+    with pytest.raises(phx.PhxError) as e:  # nor bands other than 40 and 64 rows
+        GpuRun(ph, psi, n, V, P, precision=C64, E=E, kernel=phx.PHX_KERNEL_STEP, tile_wx=1, tile_rows=88)
+    assert e.value.status == phx.PHX_EINVAL
     with pytest.raises(phx.PhxError) as e:
         GpuRun(ph, psi, n, V, P, precision=C64, E=E, drive=False)  # profile without drive
     assert e.value.status == phx.PHX_EINVAL
