@@ -54,8 +54,8 @@ def kernel_kind(name: str) -> str:
     m = re.search(r"rk4_step_kernel<[^>]*?(\d+), (\d+)>", name)
     if m:
         return f"rk4_step_{m.group(1)}x{m.group(2)}"
-    m = re.search(r"rk4_stream_kernel<[^>]*?(\d+)>", name)
-    if m:  # streaming form: shape 1 x band rows
+    m = re.search(r"rk4_stream(?:_drive)?_kernel<[^>]*?, (\d+)(?:, (?:true|false))?>", name)
+    if m:  # streaming form (also with the drive or in imaginary time): shape 1 x band rows
         return f"rk4_step_1x{m.group(1)}"
     named = {"rk4_step_kernel": "rk4_step", "batch_step_kernel": "batch_step", "dp_restart_kernel": "dp_restart",
              "dp_err_sum_kernel": "dp_error", "obs_pass1": "obs_pass1", "obs_pass2": "obs_pass2",

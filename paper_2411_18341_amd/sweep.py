@@ -219,10 +219,11 @@ def measure_noise(n: int = 4096, nu: float = 1.0, steps: int = 300, warmup: int 
 
 
 def measure_drive(n: int = 4096, omega: float = 1.3, steps: int = 100, warmup: int = 10, timed_steps: int = 20):
-    """The driven workload (complex64, n x n) on the stage-fused kernels with and
-    without a coherent drive (a Gaussian spot of amplitude 0.8): point updates per
-    second of whole steps (graph replays), and per stage kernel the mean launch time
-    with its algorithmic bandwidth (the drive adds one complex read per stage)."""
+    """The driven workload (complex64, n x n) with and without a coherent drive (a
+    Gaussian spot of amplitude 0.8), on the streaming whole-step kernel and on the
+    stage-fused kernels: point updates per second of whole steps (graph replays), and
+    per kernel the mean launch time with its algorithmic bandwidth (the drive adds one
+    complex read per stage launch, or per step in the whole-step kernel)."""
     import numpy as np
     import torch
     ph, psi0, n0, P = inputs.driven(n)
@@ -230,13 +231,14 @@ def measure_drive(n: int = 4096, omega: float = 1.3, steps: int = 100, warmup: i
     E0 = (0.8 * np.exp(-(X * X + Y * Y) / (2 * 30.0 ** 2)))[None].astype(np.complex64)
     dev = torch.device("cuda:0")
     out = {"n": n, "omega": omega}
-    for label, drive in (("undriven", False), ("driven", True)):
+    runs = (("undriven", False, phx.PHX_KERNEL_STAGE), ("driven", True, phx.PHX_KERNEL_STAGE),
+            ("undriven_step", False, phx.PHX_KERNEL_STEP), ("driven_step", True, phx.PHX_KERNEL_STEP))
+    for label, drive, family in runs:
         psi = torch.from_numpy(psi0).to(dtype=torch.complex64, device=dev).contiguous()
         nn = torch.from_numpy(n0).to(dtype=torch.float32, device=dev).contiguous()
         Pd = torch.from_numpy(P).to(dtype=torch.float32, device=dev).contiguous()
         Ed = torch.from_numpy(E0).to(device=dev).contiguous() if drive else None
-        cfg = phx.config_from_physics(ph, precision=phx.PHX_C64, kernel=phx.PHX_KERNEL_STAGE, drive=drive,
-                                      drive_omega=omega)
+        cfg = phx.config_from_physics(ph, precision=phx.PHX_C64, kernel=family, drive=drive, drive_omega=omega)
         solver = phx.Solver(cfg, psi, nn, None, Pd, E=Ed)
         try:
             tune = solver.autotune(reps=5, use_cache=False)
@@ -252,13 +254,18 @@ def measure_drive(n: int = 4096, omega: float = 1.3, steps: int = 100, warmup: i
             times = solver.kernel_times()
         finally:
             solver.close()
-        model = bytemodel.rk4_stage_fused(4, reservoir=True, has_v=False, drive=drive)
+        if family == phx.PHX_KERNEL_STAGE:
+            model = bytemodel.rk4_stage_fused(4, reservoir=True, has_v=False, drive=drive)
+        else:
+            model = {"step": bytemodel.rk4_whole_step(4, reservoir=True, has_v=False)["step"] + (8 if drive else 0)}
         ks = {}
         for k, v in times.items():
             us = v["ms_total"] / v["launches"] * 1e3
             ks[k] = {"avg_us": us}
             if k.startswith("rk4_stage"):
                 ks[k]["algorithmic_GBps"] = model["stage" + k[-1]] * n * n / (us * 1e-6) / 1e9
+            if k == "rk4_step":
+                ks[k]["algorithmic_GBps"] = model["step"] * n * n / (us * 1e-6) / 1e9
         out[label] = {"tile": [tune["tile_wx"], tune["tile_rows"]], "UPs": n * n * steps / wall,
                       "us_per_step": wall / steps * 1e6, "step_bytes_per_point": model["step"], "kernels": ks}
     return out

@@ -298,3 +298,18 @@ def test_batch_descriptor_validation():
     with pytest.raises(phx.PhxError) as e:
         phx.phx_batch_step(small, 1, None)
     assert e.value.status == phx.PHX_EWORKSPACE
+
+
+def test_profile_kernel_names():
+    """Kernel names in rocprofv3 output map to the kinds the counter records use."""
+    from paper_2411_18341_amd.profiling import kernel_kind
+    cases = {
+        "void phx::rk4_stream_kernel<float, true, false, false, false, 40, false>(phx::StepArgs<float>)": "rk4_step_1x40",
+        "void phx::rk4_stream_kernel<double, false, true, true, true, 64, true>(phx::StepArgs<double>)": "rk4_step_1x64",
+        "void phx::rk4_stream_drive_kernel<float, true, false, false, false, 64>(phx::StepArgs<float>)": "rk4_step_1x64",
+        "void phx::rk4_step_kernel<float, true, false, false, 12, 6>(phx::StepArgs<float>)": "rk4_step_12x6",
+        "void phx::rk4_stage_kernel<float, 1, true, false, 3>(phx::Rk4Args<float>)": "rk4_stage3",
+        "void (anonymous namespace)::wiener_noise_kernel<float, true>(float2*, float const*)": "wiener_noise",
+    }
+    for name, kind in cases.items():
+        assert kernel_kind(name) == kind, name
