@@ -18,7 +18,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 OUT = os.path.join(HERE, "libphx.so")
 BUILD_DIR = os.path.join(HERE, "_build")
-SOURCES = ["runtime.hip", "rk4.hip", "rk4_step.hip", "reduce.hip", "dopri5.hip", "batch.hip", "autotune.hip", "cnn.hip", "noise.hip", "drive.hip", "imag.hip", "rk4_stream_drive.hip"]
+SOURCES = ["runtime.hip", "rk4.hip", "rk4_step.hip", "reduce.hip", "dopri5.hip", "batch.hip", "autotune.hip", "cnn.hip", "noise.hip", "drive.hip", "imag.hip", "rk4_stream_drive.hip", "rk4_stream_spinor.hip"]
 
 ARCH = "gfx950"
 FLAGS = [

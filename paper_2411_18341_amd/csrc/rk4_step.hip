@@ -129,12 +129,16 @@ static hipError_t launch_step_shape(const StepShapeId& sh, const StepArgs<R>& a,
 
 template <typename R>
 hipError_t launch_stream_drive(bool reservoir, bool has_v, int rows, const StepArgs<R>& a, hipStream_t s);
+template <typename R>
+hipError_t launch_stream_spinor(bool has_v, int rows, const StepArgs<R>& a, hipStream_t s);
 
 template <typename R>
 hipError_t launch_rk4_step(bool reservoir, bool has_v, const StepShapeId& sh, const StepArgs<R>& a,
                            hipStream_t s)
 {
     if (a.E) return sh.waves == 1 ? launch_stream_drive<R>(reservoir, has_v, sh.rows, a, s) : hipErrorInvalidValue;
+    if (a.comps == 2)
+        return sh.waves == 1 && !reservoir ? launch_stream_spinor<R>(has_v, sh.rows, a, s) : hipErrorInvalidValue;
     if (reservoir) return has_v ? launch_step_shape<R, true, true>(sh, a, s) : launch_step_shape<R, true, false>(sh, a, s);
     return has_v ? launch_step_shape<R, false, true>(sh, a, s) : launch_step_shape<R, false, false>(sh, a, s);
 }
@@ -169,6 +173,7 @@ static StepArgs<R> step_args(const phx_handle* h, const StepShapeId& sh, const v
     a.n_in = (const R*)src_n;
     a.psi_out = (C*)dst;
     a.n_out = (R*)dst_n;
+    a.comps = c.components;
     if (c.imag_time) {
         a.imag_slots = (const double*)(h->ws + h->L.imag);
         a.imag_partials = (double*)(h->ws + h->L.imag_partials);
@@ -262,7 +267,8 @@ phx_status rk4_fused_steps(phx_handle* h, int64_t n)
     h->step_parity = 0;
     if (n & 1) {
         void* alt = h->ws + h->L.alt;
-        if (hipMemcpyAsync(alt, h->f.psi, cells * 2 * rs, hipMemcpyDeviceToDevice, h->stream) != hipSuccess ||
+        if (hipMemcpyAsync(alt, h->f.psi, cells * c.components * 2 * rs, hipMemcpyDeviceToDevice, h->stream) !=
+                hipSuccess ||
             (c.reservoir && hipMemcpyAsync(h->ws + h->L.alt_n, h->f.n, cells * rs, hipMemcpyDeviceToDevice,
                                            h->stream) != hipSuccess))
             return fail(PHX_EHIP, "state copy failed");

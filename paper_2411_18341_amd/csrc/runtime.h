@@ -122,7 +122,8 @@ template <typename R> hipError_t rk4_stage_trial(phx_handle* h, const TileShape&
 int step_shapes(int precision, const StepShapeId** out);
 bool step_shape_fits(const phx_config& c, int waves);
 // A whole-step shape this configuration can run (size limit of the streaming form;
-// imaginary time and the drive only on streaming shapes, the drive on 40 and 64 rows).
+// imaginary time, the drive and the spinor only on streaming shapes, the drive and
+// the spinor on bands of 40 and 64 rows).
 bool step_shape_allowed(const phx_config& c, const StepShapeId& sh);
 bool drive_stream_rows(int rows);
 int rk4_family(const phx_config& c);

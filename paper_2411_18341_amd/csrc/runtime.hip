@@ -53,16 +53,18 @@ phx_status validate_config(const phx_config* c)
         return fail(PHX_EINVAL, "integrator=%d must be PHX_RK4 or PHX_RK45", c->integrator);
     if (c->kernel < PHX_KERNEL_AUTO || c->kernel > PHX_KERNEL_STEP)
         return fail(PHX_EINVAL, "kernel=%d is not a PHX_KERNEL_* value", c->kernel);
-    if (c->kernel == PHX_KERNEL_STEP && (c->integrator != PHX_RK4 || c->components != 1))
-        return fail(PHX_EUNSUPPORTED, "the whole-step kernel covers RK4 with one component");
+    if (c->kernel == PHX_KERNEL_STEP &&
+        (c->integrator != PHX_RK4 || (c->components == 2 && (c->reservoir || c->drive || c->imag_time))))
+        return fail(PHX_EUNSUPPORTED, "the whole-step kernel covers RK4 with one component, or two without the "
+                                      "reservoir, drive and imaginary time");
     if ((c->tile_wx == 0) != (c->tile_rows == 0)) return fail(PHX_EINVAL, "tile_wx and tile_rows: both 0 or both set");
     if (c->tile_wx != 0) {
         if (c->integrator == PHX_RK4 && rk4_family(*c) == PHX_KERNEL_STEP) {
-            if ((c->imag_time || c->drive) && c->tile_wx != 1)
-                return fail(PHX_EINVAL, "imaginary time and the drive on the whole-step kernel use the streaming "
-                                        "shapes (tile_wx 1)");
-            if (c->drive && !drive_stream_rows(c->tile_rows))
-                return fail(PHX_EINVAL, "the drive on the whole-step kernel uses bands of 40 or 64 rows");
+            if ((c->imag_time || c->drive || c->components == 2) && c->tile_wx != 1)
+                return fail(PHX_EINVAL, "imaginary time, the drive and the spinor on the whole-step kernel use the "
+                                        "streaming shapes (tile_wx 1)");
+            if ((c->drive || c->components == 2) && !drive_stream_rows(c->tile_rows))
+                return fail(PHX_EINVAL, "the drive and the spinor on the whole-step kernel use bands of 40 or 64 rows");
             if (!valid_step_shape(c->precision, c->tile_wx, c->tile_rows))
                 return fail(PHX_EINVAL, "tile %d x %d is not a whole-step kernel shape", c->tile_wx, c->tile_rows);
             if (!step_shape_fits(*c, c->tile_wx))
@@ -167,14 +169,14 @@ Layout make_layout(const phx_config& c)
 bool step_shape_fits(const phx_config& c, int waves)
 {
     const double bytes = (double)c.nx * c.ny * c.components * (c.precision == PHX_C64 ? 8.0 : 16.0);
-    if ((c.imag_time || c.drive) && waves != 1) return false;  // streaming form only
+    if ((c.imag_time || c.drive || c.components == 2) && waves != 1) return false;  // streaming form only
     return waves != 1 || bytes < 2147483648.0 - 256.0;
 }
 
 bool step_shape_allowed(const phx_config& c, const StepShapeId& sh)
 {
     if (!step_shape_fits(c, sh.waves)) return false;
-    return !c.drive || drive_stream_rows(sh.rows);
+    return (!c.drive && c.components == 1) || drive_stream_rows(sh.rows);
 }
 
 bool valid_step_shape(int precision, int waves, int rows)
@@ -187,13 +189,16 @@ bool valid_step_shape(int precision, int waves, int rows)
 }
 
 // RK4 kernel family: the whole-step kernel (one launch per step, state read and
-// written once) for one component, the stage-fused kernels otherwise or on request.
+// written once) for one component and for the spinor without the reservoir (its
+// streaming form; also with the drive or in imaginary time for one component), the
+// stage-fused kernels otherwise or on request.
 int rk4_family(const phx_config& c)
 {
     if (c.kernel == PHX_KERNEL_STAGE) return PHX_KERNEL_STAGE;
     if (c.imag_time || c.drive)  // the streaming form when it fits, else the stage-fused kernels
         return (c.components == 1 && step_shape_fits(c, 1)) ? PHX_KERNEL_STEP : PHX_KERNEL_STAGE;
     if (c.components == 1) return PHX_KERNEL_STEP;
+    if (!c.reservoir && step_shape_fits(c, 1)) return PHX_KERNEL_STEP;  // spinor: streaming form
     return PHX_KERNEL_STAGE;
 }
 
@@ -320,7 +325,7 @@ phx_status phx_create(const phx_config* cfg, const phx_fields* f, void* stream,
         const StepShapeId* shapes;
         step_shapes(cfg->precision, &shapes);
         h->step_shape = shapes[0];
-        if (cfg->imag_time || cfg->drive) h->step_shape = StepShapeId{1, 40};  // streaming form
+        if (cfg->imag_time || cfg->drive || cfg->components == 2) h->step_shape = StepShapeId{1, 40};  // streaming
         if (cfg->tile_wx != 0 && L.family == PHX_KERNEL_STEP) h->step_shape = StepShapeId{cfg->tile_wx, cfg->tile_rows};
     }
     if (cfg->integrator == PHX_RK45) {

@@ -42,6 +42,7 @@ struct StepArgs {
     // exp(-i omega t_s) of the four stage times of this step
     const C* E;
     const C* drive_ph;
+    int comps;  // 2: the spinor streaming kernel (component stride nx*ny)
 };
 
 // value held by lane-1 (lane 0 receives 0) and by lane+1 (lane 63 receives 0):

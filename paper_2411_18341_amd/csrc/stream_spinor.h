@@ -1,0 +1,216 @@
+// Device code of the streaming whole-step RK4 kernel for the two-component (spinor)
+// form of Eq. (PULSE_psi) without the reservoir: self and cross interaction, the
+// potential and the TE-TM coupling J_+- = Delta_LT (d_x -+ i d_y)^2, whose mixed
+// derivative needs the diagonal neighbours of the other component.
+//
+// The band walk is the one-component kernel's (stream_body.h): one wave per strip of
+// 56 columns plus a 4-column halo, rows walked once with the four stages pipelined
+// one row apart, inputs in an 8-row ring, running sums in a 4-row ring, stage
+// arguments in 3-row windows -- here for both components.  x-neighbours come from
+// DPP lane shifts; the mixed difference
+//   X = o[i+1,j+1] - o[i+1,j-1] - o[i-1,j+1] + o[i-1,j-1]
+// is the lane shift of (row below - row above) of the other component, and changes
+// sign with the walking direction (odd bands walk upwards).
+#pragma once
+
+#include "stream_body.h"
+
+namespace phx {
+
+// f_s for both components from the stage arguments (cur), the neighbour sums in x
+// (lr) and y (ud), the y-differences of the rows below and above (dy = below - above,
+// for the mixed term) and the per-cell constant kv = V/hbar + 2 (ax + ay).
+//   f_s = i T_s + (-gamma/2 - i om_s) p_s - sgn_s bxy X_o,
+//   T_s = ax lr_s + ay ud_s - 2(ax + ay) p_s - bx (lr_o - 2 q) + by (ud_o - 2 q),
+//   om_s = V/hbar + gh rho_s + gxh rho_o (the -2(ax + ay) p_s term folded into kv),
+// X_o = dir (next(dy_o) - prev(dy_o)), sgn = +1 for psi_+, -1 for psi_-.
+template <typename R>
+__device__ __forceinline__ void spinor_rhs(const Coef<R>& c, const typename cvec<R>::type (&cur)[2],
+                                           const typename cvec<R>::type (&lr)[2],
+                                           const typename cvec<R>::type (&ud)[2],
+                                           const typename cvec<R>::type (&dy)[2], R kv, R dir,
+                                           typename cvec<R>::type (&f)[2])
+{
+    using C = typename cvec<R>::type;
+    const R rho0 = fma(cur[0].x, cur[0].x, cur[0].y * cur[0].y);
+    const R rho1 = fma(cur[1].x, cur[1].x, cur[1].y * cur[1].y);
+    const R cb = R(2) * (c.bx - c.by);
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        const int o = 1 - s;
+        const C p = cur[s], q = cur[o];
+        const R om = fma(c.gh, s == 0 ? rho0 : rho1, fma(c.gxh, s == 0 ? rho1 : rho0, kv));
+        // other component's second differences: -bx (lr_o - 2q) + by (ud_o - 2q)
+        const R ox = fma(-c.bx, lr[o].x, fma(c.by, ud[o].x, cb * q.x));
+        const R oy = fma(-c.bx, lr[o].y, fma(c.by, ud[o].y, cb * q.y));
+        const R tx = fma(c.ax, lr[s].x, fma(c.ay, ud[s].x, ox));
+        const R ty = fma(c.ax, lr[s].y, fma(c.ay, ud[s].y, oy));
+        const R xx = dir * (lane_next(dy[o].x) - lane_prev(dy[o].x));
+        const R xy = dir * (lane_next(dy[o].y) - lane_prev(dy[o].y));
+        const R sb = s == 0 ? -c.bxy : c.bxy;
+        f[s].x = fma(sb, xx, fma(-c.half_gamma, p.x, fma(om, p.y, -ty)));
+        f[s].y = fma(sb, xy, fma(-c.half_gamma, p.y, fma(-om, p.x, tx)));
+    }
+}
+
+template <typename R, bool HASV, bool GHOSTS, bool YZERO, int B>
+__device__ __forceinline__ bool stream_band_spinor(const StepArgs<R>& a, int strip, int band, int dir)
+{
+    using C = typename cvec<R>::type;
+    static_assert((B + 8) % 24 == 0, "band rows + 8 must be a multiple of the unroll length");
+    constexpr int PF = 3;
+    const int lane = threadIdx.x & 63;
+    const Coef<R>& c = a.c;
+    const int gi = strip * 56 - 4 + lane;
+    const int ci = wrap_any(gi, a.nx, a.bcx);
+    const bool gcol = GHOSTS && ci < 0;
+    const int b0 = band * B;
+    const R kdiag = R(2) * (c.ax + c.ay);
+    const R rdir = (R)dir;
+    const size_t cells = (size_t)a.nx * a.ny;
+    const __amdgpu_buffer_rsrc_t rpo = buffer_of(a.psi_out, 2 * cells * sizeof(C));
+
+    C sp[2][8];
+    R sk[8];
+    unsigned int gmask = 0;
+    C acc[2][4];
+    C w2[2][3], w3[2][3], w4[2][3];
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+        sp[0][s] = sp[1][s] = czero<C>();
+        sk[s] = kdiag;
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s) acc[0][s] = acc[1][s] = czero<C>();
+#pragma unroll
+    for (int s = 0; s < 3; ++s)
+#pragma unroll
+        for (int m = 0; m < 2; ++m) w2[m][s] = w3[m][s] = w4[m][s] = czero<C>();
+
+    const int start = dir > 0 ? b0 - 4 : b0 + B + 3;
+    int g = start;
+    int rw = wrap_any(g, a.ny, a.bcy);
+    const int ci0 = ci < 0 ? 0 : ci;
+    auto fetch = [&](int s, bool use) {
+        const bool gh = GHOSTS && (gcol || rw < 0);
+        const int idx = gh ? 0 : rw * a.nx + ci0;
+        const C v0 = a.psi_in[idx];
+        const C v1 = a.psi_in[cells + idx];
+        sp[0][s] = gh ? czero<C>() : v0;
+        sp[1][s] = gh ? czero<C>() : v1;
+        if (HASV) {
+            const R vv = a.V[idx];
+            sk[s] = gh ? kdiag : fma(c.inv_hbar, vv, kdiag);
+        }
+        if (GHOSTS) gmask = (gmask & ~(1u << s)) | ((gh ? 1u : 0u) << s);
+        const int gn = g + dir;
+        int rn;
+        if (YZERO) {
+            rn = (gn >= 0 && gn < a.ny) ? gn : -1;
+        } else {
+            rn = rw + dir;
+            rn = rn == a.ny ? 0 : (rn < 0 ? a.ny - 1 : rn);
+        }
+        g = use ? gn : g;
+        rw = use ? rn : rw;
+    };
+#pragma unroll
+    for (int t = 0; t < PF; ++t) fetch(t, true);
+
+    // neighbour sums and y-differences of one stage argument (rows above, at, below
+    // in walking order) for both components
+    auto sums = [&](const C (&up)[2], const C (&cur)[2], const C (&dn)[2], C (&lr)[2], C (&ud)[2], C (&dy)[2]) {
+#pragma unroll
+        for (int m = 0; m < 2; ++m) {
+            lr[m] = C{lane_prev(cur[m].x) + lane_next(cur[m].x), lane_prev(cur[m].y) + lane_next(cur[m].y)};
+            ud[m] = C{up[m].x + dn[m].x, up[m].y + dn[m].y};
+            dy[m] = C{dn[m].x - up[m].x, dn[m].y - up[m].y};
+        }
+    };
+
+    bool bad = false;
+    const bool out_col = lane >= 4 && lane < 60 && gi < a.nx;
+    for (int base = 0; base < B + 8; base += 24) {
+#pragma unroll
+        for (int u = 0; u < 24; ++u) {
+            const int j = start + dir * (base + u);
+            fetch(slot<8>(u, -PF), base + u + PF < B + 8);
+            C f[2], lr[2], ud[2], dy[2];
+            // stage 1 at row j-1 from the input ring
+            {
+                const int s0 = slot<8>(u, 1);
+                const C cur[2] = {sp[0][s0], sp[1][s0]};
+                const C up[2] = {sp[0][slot<8>(u, 2)], sp[1][slot<8>(u, 2)]};
+                const C dn[2] = {sp[0][slot<8>(u, 0)], sp[1][slot<8>(u, 0)]};
+                sums(up, cur, dn, lr, ud, dy);
+                spinor_rhs<R>(c, cur, lr, ud, dy, sk[s0], rdir, f);
+                const bool gz = GHOSTS && ((gmask >> s0) & 1u);
+#pragma unroll
+                for (int m = 0; m < 2; ++m) {
+                    acc[m][slot<4>(u, 1)] = f[m];
+                    w2[m][slot<3>(u, 1)] =
+                        gz ? czero<C>() : C{fma(a.half_dt, f[m].x, cur[m].x), fma(a.half_dt, f[m].y, cur[m].y)};
+                }
+            }
+            // stage 2 at row j-2 from w2
+            {
+                const int s0 = slot<8>(u, 2);
+                const C cur[2] = {w2[0][slot<3>(u, 2)], w2[1][slot<3>(u, 2)]};
+                const C up[2] = {w2[0][slot<3>(u, 3)], w2[1][slot<3>(u, 3)]};
+                const C dn[2] = {w2[0][slot<3>(u, 1)], w2[1][slot<3>(u, 1)]};
+                sums(up, cur, dn, lr, ud, dy);
+                spinor_rhs<R>(c, cur, lr, ud, dy, sk[s0], rdir, f);
+                const bool gz = GHOSTS && ((gmask >> s0) & 1u);
+#pragma unroll
+                for (int m = 0; m < 2; ++m) {
+                    C& ac = acc[m][slot<4>(u, 2)];
+                    ac = C{fma(R(2), f[m].x, ac.x), fma(R(2), f[m].y, ac.y)};
+                    const C p0 = sp[m][s0];
+                    w3[m][slot<3>(u, 2)] =
+                        gz ? czero<C>() : C{fma(a.half_dt, f[m].x, p0.x), fma(a.half_dt, f[m].y, p0.y)};
+                }
+            }
+            // stage 3 at row j-3 from w3
+            {
+                const int s0 = slot<8>(u, 3);
+                const C cur[2] = {w3[0][slot<3>(u, 3)], w3[1][slot<3>(u, 3)]};
+                const C up[2] = {w3[0][slot<3>(u, 4)], w3[1][slot<3>(u, 4)]};
+                const C dn[2] = {w3[0][slot<3>(u, 2)], w3[1][slot<3>(u, 2)]};
+                sums(up, cur, dn, lr, ud, dy);
+                spinor_rhs<R>(c, cur, lr, ud, dy, sk[s0], rdir, f);
+                const bool gz = GHOSTS && ((gmask >> s0) & 1u);
+#pragma unroll
+                for (int m = 0; m < 2; ++m) {
+                    C& ac = acc[m][slot<4>(u, 3)];
+                    ac = C{fma(R(2), f[m].x, ac.x), fma(R(2), f[m].y, ac.y)};
+                    const C p0 = sp[m][s0];
+                    w4[m][slot<3>(u, 3)] = gz ? czero<C>() : C{fma(a.dt, f[m].x, p0.x), fma(a.dt, f[m].y, p0.y)};
+                }
+            }
+            // stage 4 at row j-4 from w4; the finished row is stored when it lies in the
+            // band and in the grid
+            {
+                const int s0 = slot<8>(u, 4);
+                const C cur[2] = {w4[0][slot<3>(u, 4)], w4[1][slot<3>(u, 4)]};
+                const C up[2] = {w4[0][slot<3>(u, 5)], w4[1][slot<3>(u, 5)]};
+                const C dn[2] = {w4[0][slot<3>(u, 3)], w4[1][slot<3>(u, 3)]};
+                sums(up, cur, dn, lr, ud, dy);
+                spinor_rhs<R>(c, cur, lr, ud, dy, sk[s0], rdir, f);
+                const int r = j - 4 * dir;
+                const bool st = out_col && r >= b0 && r < b0 + B && r < a.ny;
+                const int cell = r * a.nx + gi;
+#pragma unroll
+                for (int m = 0; m < 2; ++m) {
+                    const C ac = acc[m][slot<4>(u, 4)];
+                    const C p0 = sp[m][s0];
+                    const C y = C{fma(a.dt6, ac.x + f[m].x, p0.x), fma(a.dt6, ac.y + f[m].y, p0.y)};
+                    buf_store_nt(y, rpo, st ? (int)((m * cells + cell) * sizeof(C)) : kOutOfRange);
+                    bad = bad || (st && !(isfinite(y.x) && isfinite(y.y)));
+                }
+            }
+        }
+    }
+    return bad;
+}
+
+}  // namespace phx

@@ -124,7 +124,8 @@ def measure_batch(steps: int = 500, warmup: int = 20, count: int = 256, seed: in
 def measure_spinor(n: int = 4096, accepted: int = 20, rk4_steps: int = 50):
     """The spinor workload (inputs.spinor: two components, TE-TM coupling, cross
     interaction, disorder potential, zero boundaries, complex64) on an n x n grid:
-    RK4 with the stage-fused kernels (the two-component family), and Dormand-Prince
+    RK4 with the tuned kernel family (the two-component streaming whole-step kernel),
+    and Dormand-Prince
     with rtol = atol = 1e-6 from dt 1e-3 for `accepted` accepted steps.  Reports point
     updates per second (accepted steps for RK45), attempts, and per-kernel launch
     times with their algorithmic bandwidth."""
@@ -159,6 +160,7 @@ def measure_spinor(n: int = 4096, accepted: int = 20, rk4_steps: int = 50):
         if integ == "rk4":
             model = bytemodel.rk4_stage_fused(4, reservoir=False, has_v=True, components=2)
             names = {f"rk4_stage{k}": model[f"stage{k}"] for k in range(1, 5)}
+            names["rk4_step"] = bytemodel.rk4_whole_step(4, reservoir=False, has_v=True, components=2)["step"]
         else:
             model = bytemodel.dopri5_attempt(4, reservoir=False, has_v=True, components=2)
             names = {f"dp_stage{k}": model[f"stage{k}"] for k in range(2, 8)}

@@ -386,3 +386,64 @@ def test_kernel_timing_api():
     for s in range(1, 5):
         assert t[f"rk4_stage{s}"]["launches"] == 3 and t[f"rk4_stage{s}"]["ms_total"] > 0
     assert t["observables"]["launches"] == 1
+
+
+@pytest.mark.parametrize("precision", PREC)
+@pytest.mark.parametrize("rows", [40, 64])
+@pytest.mark.parametrize("bc", [(0, 0), (1, 1), (0, 1), (1, 0)])
+def test_spinor_stream_kernel(bc, rows, precision):
+    """The two-component streaming kernel (no reservoir): ragged grids over several
+    strips and bands, a single strip, odd and even step counts over two calls (graph
+    replays and direct launches), against the oracle."""
+    for shape in ((130, 97), (57, 203), (40, 41), (7, 5)):
+        ph, psi, n, V, P = workload("spinor", shape[0], shape[1], bc, seed=21)
+        q = quantize(precision, psi, n, V, P)
+        run = GpuRun(ph, *q, precision=precision, kernel=phx.PHX_KERNEL_STEP, tile_wx=1, tile_rows=rows,
+                     graph_steps=2)
+        run.step(5)
+        run.step(2)
+        g_psi, _ = run.state()
+        run.close()
+        o_psi, _ = oracle_rk4(ph, *q, 7)
+        e = rel_l2(g_psi, o_psi)
+        assert e <= TOL[precision], (shape, e)
+
+
+def _zero_patch(a, j, i, r):
+    """(2r+1)^2 patch of the last two axes around (j, i), zeros outside the grid."""
+    ny, nx = a.shape[-2:]
+    out = np.zeros(a.shape[:-2] + (2 * r + 1, 2 * r + 1), a.dtype)
+    j0, j1, i0, i1 = max(j - r, 0), min(j + r + 1, ny), max(i - r, 0), min(i + r + 1, nx)
+    out[..., j0 - (j - r):j1 - (j - r), i0 - (i - r):i1 - (i - r)] = a[..., j0:j1, i0:i1]
+    return out
+
+
+@pytest.mark.parametrize("steps", [1, 3])
+def test_spinor_4096_sampled(steps):
+    """The 4096^2 spinor workload (TE-TM, cross interaction, disorder, zero boundaries,
+    complex64) on the streaming kernel: sampled cells, corners and edges included,
+    against the oracle on zero-padded patches of radius 4 steps (a cell after k RK4
+    steps depends only on cells within 4k, diagonals included)."""
+    ph, psi0, V = inputs.spinor(4096)
+    q = quantize(C64, psi0, None, V, None)
+    run = GpuRun(ph, q[0], None, q[2], None, precision=C64)
+    run.step(steps)
+    g_psi, _ = run.state()
+    run.close()
+    r = 4 * steps
+    rng = np.random.default_rng(13)
+    pts = [(int(a), int(b)) for a, b in rng.integers(0, 4096, (40, 2))]
+    pts += [(0, 0), (0, 4095), (4095, 0), (4095, 4095), (2048, 2048), (3, 2000), (2000, 4093)]
+    # the condensate sits within a few hundred cells of the centre
+    pts += [(int(a), int(b)) for a, b in 2048 + rng.integers(-300, 300, (40, 2))]
+    op = oracle_physics(ph)
+    op.nx = op.ny = 2 * r + 1
+    got, exp = [], []
+    for j, i in pts:
+        o_psi, _ = oracle.rk4(op, _zero_patch(q[0], j, i, r), None, _zero_patch(q[2], j, i, r), None,
+                              dt=ph.dt, steps=steps)
+        got.append(g_psi[:, j, i])
+        exp.append(o_psi[:, r, r])
+    e = rel_l2(np.array(got), np.array(exp))
+    print(f"spinor 4096^2 sampled after {steps} steps: psi {e:.3e}")
+    assert e <= TOL[C64]
