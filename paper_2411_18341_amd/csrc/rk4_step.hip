@@ -130,7 +130,7 @@ static hipError_t launch_step_shape(const StepShapeId& sh, const StepArgs<R>& a,
 template <typename R>
 hipError_t launch_stream_drive(bool reservoir, bool has_v, int rows, const StepArgs<R>& a, hipStream_t s);
 template <typename R>
-hipError_t launch_stream_spinor(bool has_v, int rows, const StepArgs<R>& a, hipStream_t s);
+hipError_t launch_stream_spinor(bool reservoir, bool has_v, int rows, const StepArgs<R>& a, hipStream_t s);
 
 template <typename R>
 hipError_t launch_rk4_step(bool reservoir, bool has_v, const StepShapeId& sh, const StepArgs<R>& a,
@@ -138,7 +138,7 @@ hipError_t launch_rk4_step(bool reservoir, bool has_v, const StepShapeId& sh, co
 {
     if (a.E) return sh.waves == 1 ? launch_stream_drive<R>(reservoir, has_v, sh.rows, a, s) : hipErrorInvalidValue;
     if (a.comps == 2)
-        return sh.waves == 1 && !reservoir ? launch_stream_spinor<R>(has_v, sh.rows, a, s) : hipErrorInvalidValue;
+        return sh.waves == 1 ? launch_stream_spinor<R>(reservoir, has_v, sh.rows, a, s) : hipErrorInvalidValue;
     if (reservoir) return has_v ? launch_step_shape<R, true, true>(sh, a, s) : launch_step_shape<R, true, false>(sh, a, s);
     return has_v ? launch_step_shape<R, false, true>(sh, a, s) : launch_step_shape<R, false, false>(sh, a, s);
 }
@@ -269,7 +269,7 @@ phx_status rk4_fused_steps(phx_handle* h, int64_t n)
         void* alt = h->ws + h->L.alt;
         if (hipMemcpyAsync(alt, h->f.psi, cells * c.components * 2 * rs, hipMemcpyDeviceToDevice, h->stream) !=
                 hipSuccess ||
-            (c.reservoir && hipMemcpyAsync(h->ws + h->L.alt_n, h->f.n, cells * rs, hipMemcpyDeviceToDevice,
+            (c.reservoir && hipMemcpyAsync(h->ws + h->L.alt_n, h->f.n, cells * c.components * rs, hipMemcpyDeviceToDevice,
                                            h->stream) != hipSuccess))
             return fail(PHX_EHIP, "state copy failed");
         h->step_parity = 1;

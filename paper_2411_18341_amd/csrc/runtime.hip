@@ -54,9 +54,9 @@ phx_status validate_config(const phx_config* c)
     if (c->kernel < PHX_KERNEL_AUTO || c->kernel > PHX_KERNEL_STEP)
         return fail(PHX_EINVAL, "kernel=%d is not a PHX_KERNEL_* value", c->kernel);
     if (c->kernel == PHX_KERNEL_STEP &&
-        (c->integrator != PHX_RK4 || (c->components == 2 && (c->reservoir || c->drive || c->imag_time))))
+        (c->integrator != PHX_RK4 || (c->components == 2 && (c->drive || c->imag_time))))
         return fail(PHX_EUNSUPPORTED, "the whole-step kernel covers RK4 with one component, or two without the "
-                                      "reservoir, drive and imaginary time");
+                                      "drive and imaginary time");
     if ((c->tile_wx == 0) != (c->tile_rows == 0)) return fail(PHX_EINVAL, "tile_wx and tile_rows: both 0 or both set");
     if (c->tile_wx != 0) {
         if (c->integrator == PHX_RK4 && rk4_family(*c) == PHX_KERNEL_STEP) {
@@ -189,16 +189,16 @@ bool valid_step_shape(int precision, int waves, int rows)
 }
 
 // RK4 kernel family: the whole-step kernel (one launch per step, state read and
-// written once) for one component and for the spinor without the reservoir (its
-// streaming form; also with the drive or in imaginary time for one component), the
-// stage-fused kernels otherwise or on request.
+// written once) for one component and for the spinor (its streaming form; also with
+// the drive or in imaginary time for one component), the stage-fused kernels
+// otherwise or on request.
 int rk4_family(const phx_config& c)
 {
     if (c.kernel == PHX_KERNEL_STAGE) return PHX_KERNEL_STAGE;
     if (c.imag_time || c.drive)  // the streaming form when it fits, else the stage-fused kernels
         return (c.components == 1 && step_shape_fits(c, 1)) ? PHX_KERNEL_STEP : PHX_KERNEL_STAGE;
     if (c.components == 1) return PHX_KERNEL_STEP;
-    if (!c.reservoir && step_shape_fits(c, 1)) return PHX_KERNEL_STEP;  // spinor: streaming form
+    if (step_shape_fits(c, 1)) return PHX_KERNEL_STEP;  // spinor: streaming form
     return PHX_KERNEL_STAGE;
 }
 

@@ -1,7 +1,8 @@
 // Device code of the streaming whole-step RK4 kernel for the two-component (spinor)
-// form of Eq. (PULSE_psi) without the reservoir: self and cross interaction, the
-// potential and the TE-TM coupling J_+- = Delta_LT (d_x -+ i d_y)^2, whose mixed
-// derivative needs the diagonal neighbours of the other component.
+// form of Eqs. (PULSE_psi), (PULSE_res): self and cross interaction, the potential,
+// the TE-TM coupling J_+- = Delta_LT (d_x -+ i d_y)^2, whose mixed derivative needs
+// the diagonal neighbours of the other component, and (RES) the reservoirs n_+-
+// with gain, reservoir interaction and pumps P_+-.
 //
 // The band walk is the one-component kernel's (stream_body.h): one wave per strip of
 // 56 columns plus a 4-column halo, rows walked once with the four stages pipelined
@@ -19,17 +20,20 @@ namespace phx {
 
 // f_s for both components from the stage arguments (cur), the neighbour sums in x
 // (lr) and y (ud), the y-differences of the rows below and above (dy = below - above,
-// for the mixed term) and the per-cell constant kv = V/hbar + 2 (ax + ay).
-//   f_s = i T_s + (-gamma/2 - i om_s) p_s - sgn_s bxy X_o,
+// for the mixed term), the per-cell constant kv = V/hbar + 2 (ax + ay) and (RES) the
+// reservoir values nn and pumps pv.
+//   f_s = i T_s + (u_s - i om_s) p_s - sgn_s bxy X_o,   u_s = (R n_s - gamma)/2,
 //   T_s = ax lr_s + ay ud_s - 2(ax + ay) p_s - bx (lr_o - 2 q) + by (ud_o - 2 q),
-//   om_s = V/hbar + gh rho_s + gxh rho_o (the -2(ax + ay) p_s term folded into kv),
+//   om_s = V/hbar + gh rho_s + gxh rho_o + grh n_s (the -2(ax + ay) p_s term folded into kv),
+//   fn_s = P_s - (gamma_r + R rho_s) n_s,
 // X_o = dir (next(dy_o) - prev(dy_o)), sgn = +1 for psi_+, -1 for psi_-.
-template <typename R>
+template <typename R, bool RES>
 __device__ __forceinline__ void spinor_rhs(const Coef<R>& c, const typename cvec<R>::type (&cur)[2],
                                            const typename cvec<R>::type (&lr)[2],
                                            const typename cvec<R>::type (&ud)[2],
                                            const typename cvec<R>::type (&dy)[2], R kv, R dir,
-                                           typename cvec<R>::type (&f)[2])
+                                           const R (&nn)[2], const R (&pv)[2], typename cvec<R>::type (&f)[2],
+                                           R (&fn)[2])
 {
     using C = typename cvec<R>::type;
     const R rho0 = fma(cur[0].x, cur[0].x, cur[0].y * cur[0].y);
@@ -39,7 +43,11 @@ __device__ __forceinline__ void spinor_rhs(const Coef<R>& c, const typename cvec
     for (int s = 0; s < 2; ++s) {
         const int o = 1 - s;
         const C p = cur[s], q = cur[o];
-        const R om = fma(c.gh, s == 0 ? rho0 : rho1, fma(c.gxh, s == 0 ? rho1 : rho0, kv));
+        const R rs = s == 0 ? rho0 : rho1;
+        R om = fma(c.gh, rs, fma(c.gxh, s == 0 ? rho1 : rho0, kv));
+        if (RES) om = fma(c.grh, nn[s], om);
+        const R u = RES ? fma(c.half_R, nn[s], -c.half_gamma) : -c.half_gamma;
+        fn[s] = RES ? fma(-fma(c.R_, rs, c.gamma_r), nn[s], pv[s]) : R(0);
         // other component's second differences: -bx (lr_o - 2q) + by (ud_o - 2q)
         const R ox = fma(-c.bx, lr[o].x, fma(c.by, ud[o].x, cb * q.x));
         const R oy = fma(-c.bx, lr[o].y, fma(c.by, ud[o].y, cb * q.y));
@@ -48,12 +56,12 @@ __device__ __forceinline__ void spinor_rhs(const Coef<R>& c, const typename cvec
         const R xx = dir * (lane_next(dy[o].x) - lane_prev(dy[o].x));
         const R xy = dir * (lane_next(dy[o].y) - lane_prev(dy[o].y));
         const R sb = s == 0 ? -c.bxy : c.bxy;
-        f[s].x = fma(sb, xx, fma(-c.half_gamma, p.x, fma(om, p.y, -ty)));
-        f[s].y = fma(sb, xy, fma(-c.half_gamma, p.y, fma(-om, p.x, tx)));
+        f[s].x = fma(sb, xx, fma(u, p.x, fma(om, p.y, -ty)));
+        f[s].y = fma(sb, xy, fma(u, p.y, fma(-om, p.x, tx)));
     }
 }
 
-template <typename R, bool HASV, bool GHOSTS, bool YZERO, int B>
+template <typename R, bool RES, bool HASV, bool GHOSTS, bool YZERO, int B>
 __device__ __forceinline__ bool stream_band_spinor(const StepArgs<R>& a, int strip, int band, int dir)
 {
     using C = typename cvec<R>::type;
@@ -69,23 +77,35 @@ __device__ __forceinline__ bool stream_band_spinor(const StepArgs<R>& a, int str
     const R rdir = (R)dir;
     const size_t cells = (size_t)a.nx * a.ny;
     const __amdgpu_buffer_rsrc_t rpo = buffer_of(a.psi_out, 2 * cells * sizeof(C));
+    const __amdgpu_buffer_rsrc_t rno = buffer_of(a.n_out, RES ? 2 * cells * sizeof(R) : 0);
 
     C sp[2][8];
     R sk[8];
+    R sn[2][8], sP[2][8];
     unsigned int gmask = 0;
     C acc[2][4];
+    R accn[2][4];
     C w2[2][3], w3[2][3], w4[2][3];
+    R n2[2][2], n3[2][2], n4[2][2];
 #pragma unroll
     for (int s = 0; s < 8; ++s) {
         sp[0][s] = sp[1][s] = czero<C>();
+        sn[0][s] = sn[1][s] = sP[0][s] = sP[1][s] = R(0);
         sk[s] = kdiag;
     }
 #pragma unroll
-    for (int s = 0; s < 4; ++s) acc[0][s] = acc[1][s] = czero<C>();
+    for (int s = 0; s < 4; ++s) {
+        acc[0][s] = acc[1][s] = czero<C>();
+        accn[0][s] = accn[1][s] = R(0);
+    }
 #pragma unroll
     for (int s = 0; s < 3; ++s)
 #pragma unroll
         for (int m = 0; m < 2; ++m) w2[m][s] = w3[m][s] = w4[m][s] = czero<C>();
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int m = 0; m < 2; ++m) n2[m][s] = n3[m][s] = n4[m][s] = R(0);
 
     const int start = dir > 0 ? b0 - 4 : b0 + B + 3;
     int g = start;
@@ -98,6 +118,15 @@ __device__ __forceinline__ bool stream_band_spinor(const StepArgs<R>& a, int str
         const C v1 = a.psi_in[cells + idx];
         sp[0][s] = gh ? czero<C>() : v0;
         sp[1][s] = gh ? czero<C>() : v1;
+        if (RES) {
+#pragma unroll
+            for (int m = 0; m < 2; ++m) {
+                const R nv = a.n_in[m * cells + idx];
+                const R pv = a.P[m * cells + idx];
+                sn[m][s] = gh ? R(0) : nv;
+                sP[m][s] = gh ? R(0) : pv;
+            }
+        }
         if (HASV) {
             const R vv = a.V[idx];
             sk[s] = gh ? kdiag : fma(c.inv_hbar, vv, kdiag);
@@ -136,6 +165,7 @@ __device__ __forceinline__ bool stream_band_spinor(const StepArgs<R>& a, int str
             const int j = start + dir * (base + u);
             fetch(slot<8>(u, -PF), base + u + PF < B + 8);
             C f[2], lr[2], ud[2], dy[2];
+            R fn[2], nn[2], pv[2];
             // stage 1 at row j-1 from the input ring
             {
                 const int s0 = slot<8>(u, 1);
@@ -143,13 +173,22 @@ __device__ __forceinline__ bool stream_band_spinor(const StepArgs<R>& a, int str
                 const C up[2] = {sp[0][slot<8>(u, 2)], sp[1][slot<8>(u, 2)]};
                 const C dn[2] = {sp[0][slot<8>(u, 0)], sp[1][slot<8>(u, 0)]};
                 sums(up, cur, dn, lr, ud, dy);
-                spinor_rhs<R>(c, cur, lr, ud, dy, sk[s0], rdir, f);
+#pragma unroll
+                for (int m = 0; m < 2; ++m) {
+                    nn[m] = sn[m][s0];
+                    pv[m] = sP[m][s0];
+                }
+                spinor_rhs<R, RES>(c, cur, lr, ud, dy, sk[s0], rdir, nn, pv, f, fn);
                 const bool gz = GHOSTS && ((gmask >> s0) & 1u);
 #pragma unroll
                 for (int m = 0; m < 2; ++m) {
                     acc[m][slot<4>(u, 1)] = f[m];
                     w2[m][slot<3>(u, 1)] =
                         gz ? czero<C>() : C{fma(a.half_dt, f[m].x, cur[m].x), fma(a.half_dt, f[m].y, cur[m].y)};
+                    if (RES) {
+                        accn[m][slot<4>(u, 1)] = fn[m];
+                        n2[m][slot<2>(u, 1)] = gz ? R(0) : fma(a.half_dt, fn[m], sn[m][s0]);
+                    }
                 }
             }
             // stage 2 at row j-2 from w2
@@ -159,7 +198,12 @@ __device__ __forceinline__ bool stream_band_spinor(const StepArgs<R>& a, int str
                 const C up[2] = {w2[0][slot<3>(u, 3)], w2[1][slot<3>(u, 3)]};
                 const C dn[2] = {w2[0][slot<3>(u, 1)], w2[1][slot<3>(u, 1)]};
                 sums(up, cur, dn, lr, ud, dy);
-                spinor_rhs<R>(c, cur, lr, ud, dy, sk[s0], rdir, f);
+#pragma unroll
+                for (int m = 0; m < 2; ++m) {
+                    nn[m] = n2[m][slot<2>(u, 2)];
+                    pv[m] = sP[m][s0];
+                }
+                spinor_rhs<R, RES>(c, cur, lr, ud, dy, sk[s0], rdir, nn, pv, f, fn);
                 const bool gz = GHOSTS && ((gmask >> s0) & 1u);
 #pragma unroll
                 for (int m = 0; m < 2; ++m) {
@@ -168,6 +212,10 @@ __device__ __forceinline__ bool stream_band_spinor(const StepArgs<R>& a, int str
                     const C p0 = sp[m][s0];
                     w3[m][slot<3>(u, 2)] =
                         gz ? czero<C>() : C{fma(a.half_dt, f[m].x, p0.x), fma(a.half_dt, f[m].y, p0.y)};
+                    if (RES) {
+                        accn[m][slot<4>(u, 2)] = fma(R(2), fn[m], accn[m][slot<4>(u, 2)]);
+                        n3[m][slot<2>(u, 2)] = gz ? R(0) : fma(a.half_dt, fn[m], sn[m][s0]);
+                    }
                 }
             }
             // stage 3 at row j-3 from w3
@@ -177,7 +225,12 @@ __device__ __forceinline__ bool stream_band_spinor(const StepArgs<R>& a, int str
                 const C up[2] = {w3[0][slot<3>(u, 4)], w3[1][slot<3>(u, 4)]};
                 const C dn[2] = {w3[0][slot<3>(u, 2)], w3[1][slot<3>(u, 2)]};
                 sums(up, cur, dn, lr, ud, dy);
-                spinor_rhs<R>(c, cur, lr, ud, dy, sk[s0], rdir, f);
+#pragma unroll
+                for (int m = 0; m < 2; ++m) {
+                    nn[m] = n3[m][slot<2>(u, 3)];
+                    pv[m] = sP[m][s0];
+                }
+                spinor_rhs<R, RES>(c, cur, lr, ud, dy, sk[s0], rdir, nn, pv, f, fn);
                 const bool gz = GHOSTS && ((gmask >> s0) & 1u);
 #pragma unroll
                 for (int m = 0; m < 2; ++m) {
@@ -185,6 +238,10 @@ __device__ __forceinline__ bool stream_band_spinor(const StepArgs<R>& a, int str
                     ac = C{fma(R(2), f[m].x, ac.x), fma(R(2), f[m].y, ac.y)};
                     const C p0 = sp[m][s0];
                     w4[m][slot<3>(u, 3)] = gz ? czero<C>() : C{fma(a.dt, f[m].x, p0.x), fma(a.dt, f[m].y, p0.y)};
+                    if (RES) {
+                        accn[m][slot<4>(u, 3)] = fma(R(2), fn[m], accn[m][slot<4>(u, 3)]);
+                        n4[m][slot<2>(u, 3)] = gz ? R(0) : fma(a.dt, fn[m], sn[m][s0]);
+                    }
                 }
             }
             // stage 4 at row j-4 from w4; the finished row is stored when it lies in the
@@ -195,7 +252,12 @@ __device__ __forceinline__ bool stream_band_spinor(const StepArgs<R>& a, int str
                 const C up[2] = {w4[0][slot<3>(u, 5)], w4[1][slot<3>(u, 5)]};
                 const C dn[2] = {w4[0][slot<3>(u, 3)], w4[1][slot<3>(u, 3)]};
                 sums(up, cur, dn, lr, ud, dy);
-                spinor_rhs<R>(c, cur, lr, ud, dy, sk[s0], rdir, f);
+#pragma unroll
+                for (int m = 0; m < 2; ++m) {
+                    nn[m] = n4[m][slot<2>(u, 4)];
+                    pv[m] = sP[m][s0];
+                }
+                spinor_rhs<R, RES>(c, cur, lr, ud, dy, sk[s0], rdir, nn, pv, f, fn);
                 const int r = j - 4 * dir;
                 const bool st = out_col && r >= b0 && r < b0 + B && r < a.ny;
                 const int cell = r * a.nx + gi;
@@ -205,7 +267,13 @@ __device__ __forceinline__ bool stream_band_spinor(const StepArgs<R>& a, int str
                     const C p0 = sp[m][s0];
                     const C y = C{fma(a.dt6, ac.x + f[m].x, p0.x), fma(a.dt6, ac.y + f[m].y, p0.y)};
                     buf_store_nt(y, rpo, st ? (int)((m * cells + cell) * sizeof(C)) : kOutOfRange);
-                    bad = bad || (st && !(isfinite(y.x) && isfinite(y.y)));
+                    bool b = !(isfinite(y.x) && isfinite(y.y));
+                    if (RES) {
+                        const R yn = fma(a.dt6, accn[m][slot<4>(u, 4)] + fn[m], sn[m][s0]);
+                        buf_store_nt(yn, rno, st ? (int)((m * cells + cell) * sizeof(R)) : kOutOfRange);
+                        b = b || !isfinite(yn);
+                    }
+                    bad = bad || (st && b);
                 }
             }
         }

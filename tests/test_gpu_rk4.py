@@ -391,22 +391,24 @@ def test_kernel_timing_api():
 @pytest.mark.parametrize("precision", PREC)
 @pytest.mark.parametrize("rows", [40, 64])
 @pytest.mark.parametrize("bc", [(0, 0), (1, 1), (0, 1), (1, 0)])
-def test_spinor_stream_kernel(bc, rows, precision):
-    """The two-component streaming kernel (no reservoir): ragged grids over several
-    strips and bands, a single strip, odd and even step counts over two calls (graph
-    replays and direct launches), against the oracle."""
+@pytest.mark.parametrize("kind", ["spinor", "spinor_res"])
+def test_spinor_stream_kernel(kind, bc, rows, precision):
+    """The two-component streaming kernel, with and without the reservoirs: ragged
+    grids over several strips and bands, a single strip, odd and even step counts over
+    two calls (graph replays and direct launches), against the oracle."""
     for shape in ((130, 97), (57, 203), (40, 41), (7, 5)):
-        ph, psi, n, V, P = workload("spinor", shape[0], shape[1], bc, seed=21)
+        ph, psi, n, V, P = workload(kind, shape[0], shape[1], bc, seed=21)
         q = quantize(precision, psi, n, V, P)
         run = GpuRun(ph, *q, precision=precision, kernel=phx.PHX_KERNEL_STEP, tile_wx=1, tile_rows=rows,
                      graph_steps=2)
         run.step(5)
         run.step(2)
-        g_psi, _ = run.state()
+        g_psi, g_n = run.state()
         run.close()
-        o_psi, _ = oracle_rk4(ph, *q, 7)
+        o_psi, o_n = oracle_rk4(ph, *q, 7)
         e = rel_l2(g_psi, o_psi)
-        assert e <= TOL[precision], (shape, e)
+        e_n = rel_l2(g_n, o_n) if ph.reservoir else 0.0
+        assert e <= TOL[precision] and e_n <= TOL[precision], (shape, e, e_n)
 
 
 def _zero_patch(a, j, i, r):
