@@ -116,6 +116,10 @@ __device__ __forceinline__ bool stream_band(const StepArgs<R>& a, int strip, int
     const int gi = strip * 56 - 4 + lane;
     const int ci = wrap_any(gi, a.nx, a.bcx);
     const bool gcol = GHOSTS && ci < 0;
+    const R keep = gcol ? R(0) : R(1);  // ghost columns stay 0 in every stage
+    R rowk[8];                           // 0 for ghost rows (zero y boundary), else 1
+#pragma unroll
+    for (int s = 0; s < 8; ++s) rowk[s] = R(1);
     const int b0 = band * B;
     const R kdiag = R(2) * (c.ax + c.ay);
     const size_t cells = (size_t)a.nx * a.ny;
@@ -140,10 +144,12 @@ __device__ __forceinline__ bool stream_band(const StepArgs<R>& a, int strip, int
         fy = fma(-c.inv_hbar, zx, fy);
     };
 
-    // 8-row ring of inputs; ghost flags in bit s of gmask
+    // 8-row ring of inputs.  Zero boundaries: ghost cells load from a block of zeros
+    // (a.zeros), and every stage argument is multiplied by keep (0 in ghost columns)
+    // and by the row factor of its ring slot (0 in ghost rows), which leaves the other
+    // cells' values unchanged.
     C sp[8];
     R sn[8], sP[8], sk[8];
-    unsigned int gmask = 0;
     C acc[4];
     R accn[4];
     C w2[3], w3[3], w4[3];
@@ -176,26 +182,26 @@ __device__ __forceinline__ bool stream_band(const StepArgs<R>& a, int strip, int
     auto fetch = [&](int s, bool use) {
         const bool gh = GHOSTS && (gcol || rw < 0);
         const int idx = gh ? 0 : rw * a.nx + ci0;
-        const C v = a.psi_in[idx];
+        // ghost cells read a block of zeros instead of the arrays
+        const C* pp = gh ? (const C*)a.zeros : a.psi_in + idx;
+        const C v = *pp;
         if constexpr (IMAG)
-            sp[s] = gh ? czero<C>() : C{v.x * sc, v.y * sc};
+            sp[s] = C{v.x * sc, v.y * sc};
         else
-            sp[s] = gh ? czero<C>() : v;
+            sp[s] = v;
         if (RES) {
-            const R nv = a.n_in[idx];
-            const R pv = a.P[idx];
-            sn[s] = gh ? R(0) : nv;
-            sP[s] = gh ? R(0) : pv;
+            sn[s] = *(gh ? (const R*)a.zeros : a.n_in + idx);
+            sP[s] = *(gh ? (const R*)a.zeros : a.P + idx);
         }
         if (HASV) {
-            const R vv = a.V[idx];
-            sk[s] = gh ? kdiag : fma(c.inv_hbar, vv, kdiag);
+            const R vv = *(gh ? (const R*)a.zeros : a.V + idx);
+            sk[s] = fma(c.inv_hbar, vv, kdiag);
         }
         if constexpr (DRIVE) {
             const C ev = a.E[idx];
             sE[s] = gh ? czero<C>() : ev;
         }
-        if (GHOSTS) gmask = (gmask & ~(1u << s)) | ((gh ? 1u : 0u) << s);
+        if (YZERO) rowk[s] = rw < 0 ? R(0) : R(1);
         const int gn = g + dir;
         int rn;
         if (YZERO) {
@@ -227,11 +233,11 @@ __device__ __forceinline__ bool stream_band(const StepArgs<R>& a, int strip, int
                 const R lry = lane_prev(cur.y) + lane_next(cur.y);
                 cell_rhs<R, RES, IMAG>(c, cur, lrx, lry, up.x + dn.x, up.y + dn.y, sn[s0], sP[s0], sk[s0], fx, fy, fn);
                 if constexpr (DRIVE) drive(fx, fy, sE[s0], ph[0]);
-                const bool g = GHOSTS && ((gmask >> s0) & 1u);
+                const R kk = YZERO ? keep * rowk[s0] : keep;
                 acc[slot<4>(u, 1)] = C{fx, fy};
                 accn[slot<4>(u, 1)] = fn;
-                w2[slot<3>(u, 1)] = g ? czero<C>() : C{fma(a.half_dt, fx, cur.x), fma(a.half_dt, fy, cur.y)};
-                n2[slot<2>(u, 1)] = g ? R(0) : fma(a.half_dt, fn, sn[s0]);
+                w2[slot<3>(u, 1)] = C{kk * fma(a.half_dt, fx, cur.x), kk * fma(a.half_dt, fy, cur.y)};
+                n2[slot<2>(u, 1)] = kk * fma(a.half_dt, fn, sn[s0]);
             }
             // stage 2 at row j-2: argument in w2 (rows j-3..j-1)
             {
@@ -243,13 +249,13 @@ __device__ __forceinline__ bool stream_band(const StepArgs<R>& a, int strip, int
                 const R lry = lane_prev(cur.y) + lane_next(cur.y);
                 cell_rhs<R, RES, IMAG>(c, cur, lrx, lry, up.x + dn.x, up.y + dn.y, nn, sP[s0], sk[s0], fx, fy, fn);
                 if constexpr (DRIVE) drive(fx, fy, sE[s0], ph[1]);
-                const bool g = GHOSTS && ((gmask >> s0) & 1u);
+                const R kk = YZERO ? keep * rowk[s0] : keep;
                 C& ac = acc[slot<4>(u, 2)];
                 ac = C{fma(R(2), fx, ac.x), fma(R(2), fy, ac.y)};
                 accn[slot<4>(u, 2)] = fma(R(2), fn, accn[slot<4>(u, 2)]);
                 const C p0 = sp[s0];
-                w3[slot<3>(u, 2)] = g ? czero<C>() : C{fma(a.half_dt, fx, p0.x), fma(a.half_dt, fy, p0.y)};
-                n3[slot<2>(u, 2)] = g ? R(0) : fma(a.half_dt, fn, sn[s0]);
+                w3[slot<3>(u, 2)] = C{kk * fma(a.half_dt, fx, p0.x), kk * fma(a.half_dt, fy, p0.y)};
+                n3[slot<2>(u, 2)] = kk * fma(a.half_dt, fn, sn[s0]);
             }
             // stage 3 at row j-3: argument in w3 (rows j-4..j-2)
             {
@@ -261,13 +267,13 @@ __device__ __forceinline__ bool stream_band(const StepArgs<R>& a, int strip, int
                 const R lry = lane_prev(cur.y) + lane_next(cur.y);
                 cell_rhs<R, RES, IMAG>(c, cur, lrx, lry, up.x + dn.x, up.y + dn.y, nn, sP[s0], sk[s0], fx, fy, fn);
                 if constexpr (DRIVE) drive(fx, fy, sE[s0], ph[2]);
-                const bool g = GHOSTS && ((gmask >> s0) & 1u);
+                const R kk = YZERO ? keep * rowk[s0] : keep;
                 C& ac = acc[slot<4>(u, 3)];
                 ac = C{fma(R(2), fx, ac.x), fma(R(2), fy, ac.y)};
                 accn[slot<4>(u, 3)] = fma(R(2), fn, accn[slot<4>(u, 3)]);
                 const C p0 = sp[s0];
-                w4[slot<3>(u, 3)] = g ? czero<C>() : C{fma(a.dt, fx, p0.x), fma(a.dt, fy, p0.y)};
-                n4[slot<2>(u, 3)] = g ? R(0) : fma(a.dt, fn, sn[s0]);
+                w4[slot<3>(u, 3)] = C{kk * fma(a.dt, fx, p0.x), kk * fma(a.dt, fy, p0.y)};
+                n4[slot<2>(u, 3)] = kk * fma(a.dt, fn, sn[s0]);
             }
             // stage 4 at row j-4: argument in w4 (rows j-5..j-3); the row is finished and
             // stored when it lies in the band and in the grid (else the offset is out of

@@ -72,6 +72,7 @@ __device__ __forceinline__ bool stream_band_spinor(const StepArgs<R>& a, int str
     const int gi = strip * 56 - 4 + lane;
     const int ci = wrap_any(gi, a.nx, a.bcx);
     const bool gcol = GHOSTS && ci < 0;
+    const R keep = gcol ? R(0) : R(1);  // ghost columns stay 0 in every stage
     const int b0 = band * B;
     const R kdiag = R(2) * (c.ax + c.ay);
     const R rdir = (R)dir;
@@ -82,7 +83,7 @@ __device__ __forceinline__ bool stream_band_spinor(const StepArgs<R>& a, int str
     C sp[2][8];
     R sk[8];
     R sn[2][8], sP[2][8];
-    unsigned int gmask = 0;
+    R rowk[8];  // 0 for ghost rows (zero y boundary), else 1
     C acc[2][4];
     R accn[2][4];
     C w2[2][3], w3[2][3], w4[2][3];
@@ -92,6 +93,7 @@ __device__ __forceinline__ bool stream_band_spinor(const StepArgs<R>& a, int str
         sp[0][s] = sp[1][s] = czero<C>();
         sn[0][s] = sn[1][s] = sP[0][s] = sP[1][s] = R(0);
         sk[s] = kdiag;
+        rowk[s] = R(1);
     }
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
@@ -114,24 +116,22 @@ __device__ __forceinline__ bool stream_band_spinor(const StepArgs<R>& a, int str
     auto fetch = [&](int s, bool use) {
         const bool gh = GHOSTS && (gcol || rw < 0);
         const int idx = gh ? 0 : rw * a.nx + ci0;
-        const C v0 = a.psi_in[idx];
-        const C v1 = a.psi_in[cells + idx];
-        sp[0][s] = gh ? czero<C>() : v0;
-        sp[1][s] = gh ? czero<C>() : v1;
+        // ghost cells read a block of zeros instead of the arrays
+        const C* z = (const C*)a.zeros;
+        sp[0][s] = *(gh ? z : a.psi_in + idx);
+        sp[1][s] = *(gh ? z : a.psi_in + cells + idx);
         if (RES) {
 #pragma unroll
             for (int m = 0; m < 2; ++m) {
-                const R nv = a.n_in[m * cells + idx];
-                const R pv = a.P[m * cells + idx];
-                sn[m][s] = gh ? R(0) : nv;
-                sP[m][s] = gh ? R(0) : pv;
+                sn[m][s] = *(gh ? (const R*)a.zeros : a.n_in + m * cells + idx);
+                sP[m][s] = *(gh ? (const R*)a.zeros : a.P + m * cells + idx);
             }
         }
         if (HASV) {
-            const R vv = a.V[idx];
-            sk[s] = gh ? kdiag : fma(c.inv_hbar, vv, kdiag);
+            const R vv = *(gh ? (const R*)a.zeros : a.V + idx);
+            sk[s] = fma(c.inv_hbar, vv, kdiag);
         }
-        if (GHOSTS) gmask = (gmask & ~(1u << s)) | ((gh ? 1u : 0u) << s);
+        if (YZERO) rowk[s] = rw < 0 ? R(0) : R(1);
         const int gn = g + dir;
         int rn;
         if (YZERO) {
@@ -179,15 +179,14 @@ __device__ __forceinline__ bool stream_band_spinor(const StepArgs<R>& a, int str
                     pv[m] = sP[m][s0];
                 }
                 spinor_rhs<R, RES>(c, cur, lr, ud, dy, sk[s0], rdir, nn, pv, f, fn);
-                const bool gz = GHOSTS && ((gmask >> s0) & 1u);
+                const R kk = YZERO ? keep * rowk[s0] : keep;
 #pragma unroll
                 for (int m = 0; m < 2; ++m) {
                     acc[m][slot<4>(u, 1)] = f[m];
-                    w2[m][slot<3>(u, 1)] =
-                        gz ? czero<C>() : C{fma(a.half_dt, f[m].x, cur[m].x), fma(a.half_dt, f[m].y, cur[m].y)};
+                    w2[m][slot<3>(u, 1)] = C{kk * fma(a.half_dt, f[m].x, cur[m].x), kk * fma(a.half_dt, f[m].y, cur[m].y)};
                     if (RES) {
                         accn[m][slot<4>(u, 1)] = fn[m];
-                        n2[m][slot<2>(u, 1)] = gz ? R(0) : fma(a.half_dt, fn[m], sn[m][s0]);
+                        n2[m][slot<2>(u, 1)] = kk * fma(a.half_dt, fn[m], sn[m][s0]);
                     }
                 }
             }
@@ -204,17 +203,16 @@ __device__ __forceinline__ bool stream_band_spinor(const StepArgs<R>& a, int str
                     pv[m] = sP[m][s0];
                 }
                 spinor_rhs<R, RES>(c, cur, lr, ud, dy, sk[s0], rdir, nn, pv, f, fn);
-                const bool gz = GHOSTS && ((gmask >> s0) & 1u);
+                const R kk = YZERO ? keep * rowk[s0] : keep;
 #pragma unroll
                 for (int m = 0; m < 2; ++m) {
                     C& ac = acc[m][slot<4>(u, 2)];
                     ac = C{fma(R(2), f[m].x, ac.x), fma(R(2), f[m].y, ac.y)};
                     const C p0 = sp[m][s0];
-                    w3[m][slot<3>(u, 2)] =
-                        gz ? czero<C>() : C{fma(a.half_dt, f[m].x, p0.x), fma(a.half_dt, f[m].y, p0.y)};
+                    w3[m][slot<3>(u, 2)] = C{kk * fma(a.half_dt, f[m].x, p0.x), kk * fma(a.half_dt, f[m].y, p0.y)};
                     if (RES) {
                         accn[m][slot<4>(u, 2)] = fma(R(2), fn[m], accn[m][slot<4>(u, 2)]);
-                        n3[m][slot<2>(u, 2)] = gz ? R(0) : fma(a.half_dt, fn[m], sn[m][s0]);
+                        n3[m][slot<2>(u, 2)] = kk * fma(a.half_dt, fn[m], sn[m][s0]);
                     }
                 }
             }
@@ -231,16 +229,16 @@ __device__ __forceinline__ bool stream_band_spinor(const StepArgs<R>& a, int str
                     pv[m] = sP[m][s0];
                 }
                 spinor_rhs<R, RES>(c, cur, lr, ud, dy, sk[s0], rdir, nn, pv, f, fn);
-                const bool gz = GHOSTS && ((gmask >> s0) & 1u);
+                const R kk = YZERO ? keep * rowk[s0] : keep;
 #pragma unroll
                 for (int m = 0; m < 2; ++m) {
                     C& ac = acc[m][slot<4>(u, 3)];
                     ac = C{fma(R(2), f[m].x, ac.x), fma(R(2), f[m].y, ac.y)};
                     const C p0 = sp[m][s0];
-                    w4[m][slot<3>(u, 3)] = gz ? czero<C>() : C{fma(a.dt, f[m].x, p0.x), fma(a.dt, f[m].y, p0.y)};
+                    w4[m][slot<3>(u, 3)] = C{kk * fma(a.dt, f[m].x, p0.x), kk * fma(a.dt, f[m].y, p0.y)};
                     if (RES) {
                         accn[m][slot<4>(u, 3)] = fma(R(2), fn[m], accn[m][slot<4>(u, 3)]);
-                        n4[m][slot<2>(u, 3)] = gz ? R(0) : fma(a.dt, fn[m], sn[m][s0]);
+                        n4[m][slot<2>(u, 3)] = kk * fma(a.dt, fn[m], sn[m][s0]);
                     }
                 }
             }
