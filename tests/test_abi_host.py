@@ -92,17 +92,20 @@ def test_workspace_bytes_scale_with_precision_and_reservoir():
     d = phx.phx_workspace_bytes(good_config(kernel=phx.PHX_KERNEL_STEP))
     assert 2 * 64 * 48 * 8 <= d < a
     assert phx.phx_workspace_bytes(good_config()) == d  # AUTO picks the whole-step kernel
-    # spinor: the streaming whole-step kernel without the reservoir (two state buffers
-    # of both components), bands of 40 or 64 rows; with the reservoir not available
+    # spinor: the streaming whole-step kernel (two state buffers of both components,
+    # with the reservoir two of both reservoirs), bands of 40 or 64 rows; not with the
+    # drive or in imaginary time
     s = phx.phx_workspace_bytes(good_config(kernel=phx.PHX_KERNEL_STEP, components=2, delta_lt=0.1))
     assert 2 * 2 * 64 * 48 * 8 <= s
     assert phx.phx_workspace_bytes(good_config(components=2, delta_lt=0.1)) == s
+    sr = phx.phx_workspace_bytes(good_config(kernel=phx.PHX_KERNEL_STEP, components=2, reservoir=True))
+    assert sr >= s + 2 * 2 * 64 * 48 * 4
     for bad in (dict(tile_wx=8, tile_rows=4), dict(tile_wx=1, tile_rows=88)):
         with pytest.raises(phx.PhxError) as e:
             phx.phx_workspace_bytes(good_config(kernel=phx.PHX_KERNEL_STEP, components=2, **bad))
         assert e.value.status == phx.PHX_EINVAL, bad
     with pytest.raises(phx.PhxError) as e:
-        phx.phx_workspace_bytes(good_config(kernel=phx.PHX_KERNEL_STEP, components=2, reservoir=True))
+        phx.phx_workspace_bytes(good_config(kernel=phx.PHX_KERNEL_STEP, components=2, drive=True))
     assert e.value.status == phx.PHX_EUNSUPPORTED
 
 
