@@ -8,6 +8,7 @@ from __future__ import annotations
 
 import concurrent.futures as cf
 import os
+import re
 import shutil
 import subprocess
 import sys
@@ -18,7 +19,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 OUT = os.path.join(HERE, "libphx.so")
 BUILD_DIR = os.path.join(HERE, "_build")
-SOURCES = ["runtime.hip", "rk4.hip", "rk4_step.hip", "reduce.hip", "dopri5.hip", "batch.hip", "autotune.hip", "cnn.hip", "noise.hip", "drive.hip", "imag.hip", "rk4_stream_drive.hip", "rk4_stream_spinor.hip"]
+SOURCES = ["rk4_step.hip", "rk4_stream_spinor_res_f40.hip", "rk4_stream_spinor_res_f64.hip", "rk4_stream_spinor_res_d40.hip", "rk4_stream_spinor_res_d64.hip", "runtime.hip", "rk4.hip", "reduce.hip", "dopri5.hip", "batch.hip", "autotune.hip", "cnn.hip", "noise.hip", "drive.hip", "imag.hip", "rk4_stream_drive.hip", "rk4_stream_spinor.hip"]
 
 ARCH = "gfx950"
 FLAGS = [
@@ -26,6 +27,32 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function", "-I", INCLUDE, "-I", CSRC,
 ]
+
+# The streaming whole-step kernels keep their row rings in registers only when the
+# walk's 24-row loop is unrolled completely (every ring index is then a constant);
+# the two-component walk with reservoirs is larger than LLVM's default size limit
+# for a requested full unroll, so its unit raises that limit.
+_FULL_UNROLL = ["-mllvm", "-pragma-unroll-threshold=40000"]
+EXTRA_FLAGS = {f"rk4_stream_spinor{t}.hip": _FULL_UNROLL
+               for t in ("", "_res_f40", "_res_f64", "_res_d40", "_res_d64")}
+# Units whose streaming kernels are checked for private (scratch) memory: a ring
+# that is not in registers makes the walk several times slower.
+STREAM_SOURCES = {"rk4_step.hip", "rk4_stream_drive.hip"} | set(EXTRA_FLAGS)
+_USAGE = "-Rpass-analysis=kernel-resource-usage"
+
+
+def _scratch_kernels(stderr: str) -> list:
+    """(kernel, bytes per lane) of every streaming kernel with scratch memory, read
+    from the compiler's resource-usage remarks."""
+    out, name = [], None
+    for line in stderr.splitlines():
+        if "Function Name:" in line:
+            name = line.split("Function Name:")[1].split("[")[0].strip()
+        elif "ScratchSize [bytes/lane]:" in line and name and "stream" in name:
+            size = int(line.split("ScratchSize [bytes/lane]:")[1].split("[")[0])
+            if size:
+                out.append((name, size))
+    return out
 
 
 def hipcc() -> str:
@@ -37,13 +64,19 @@ def hipcc() -> str:
 
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD_DIR, os.path.splitext(src)[0] + ".o")
-    cmd = [hipcc(), *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    extra = EXTRA_FLAGS.get(src, []) + ([_USAGE] if src in STREAM_SOURCES else [])
+    cmd = [hipcc(), *FLAGS, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed on {src}:\n{r.stderr}")
+    spilled = _scratch_kernels(r.stderr)
+    if spilled:
+        raise RuntimeError(f"streaming kernels of {src} use scratch memory: {spilled}")
     if r.stderr.strip():
         # hipcc's host pass does not know the packed-fp32 feature; keep other warnings
-        lines = [l for l in r.stderr.splitlines() if "packed-fp32-ops" not in l and l.strip()]
+        lines = [l for l in r.stderr.splitlines()
+                 if "packed-fp32-ops" not in l and "kernel-resource-usage" not in l and l.strip()
+                 and not re.match(r"^\s*\d*\s*\|", l) and not l.startswith("In file included")]
         if lines:
             sys.stderr.write("\n".join(lines) + "\n")
     return obj

@@ -1,46 +1,26 @@
 // Streaming whole-step RK4 kernel for the two-component (spinor) form, with or
-// without the reservoirs (stream_spinor.h): bands of 40 and 64 rows, a translation
-// unit of its own.
-#include "runtime.h"
-#include "stream_spinor.h"
+// without the reservoirs (stream_spinor.h): bands of 40 and 64 rows.  This unit
+// holds the dispatch and the variants without reservoirs; each precision and band
+// height with reservoirs has a unit of its own (rk4_stream_spinor_res_*.hip).
+#include "stream_spinor_launch.h"
 
 namespace phx {
-
-template <typename R, bool RES, bool HASV, bool GHOSTS, bool YZERO, int B>
-__global__ __launch_bounds__(256) void rk4_stream_spinor_kernel(const StepArgs<R> a)
-{
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int t = xcd_tile(blockIdx.x, gridDim.x);
-    const int groups_x = (a.tiles_x + 3) / 4;
-    const int band = t / groups_x, strip = (t - band * groups_x) * 4 + wave;
-    if (strip >= a.tiles_x) return;
-    if (stream_band_spinor<R, RES, HASV, GHOSTS, YZERO, B>(a, strip, band, (band & 1) ? -1 : 1))
-        a.flag[0] = 1u;  // benign race
-}
-
-template <typename R, bool RES, bool HASV, int B>
-static hipError_t launch_spinor_t(const StepArgs<R>& a, hipStream_t s)
-{
-    const bool ghosts = a.bcx == PHX_BC_ZERO || a.bcy == PHX_BC_ZERO;
-    if (a.bcy == PHX_BC_ZERO)
-        rk4_stream_spinor_kernel<R, RES, HASV, true, true, B><<<a.tiles, 256, 0, s>>>(a);
-    else if (ghosts)
-        rk4_stream_spinor_kernel<R, RES, HASV, true, false, B><<<a.tiles, 256, 0, s>>>(a);
-    else
-        rk4_stream_spinor_kernel<R, RES, HASV, false, false, B><<<a.tiles, 256, 0, s>>>(a);
-    return hipGetLastError();
-}
 
 template <typename R>
 hipError_t launch_stream_spinor(bool reservoir, bool has_v, int rows, const StepArgs<R>& a, hipStream_t s)
 {
-#define PHX_S(RS, HV, B) \
-    if (reservoir == RS && has_v == HV && rows == B) return launch_spinor_t<R, RS, HV, B>(a, s)
-    PHX_S(false, false, 40); PHX_S(false, true, 40); PHX_S(true, false, 40); PHX_S(true, true, 40);
-    PHX_S(false, false, 64); PHX_S(false, true, 64); PHX_S(true, false, 64); PHX_S(true, true, 64);
+#define PHX_S(RS, B) \
+    if (reservoir == RS && rows == B) return launch_spinor_part<R, RS, B>(has_v, a, s)
+    PHX_S(false, 40); PHX_S(true, 40); PHX_S(false, 64); PHX_S(true, 64);
 #undef PHX_S
     return hipErrorInvalidValue;
 }
+
+// the reservoir variants are instantiated in their own units
+extern template hipError_t launch_spinor_part<float, true, 40>(bool, const StepArgs<float>&, hipStream_t);
+extern template hipError_t launch_spinor_part<float, true, 64>(bool, const StepArgs<float>&, hipStream_t);
+extern template hipError_t launch_spinor_part<double, true, 40>(bool, const StepArgs<double>&, hipStream_t);
+extern template hipError_t launch_spinor_part<double, true, 64>(bool, const StepArgs<double>&, hipStream_t);
 
 template hipError_t launch_stream_spinor<float>(bool, bool, int, const StepArgs<float>&, hipStream_t);
 template hipError_t launch_stream_spinor<double>(bool, bool, int, const StepArgs<double>&, hipStream_t);

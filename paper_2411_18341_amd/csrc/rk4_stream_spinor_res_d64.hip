@@ -1,0 +1,6 @@
+// Spinor streaming whole-step kernel with reservoirs, double, bands of 64 rows.
+#include "stream_spinor_launch.h"
+
+namespace phx {
+template hipError_t launch_spinor_part<double, true, 64>(bool, const StepArgs<double>&, hipStream_t);
+}  // namespace phx

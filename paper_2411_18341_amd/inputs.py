@@ -20,6 +20,9 @@ part of its text, so these stand in for them):
   spinor        4096^2, dx 0.1, zero boundaries, g 1, g_x -0.1, Delta_LT 0.1,
                 Gaussian-correlated disorder (length 1, rms 0.05), x-linear Gaussian
                 state of width 20, Dormand-Prince with tolerance 1e-6.
+  spinor_driven the spinor grid with a reservoir per component: the driven
+                workload's reservoir parameters and ring pump on both components,
+                noise psi0 of amplitude 1e-3, n0 = 0.
   batch         256 driven instances on square grids drawn log-uniformly in
                 [128, 1024], pump p_i P_th with p_i ~ U(0.5, 3), Gaussian spot of
                 width L_i/10, seeded noise psi0.
@@ -134,6 +137,23 @@ def spinor(n: int = 4096, seed: int = 3, dx: float = 0.1, width: float = 20.0):
     psi = np.stack([env, env]).astype(np.complex128)
     V = disorder(n, dx, seed)
     return ph, psi, V
+
+
+def spinor_driven(n: int = 4096, seed: int = 3, dx: float = 0.1):
+    """The spinor workload with a reservoir per component (Eq. PULSE_res for each
+    spin): the spinor's grid, boundaries, interactions, TE-TM coupling and disorder,
+    the driven workload's reservoir parameters and ring pump (2 P_th at radius 20,
+    width 3) on both components, seeded complex white noise psi0 of amplitude 1e-3,
+    n0 = 0.  Returns (physics, psi0 [2,n,n], n0 [2,n,n], V, P [2,n,n])."""
+    ph, _, V = spinor(n, seed=seed, dx=dx)
+    ph.reservoir = True
+    ph.g_r, ph.R, ph.gamma_c, ph.gamma_r = 0.02, 0.01, 0.15, 0.225
+    X, Y = coords(n, n, dx, dx)
+    r = np.sqrt(X * X + Y * Y)
+    pth = pump_threshold(ph.gamma_c, ph.gamma_r, ph.R)
+    ring = 2.0 * pth * np.exp(-((r - 20.0) ** 2) / (2.0 * 3.0 ** 2))
+    psi = random_state((2, n, n), seed + 1, 1e-3)
+    return ph, psi, np.zeros((2, n, n)), V, np.stack([ring, ring])
 
 
 def batch_sizes(count: int = 256, seed: int = 4, lo: int = 128, hi: int = 1024):

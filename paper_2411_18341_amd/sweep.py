@@ -121,26 +121,31 @@ def measure_batch(steps: int = 500, warmup: int = 20, count: int = 256, seed: in
             "one_solver_per_instance_steps": loop_steps}
 
 
-def measure_spinor(n: int = 4096, accepted: int = 20, rk4_steps: int = 50):
+def measure_spinor(n: int = 4096, accepted: int = 20, rk4_steps: int = 50, reservoir: bool = False):
     """The spinor workload (inputs.spinor: two components, TE-TM coupling, cross
-    interaction, disorder potential, zero boundaries, complex64) on an n x n grid:
-    RK4 with the tuned kernel family (the two-component streaming whole-step kernel),
-    and Dormand-Prince
-    with rtol = atol = 1e-6 from dt 1e-3 for `accepted` accepted steps.  Reports point
-    updates per second (accepted steps for RK45), attempts, and per-kernel launch
-    times with their algorithmic bandwidth."""
+    interaction, disorder potential, zero boundaries, complex64) on an n x n grid, or
+    with `reservoir` its driven form (inputs.spinor_driven: a reservoir and a ring
+    pump per component): RK4 with the tuned kernel family (the two-component
+    streaming whole-step kernel), and Dormand-Prince with rtol = atol = 1e-6 from
+    dt 1e-3 for `accepted` accepted steps.  Reports point updates per second
+    (accepted steps for RK45), attempts, and per-kernel launch times with their
+    algorithmic bandwidth."""
     import torch
-    ph, psi0, V = inputs.spinor(n)
+    if reservoir:
+        ph, psi0, n0, V, P = inputs.spinor_driven(n)
+    else:
+        ph, psi0, V = inputs.spinor(n)
+        n0 = P = None
     dev = torch.device("cuda:0")
-    out = {"n": n}
+    out = {"n": n, "reservoir": reservoir}
+    real = lambda a: None if a is None else torch.from_numpy(a).to(dtype=torch.float32, device=dev).contiguous()
     for integ in ("rk4", "rk45"):
         psi = torch.from_numpy(psi0).to(dtype=torch.complex64, device=dev).contiguous()
-        Vd = torch.from_numpy(V).to(dtype=torch.float32, device=dev).contiguous()
         kw = dict(precision=phx.PHX_C64)
         if integ == "rk45":
             kw.update(integrator=phx.PHX_RK45, rtol=1e-6, atol=1e-6, dt=1e-3)
         cfg = phx.config_from_physics(ph, **kw)
-        solver = phx.Solver(cfg, psi, None, Vd, None)
+        solver = phx.Solver(cfg, psi, real(n0), real(V), real(P))
         try:
             if integ == "rk4":
                 solver.autotune(reps=3, use_cache=False)
@@ -158,11 +163,11 @@ def measure_spinor(n: int = 4096, accepted: int = 20, rk4_steps: int = 50):
         finally:
             solver.close()
         if integ == "rk4":
-            model = bytemodel.rk4_stage_fused(4, reservoir=False, has_v=True, components=2)
+            model = bytemodel.rk4_stage_fused(4, reservoir=reservoir, has_v=True, components=2)
             names = {f"rk4_stage{k}": model[f"stage{k}"] for k in range(1, 5)}
-            names["rk4_step"] = bytemodel.rk4_whole_step(4, reservoir=False, has_v=True, components=2)["step"]
+            names["rk4_step"] = bytemodel.rk4_whole_step(4, reservoir=reservoir, has_v=True, components=2)["step"]
         else:
-            model = bytemodel.dopri5_attempt(4, reservoir=False, has_v=True, components=2)
+            model = bytemodel.dopri5_attempt(4, reservoir=reservoir, has_v=True, components=2)
             names = {f"dp_stage{k}": model[f"stage{k}"] for k in range(2, 8)}
             names["dp_stage1"] = model["restart"]  # after the first step every attempt restarts from K1
         ks = {}
@@ -315,6 +320,8 @@ def main():
     ap.add_argument("--out", default=None, help="write the markdown table here")
     ap.add_argument("--batch", action="store_true", help="also measure the 256-instance batched workload")
     ap.add_argument("--spinor", action="store_true", help="also measure the 4096^2 spinor workload (RK4, RK45)")
+    ap.add_argument("--spinor-reservoir", action="store_true",
+                    help="also measure the 4096^2 spinor workload with a reservoir per component")
     ap.add_argument("--noise", action="store_true", help="also measure the 4096^2 driven workload with Wiener noise")
     ap.add_argument("--drive", action="store_true", help="also measure the stage-fused kernels with a coherent drive")
     ap.add_argument("--ensemble", action="store_true", help="also measure a batched noisy ensemble (128 x 256^2)")
@@ -342,6 +349,12 @@ def main():
         print(json.dumps({"spinor": r}), flush=True)
         if args.out:
             with open(args.out + ".spinor.json", "w") as f:
+                json.dump(r, f, indent=1)
+    if args.spinor_reservoir:
+        r = measure_spinor(reservoir=True)
+        print(json.dumps({"spinor_reservoir": r}), flush=True)
+        if args.out:
+            with open(args.out + ".spinor_reservoir.json", "w") as f:
                 json.dump(r, f, indent=1)
     if args.batch:
         r = measure_batch()
