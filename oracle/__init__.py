@@ -19,7 +19,13 @@ Parity status of each function (what pins it, see ``tests/test_oracle_pins.py``)
                       scalar problem; the accepted-step sequence of long runs is
                       otherwise parity unpinned (controller constants are a choice).
   observables      -- pinned: Parseval norm, summation-by-parts kinetic identity,
-                      closed-form energy of plane waves, uniform-state values.
+                      closed-form energy of plane waves, uniform-state values; the cross,
+                      TE-TM and reservoir energies and the reservoir total by Hamilton's
+                      equation (the energy's directional derivative equals the one the
+                      right-hand side implies), the dense quadratic form, fourth-order
+                      energy conservation of spinor and frozen-reservoir runs, and the
+                      conserved norm + reservoir total of particle exchange
+                      (tests/test_oracle_observable_pins.py).
 """
 from __future__ import annotations
 

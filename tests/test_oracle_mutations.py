@@ -83,6 +83,19 @@ IMAG_MUTATIONS = {
 }
 
 
+# Mistakes in the observables that only the dynamics fix, checked by their pins.
+OBS_MUTATIONS = {
+    "tetm_energy_factor_two": ("s_tetm += 2.0 * creal(conj(pp[k]) * jp);", "s_tetm += creal(conj(pp[k]) * jp);"),
+    "tetm_energy_mixed_sign": ("- 2.0 * I * d_xy(p, pm, i, j));", "+ 2.0 * I * d_xy(p, pm, i, j));"),
+    "tetm_energy_dyy_sign": ("(d_xx(p, pm, i, j) - d_yy(p, pm, i, j)", "(d_xx(p, pm, i, j) + d_yy(p, pm, i, j)"),
+    "cross_energy_zero": ("o->e_cross = p->g_x * dA * s_cross;", "o->e_cross = 0.0 * dA * s_cross;"),
+    "cross_energy_half": ("o->e_cross = p->g_x * dA * s_cross;", "o->e_cross = 0.5 * p->g_x * dA * s_cross;"),
+    "reservoir_energy_half": ("o->e_res = p->g_r * dA * s_res;", "o->e_res = 0.5 * p->g_r * dA * s_res;"),
+    "reservoir_total_area": ("o->reservoir = dA * s_nr;", "o->reservoir = s_nr;"),
+    "energy_sum_drops_tetm": ("o->e_cross + o->e_tetm + o->e_res;", "o->e_cross + o->e_res;"),
+}
+
+
 def _run_pins_on_mutant(old, new, pins, tmp_path):
     src = open(SRC).read()
     assert src.count(old) >= 1, f"mutation anchor {old!r} no longer in the oracle source"
@@ -121,3 +134,10 @@ def test_pins_reject_planted_mistake(name, tmp_path):
     old, new = MUTATIONS[name]
     r = _run_pins_on_mutant(old, new, "test_oracle_pins.py", tmp_path)
     assert r.returncode != 0, f"pins passed with planted mistake {name}:\n{r.stdout[-2000:]}"
+
+
+@pytest.mark.parametrize("name", sorted(OBS_MUTATIONS))
+def test_observable_pins_reject_planted_mistake(name, tmp_path):
+    old, new = OBS_MUTATIONS[name]
+    r = _run_pins_on_mutant(old, new, "test_oracle_observable_pins.py", tmp_path)
+    assert r.returncode != 0, f"observable pins passed with planted mistake {name}:\n{r.stdout[-2000:]}"
