@@ -205,6 +205,15 @@ phx_status phx_observables(phx_handle *h, phx_obs *out);
 phx_status phx_get_info(const phx_handle *h, phx_info *out);
 phx_status phx_set_info(phx_handle *h, const phx_info *in);
 
+/* RK45 only: log every later Dormand-Prince attempt (Sec. 2) into the caller's host
+ * array log[3k], log[3k+1], log[3k+2] = (dt of the attempt, its error norm, 1.0 if it
+ * was accepted else 0.0) for k = *count .. cap-1; *count (caller-owned, host) counts
+ * the attempts logged so far and is advanced by phx_step; attempts beyond cap are
+ * not logged.  log = NULL stops logging.  The arrays stay owned by the caller and
+ * must stay valid while logging is on.  Host-only.  Errors: PHX_EINVAL (NULL
+ * handle, cap < 0, NULL count with a log), PHX_EUNSUPPORTED (RK4 handle). */
+phx_status phx_log_attempts(phx_handle *h, double *log, int64_t cap, int64_t *count);
+
 /* Release host resources of a handle (NULL is a no-op).  Does not synchronize;
  * the caller keeps its arrays alive until enqueued work has finished. */
 void phx_destroy(phx_handle *h);

@@ -432,6 +432,13 @@ phx_status step_rk45(phx_handle* h, int64_t n, phx_info* out)
                                     : dp_attempt<double>(h, dt, !h->k1_valid, &err);
         if (st != PHX_OK) break;
         h->k1_valid = true;  // K_1 of the current state now sits in slot fsal
+        if (h->att_log && *h->att_count >= 0 && *h->att_count < h->att_cap) {
+            double* e = h->att_log + 3 * *h->att_count;
+            e[0] = dt;
+            e[1] = err;
+            e[2] = err <= 1.0 ? 1.0 : 0.0;
+            *h->att_count += 1;
+        }
         const double fmax_ = h->info.last_rejected ? 1.0 : 5.0;
         double fac;
         if (!isfinite(err)) fac = 0.2;

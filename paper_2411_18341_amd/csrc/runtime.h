@@ -84,6 +84,10 @@ struct phx_handle {
     int64_t drive_k0;
     int fsal;               // index of the buffer that holds K1 of the current state
     bool k1_valid;
+    // attempt log of the caller (phx_log_attempts): (dt, err, accepted) per attempt
+    double* att_log;
+    int64_t att_cap;
+    int64_t* att_count;
     // hipGraph of graph_steps RK4 steps, captured on cap_stream, replayed on stream
     hipStream_t cap_stream;
     hipGraphExec_t graph;
@@ -111,6 +115,12 @@ const char* kernel_kind_name(int k);
 hipError_t timing_begin(phx_handle* h, hipEvent_t* start);
 hipError_t timing_end(phx_handle* h, hipEvent_t start, int kind);
 const void* state_psi(const phx_handle* h);
+// Observables: kernel arguments from a configuration, its tile plan and the fields
+// (drive phase at time t), and phx_obs from the reduced slots.
+template <typename R>
+ObsArgs<R> obs_args(const phx_config& c, const TilePlan& tiles, const void* psi, const void* n, const void* V,
+                    const void* P, const void* E, double t, double* partials, double* out);
+void obs_from_slots(const phx_config& c, const double* q, phx_obs* out);
 const void* state_n(const phx_handle* h);
 phx_status create_rk45(phx_handle* h);
 template <typename R> phx_status rk4_fused_steps(phx_handle* h, int64_t n);

@@ -579,10 +579,12 @@ phx_status phx_step(phx_handle* h, int64_t n_steps, phx_info* out)
     return PHX_OK;
 }
 
+namespace phx {
+
 template <typename R>
-static phx_status observables_t(phx_handle* h)
+ObsArgs<R> obs_args(const phx_config& c, const TilePlan& tiles, const void* psi, const void* n, const void* V,
+                    const void* P, const void* E, double t, double* partials, double* out)
 {
-    const phx_config& c = h->cfg;
     ObsArgs<R> a{};
     a.nx = c.nx;
     a.ny = c.ny;
@@ -590,9 +592,9 @@ static phx_status observables_t(phx_handle* h)
     a.bcy = c.bc_y;
     a.comps = c.components;
     a.reservoir = c.reservoir;
-    a.tiles_x = h->L.tiles.tiles_x;
-    a.tiles = h->L.tiles.tiles;
-    a.ts = h->L.tiles.ts;
+    a.tiles_x = tiles.tiles_x;
+    a.tiles = tiles.tiles;
+    a.ts = tiles.ts;
     a.cstride = (int64_t)c.nx * c.ny;
     a.c = make_coef<R>(c);
     a.inv_dx2 = 1.0 / (c.dx * c.dx);
@@ -601,36 +603,27 @@ static phx_status observables_t(phx_handle* h)
     a.inv_4dxdy = 1.0 / (4.0 * c.dx * c.dy);
     a.gamma_r_d = c.gamma_r;
     a.R_d = c.R;
-    a.psi = (const typename cvec<R>::type*)state_psi(h);
-    a.n = (const R*)state_n(h);
-    a.V = (const R*)h->f.V;
-    a.P = (const R*)h->f.P;
-    a.partials = (double*)(h->ws + h->L.partials);
-    a.out = (double*)(h->ws + h->L.obs);
-    if (c.drive) {  // the residual's right-hand side at the handle's time
-        a.E = (const typename cvec<R>::type*)h->f.E;
-        const double th = c.drive_omega * h->info.t;
+    a.psi = (const typename cvec<R>::type*)psi;
+    a.n = (const R*)n;
+    a.V = (const R*)V;
+    a.P = (const R*)P;
+    a.partials = partials;
+    a.out = out;
+    if (c.drive) {  // the residual's right-hand side at time t
+        a.E = (const typename cvec<R>::type*)E;
+        const double th = c.drive_omega * t;
         a.drive_ph = typename cvec<R>::type{(R)cos(th), (R)-sin(th)};
     }
-    hipEvent_t t0 = nullptr;
-    hipError_t e = timing_begin(h, &t0);
-    if (e == hipSuccess) e = launch_observables<R>(a, h->L.obs_blocks, h->stream);
-    if (e == hipSuccess) e = timing_end(h, t0, K_OBS);
-    if (e != hipSuccess) return fail(PHX_EHIP, "observables launch: %s", hipGetErrorString(e));
-    return PHX_OK;
+    return a;
 }
 
-phx_status phx_observables(phx_handle* h, phx_obs* out)
+template ObsArgs<float> obs_args<float>(const phx_config&, const TilePlan&, const void*, const void*, const void*,
+                                        const void*, const void*, double, double*, double*);
+template ObsArgs<double> obs_args<double>(const phx_config&, const TilePlan&, const void*, const void*, const void*,
+                                          const void*, const void*, double, double*, double*);
+
+void obs_from_slots(const phx_config& c, const double* q, phx_obs* out)
 {
-    clear_error();
-    if (!h || !out) return fail(PHX_EINVAL, "handle or out is NULL");
-    phx_status s = h->cfg.precision == PHX_C64 ? observables_t<float>(h) : observables_t<double>(h);
-    if (s != PHX_OK) return s;
-    HIP_OR_FAIL(hipMemcpyAsync(h->host, h->ws + h->L.obs, OBS_SLOTS * sizeof(double),
-                               hipMemcpyDeviceToHost, h->stream));
-    HIP_OR_FAIL(hipStreamSynchronize(h->stream));
-    const double* q = h->host;
-    const phx_config& c = h->cfg;
     const double A = c.dx * c.dy;
     memset(out, 0, sizeof(*out));
     out->norm[0] = A * q[O_NORM0];
@@ -649,6 +642,33 @@ phx_status phx_observables(phx_handle* h, phx_obs* out)
     out->nonfinite = (int64_t)q[O_NONFINITE];
     const double vacuum = 0.5 * c.noise * (double)c.nx * (double)c.ny;  // nu/(2A) per cell, times A
     for (int s = 0; s < c.components; ++s) out->norm_renorm[s] = out->norm[s] - vacuum;
+}
+
+}  // namespace phx
+
+template <typename R>
+static phx_status observables_t(phx_handle* h)
+{
+    const ObsArgs<R> a = obs_args<R>(h->cfg, h->L.tiles, state_psi(h), state_n(h), h->f.V, h->f.P, h->f.E,
+                                     h->info.t, (double*)(h->ws + h->L.partials), (double*)(h->ws + h->L.obs));
+    hipEvent_t t0 = nullptr;
+    hipError_t e = timing_begin(h, &t0);
+    if (e == hipSuccess) e = launch_observables<R>(a, h->L.obs_blocks, h->stream);
+    if (e == hipSuccess) e = timing_end(h, t0, K_OBS);
+    if (e != hipSuccess) return fail(PHX_EHIP, "observables launch: %s", hipGetErrorString(e));
+    return PHX_OK;
+}
+
+phx_status phx_observables(phx_handle* h, phx_obs* out)
+{
+    clear_error();
+    if (!h || !out) return fail(PHX_EINVAL, "handle or out is NULL");
+    phx_status s = h->cfg.precision == PHX_C64 ? observables_t<float>(h) : observables_t<double>(h);
+    if (s != PHX_OK) return s;
+    HIP_OR_FAIL(hipMemcpyAsync(h->host, h->ws + h->L.obs, OBS_SLOTS * sizeof(double),
+                               hipMemcpyDeviceToHost, h->stream));
+    HIP_OR_FAIL(hipStreamSynchronize(h->stream));
+    obs_from_slots(h->cfg, h->host, out);
     poll_flag(h);
     return PHX_OK;
 }
@@ -734,6 +754,18 @@ hipError_t timing_end(phx_handle* h, hipEvent_t start, int kind)
 }
 
 }  // namespace phx
+
+phx_status phx_log_attempts(phx_handle* h, double* log, int64_t cap, int64_t* count)
+{
+    clear_error();
+    if (!h) return fail(PHX_EINVAL, "handle is NULL");
+    if (h->cfg.integrator != PHX_RK45) return fail(PHX_EUNSUPPORTED, "the attempt log is for RK45 handles");
+    if (log && (cap < 0 || !count)) return fail(PHX_EINVAL, "attempt log needs cap >= 0 and a count");
+    h->att_log = log;
+    h->att_cap = log ? cap : 0;
+    h->att_count = log ? count : nullptr;
+    return PHX_OK;
+}
 
 phx_status phx_set_timing(phx_handle* h, int32_t enable)
 {

@@ -126,7 +126,8 @@ class phx_cnn_buffers(ctypes.Structure):
 
 # names of every exported entry point (kept in step with include/phx.h)
 ENTRY_POINTS = ("phx_workspace_bytes", "phx_create", "phx_step", "phx_observables", "phx_get_info",
-                "phx_set_info", "phx_destroy", "phx_last_error", "phx_set_timing", "phx_kernel_times",
+                "phx_set_info", "phx_destroy", "phx_last_error", "phx_log_attempts", "phx_set_timing",
+                "phx_kernel_times",
                 "phx_autotune", "phx_batch_workspace_bytes", "phx_batch_step", "phx_cnn_sizes",
                 "phx_cnn_param_offsets", "phx_cnn_create", "phx_cnn_destroy", "phx_cnn_forward",
                 "phx_cnn_gradients", "phx_cnn_adam", "phx_cnn_train_step", "phx_coarsen",
@@ -164,6 +165,8 @@ def load(path: str | None = None):
     lib.phx_destroy.restype = None
     lib.phx_last_error.argtypes = []
     lib.phx_last_error.restype = ctypes.c_char_p
+    lib.phx_log_attempts.argtypes = [vp, vp, ctypes.c_int64, vp]
+    lib.phx_log_attempts.restype = st
     lib.phx_set_timing.argtypes = [vp, ctypes.c_int32]
     lib.phx_set_timing.restype = st
     lib.phx_kernel_times.argtypes = [vp, P(phx_timing)]
@@ -250,6 +253,14 @@ def phx_destroy(h) -> None:
 
 def phx_last_error() -> str:
     return (load().phx_last_error() or b"").decode()
+
+
+def phx_log_attempts(h, log, cap: int, count) -> None:
+    """log: host float64 array of >= 3*cap entries (or None to stop); count: host int64
+    array of one entry (both numpy, kept alive by the caller while logging)."""
+    lp = None if log is None else log.ctypes.data_as(ctypes.c_void_p)
+    cp = None if count is None else count.ctypes.data_as(ctypes.c_void_p)
+    _check(load().phx_log_attempts(h, lp, int(cap), cp))
 
 
 def phx_set_timing(h, enable: bool) -> None:
@@ -391,6 +402,18 @@ class Solver:
         for k, v in kw.items():
             setattr(cur, k, v)
         phx_set_info(self.handle, cur)
+
+    def log_attempts(self, cap: int) -> None:
+        """Start logging RK45 attempts (dt, error norm, accepted) into a host array of
+        `cap` entries; `attempts()` returns the entries logged so far."""
+        import numpy as np
+        self._att_log = np.zeros(3 * max(int(cap), 1), np.float64)
+        self._att_count = np.zeros(1, np.int64)
+        phx_log_attempts(self.handle, self._att_log, int(cap), self._att_count)
+
+    def attempts(self):
+        """[k, 3] array of (dt, err, accepted) of the attempts logged so far."""
+        return self._att_log[:3 * int(self._att_count[0])].reshape(-1, 3).copy()
 
     def set_timing(self, enable: bool = True) -> None:
         phx_set_timing(self.handle, enable)

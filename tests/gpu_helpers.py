@@ -76,3 +76,20 @@ class GpuRun:
 
 def oracle_rk4(ph, psi, n, V, P, steps):
     return oracle.rk4(oracle_physics(ph), psi, n, V, P, dt=ph.dt, steps=steps)
+
+
+def replay_attempts(op, psi, n, V, P, attempts, rtol, atol):
+    """Runs the GPU's own Dormand-Prince attempts (dt, err, accepted) through the
+    oracle's step: an accepted attempt advances the oracle's state and time, a
+    rejected one leaves them.  Returns (psi, n, t, errors of the oracle's attempts).
+    op.t0 is the time of the first attempt (the drive's clock)."""
+    import dataclasses
+    t = op.t0
+    errs = []
+    for dt, _, acc in attempts:
+        ot = dataclasses.replace(op, t0=t)
+        y5, n5, e, en = oracle.dopri5_step(ot, psi, n, V, P, dt=dt)
+        errs.append(oracle.error_norm(ot, psi, n, y5, n5, e, en, rtol, atol))
+        if acc:
+            psi, n, t = y5, n5, t + dt
+    return psi, n, t, np.array(errs)

@@ -16,7 +16,7 @@ import numpy as np
 import pytest
 
 import oracle
-from gpu_helpers import C64, C128, TOL, GpuRun, oracle_physics, quantize, rel_l2
+from gpu_helpers import C64, C128, TOL, GpuRun, oracle_physics, quantize, rel_l2, replay_attempts
 from paper_2411_18341_amd import inputs, phx
 from test_gpu_rk4 import workload
 
@@ -114,26 +114,26 @@ def test_drive_rk45_parity(precision):
     E = quantize_e(precision, drive_profile(ph, 11, amp=2.0))
     run = GpuRun(ph, *q, precision=precision, E=E, drive_omega=OMEGA, integrator=phx.PHX_RK45, rtol=1e-6,
                  atol=1e-6, dt=1e-3, dt_min=1e-12)
+    run.solver.log_attempts(1000)
     run.step(12)
     info = run.solver.info()
+    att = run.solver.attempts()
     g_psi, g_n = run.state()
     run.close()
-    o_psi, o_n, ctrl = oracle.dopri5(oracle_drive(ph, E), *q, rtol=1e-6, atol=1e-6, dt_min=1e-12,
-                                     accepted=12, ctrl=oracle.Controller(dt=1e-3))
-    assert info["steps_accepted"] == ctrl.accepted == 12
-    assert info["steps_rejected"] == ctrl.rejected
     tol = TOL[precision]
-    assert abs(info["t"] - ctrl.t) <= tol * ctrl.t
-    if precision == C128:
+    if precision == C128:  # the oracle's own controller takes the same decisions
+        o_psi, o_n, ctrl = oracle.dopri5(oracle_drive(ph, E), *q, rtol=1e-6, atol=1e-6, dt_min=1e-12,
+                                         accepted=12, ctrl=oracle.Controller(dt=1e-3))
+        assert info["steps_accepted"] == ctrl.accepted == 12
+        assert info["steps_rejected"] == ctrl.rejected
+        assert abs(info["t"] - ctrl.t) <= tol * ctrl.t
         assert rel_l2(g_psi, o_psi) <= tol and rel_l2(g_n, o_n) <= tol
-    else:
-        # the time grids differ by the error estimate's rounding: compare at the GPU's
-        # time, moving the oracle's state there along its derivative (first order)
-        op = oracle_drive(ph, E, t0=ctrl.t)
-        f_psi, f_n = oracle.rhs(op, o_psi, o_n, q[2], q[3])
-        shift = info["t"] - ctrl.t
-        assert rel_l2(g_psi, o_psi + shift * f_psi) <= tol
-        assert rel_l2(g_n, o_n + shift * f_n) <= tol
+    # both precisions: the oracle replays the GPU's attempts (the drive at each
+    # attempt's own time), states compared at the same time
+    r_psi, r_n, r_t, errs = replay_attempts(oracle_drive(ph, E), *q, att, 1e-6, 1e-6)
+    assert r_t == info["t"] and int(att[:, 2].sum()) == 12
+    assert np.allclose(att[:, 1], errs, rtol=1e-9 if precision == C128 else 0.1)
+    assert rel_l2(g_psi, r_psi) <= tol and rel_l2(g_n, r_n) <= tol
 
 
 @pytest.mark.parametrize("precision", [C64, C128])

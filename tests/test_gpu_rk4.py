@@ -156,6 +156,36 @@ def test_driven_1024(precision, family):
     assert e_psi <= TOL[precision] and e_n <= TOL[precision]
 
 
+_DRIVEN_1000 = {}
+
+
+def _driven_1024_oracle():
+    """The oracle's state after 1000 steps of the driven workload at 1024^2, from the
+    inputs rounded to single precision (exact in double as well, so both precisions
+    start from the same values and share this one oracle run)."""
+    if not _DRIVEN_1000:
+        ph, psi, n0, P = inputs.driven(1024)
+        q = quantize(C64, psi, n0, None, P)
+        _DRIVEN_1000["q"] = q
+        _DRIVEN_1000["o"] = oracle_rk4(ph, *q, 1000)
+    return _DRIVEN_1000["q"], _DRIVEN_1000["o"]
+
+
+@pytest.mark.parametrize("precision", PREC)
+def test_driven_1024_1000_steps(precision):
+    """The driven-dissipative workload at 1024^2 (complex64 + float32 n, then FP64) for
+    the 1000 RK4 steps of its gate (t = 20), every cell against the oracle."""
+    ph = inputs.driven(1024)[0]
+    q, (o_psi, o_n) = _driven_1024_oracle()
+    run = GpuRun(ph, *q, precision=precision)
+    run.step(1000)
+    g_psi, g_n = run.state()
+    run.close()
+    e_psi, e_n = rel_l2(g_psi, o_psi), rel_l2(g_n, o_n)
+    print(f"driven 1024^2 1000 steps prec={precision}: psi {e_psi:.3e} n {e_n:.3e}")
+    assert e_psi <= TOL[precision] and e_n <= TOL[precision]
+
+
 def _patch(a, j, i, r):
     """(2r+1)^2 patch of the last two axes around (j, i), periodic wrap."""
     ny, nx = a.shape[-2:]

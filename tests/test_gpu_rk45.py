@@ -1,8 +1,13 @@
 """GPU parity of the adaptive Dormand-Prince path against the CPU oracle.
 
 The oracle runs the same tableau and the same step-size controller, so on the same
-inputs both must take the same accepted/rejected sequence and reach the same time
-and state (relative L2 1e-12 complex128, 1e-5 complex64).  At the full 4096^2
+inputs in complex128 both take the same accepted/rejected sequence and reach the
+same time and state (relative L2 1e-12).  Every test also replays the GPU's own
+attempts (their step sizes and accept decisions, logged through phx_log_attempts)
+through the oracle's Dormand-Prince step, so the states are compared at exactly the
+same time in both precisions (1e-12 complex128, 1e-5 complex64): in complex64 the
+controller's error estimate is formed from single-precision stage values, so its own
+time grid drifts from the oracle's by that estimate's rounding.  At the full 4096^2
 spinor size one accepted step is checked on sampled cells: the fifth-order
 solution at a cell depends on the cells within 6 of it (six stencil stages), so
 the oracle advances a 13^2 patch with the step size the GPU used.
@@ -11,7 +16,7 @@ import numpy as np
 import pytest
 
 import oracle
-from gpu_helpers import C64, C128, TOL, GpuRun, oracle_physics, quantize, rel_l2
+from gpu_helpers import C64, C128, TOL, GpuRun, oracle_physics, quantize, rel_l2, replay_attempts
 from paper_2411_18341_amd import inputs, phx
 
 pytestmark = pytest.mark.gpu
@@ -43,56 +48,90 @@ def driven_case(nx, ny, seed=0):
     return ph, inputs.random_state((1, ny, nx), seed, 0.5), rng.uniform(0, 5, (1, ny, nx)), None, P[None]
 
 
-def run_both(ph, psi, n, V, P, precision, accepted, rtol, atol, dt0):
+def run_both(ph, psi, n, V, P, precision, accepted, rtol, atol, dt0, replay=False):
     q = quantize(precision, psi, n, V, P)
     run = GpuRun(ph, *q, precision=precision, integrator=phx.PHX_RK45, rtol=rtol, atol=atol,
                  dt=dt0, dt_min=1e-12)
+    run.solver.log_attempts(100 * accepted + 100)
     run.step(accepted)
     info = run.solver.info()
+    att = run.solver.attempts()
     g_psi, g_n = run.state()
     run.close()
+    assert len(att) == info["steps_accepted"] + info["steps_rejected"]
+    assert int(att[:, 2].sum()) == info["steps_accepted"]
+    if replay:
+        r_psi, r_n, r_t, errs = replay_attempts(oracle_physics(ph), *q, att, rtol, atol)
+        assert r_t == info["t"]  # the same step sizes summed in the same order
+        return info, g_psi, g_n, att, r_psi, r_n, errs
     o_psi, o_n, ctrl = oracle.dopri5(oracle_physics(ph), *q, rtol=rtol, atol=atol, dt_min=1e-12,
                                      accepted=accepted, ctrl=oracle.Controller(dt=dt0))
     return info, g_psi, g_n, ctrl, o_psi, o_n
 
 
-@pytest.mark.parametrize("precision", [C64, C128])
-@pytest.mark.parametrize("case", ["spinor_zero", "spinor_periodic_res", "driven"])
-def test_dopri5_small_parity(case, precision):
+def check_replay(precision, info, g_psi, g_n, att, r_psi, r_n, errs, label=""):
+    """The GPU state against the oracle's replay of the GPU's attempts; the oracle's
+    error norms against the logged ones (decisions equal wherever the oracle's norm
+    is not within the estimate's rounding of the threshold 1)."""
+    tol = TOL[precision]
+    e_psi = rel_l2(g_psi, r_psi)
+    e_n = rel_l2(g_n, r_n) if r_n is not None else 0.0
+    band = 1e-9 if precision == C128 else 0.1
+    clear = np.abs(errs - 1.0) > band
+    print(f"{label} replay of {len(att)} attempts ({info['steps_rejected']} rejected) to t={info['t']:.6g}: "
+          f"rel L2 psi {e_psi:.3e} n {e_n:.3e}; max rel err-norm difference "
+          f"{np.max(np.abs(att[:, 1] - errs) / errs):.2e}")
+    assert np.array_equal((errs[clear] <= 1.0), att[clear, 2] == 1.0)
+    assert np.allclose(att[:, 1], errs, rtol=1e-9 if precision == C128 else 0.1)
+    assert e_psi <= tol and e_n <= tol
+
+
+def small_case(case):
     if case == "spinor_zero":
-        args = spinor_case(150, 97, (1, 1))
-        dt0 = 1e-3
-    elif case == "spinor_periodic_res":
-        args = spinor_case(131, 70, (0, 0), seed=1, reservoir=True)
-        dt0 = 1e-3
-    else:
-        args = driven_case(140, 90)
-        dt0 = 0.05
-    ph = args[0]
-    info, g_psi, g_n, ctrl, o_psi, o_n = run_both(*args, precision, 25, 1e-6, 1e-6, dt0)
-    print(case, precision, info, (ctrl.t, ctrl.accepted, ctrl.rejected))
+        return spinor_case(150, 97, (1, 1)), 1e-3
+    if case == "spinor_periodic_res":
+        return spinor_case(131, 70, (0, 0), seed=1, reservoir=True), 1e-3
+    return driven_case(140, 90), 0.05
+
+
+@pytest.mark.parametrize("case", ["spinor_zero", "spinor_periodic_res", "driven"])
+def test_dopri5_small_parity_same_controller(case):
+    """complex128: the GPU's controller and the oracle's take the same decisions from
+    their own error norms and reach the same time and state."""
+    args, dt0 = small_case(case)
+    info, g_psi, g_n, ctrl, o_psi, o_n = run_both(*args, C128, 25, 1e-6, 1e-6, dt0)
+    print(case, info, (ctrl.t, ctrl.accepted, ctrl.rejected))
     assert info["steps_accepted"] == ctrl.accepted == 25
     assert info["steps_rejected"] == ctrl.rejected
-    tol = TOL[precision]
+    tol = TOL[C128]
     assert abs(info["t"] - ctrl.t) <= tol * ctrl.t
     assert abs(info["dt"] - ctrl.dt) <= 10 * tol * ctrl.dt
-    # The controller sizes each step from an error estimate formed from kernel-precision
-    # stage values, so the two time grids differ by that estimate's rounding (1e-6 of t
-    # in complex64, checked above).  Compare the states at the same time: move the
-    # oracle's state to the GPU's final time along its derivative (first order; the
-    # second-order term is below 1e-9 here).
-    shift = info["t"] - ctrl.t
-    _, _, qV, qP = quantize(precision, *args[1:5])
-    f_psi, f_n = oracle.rhs(oracle_physics(ph), o_psi, o_n, qV, qP)
-    o_psi_t = o_psi + shift * f_psi
-    e_psi = rel_l2(g_psi, o_psi_t)
-    print(f"rel L2 psi {rel_l2(g_psi, o_psi):.3e} at the oracle's t, {e_psi:.3e} at the GPU's t "
-          f"(t shift {shift:.3e})")
-    assert e_psi <= tol
-    if ph.reservoir:
-        e_n = rel_l2(g_n, o_n + shift * f_n)
-        print(f"rel L2 n {rel_l2(g_n, o_n):.3e} at the oracle's t, {e_n:.3e} at the GPU's t")
-        assert e_n <= tol
+    assert rel_l2(g_psi, o_psi) <= tol
+    if args[0].reservoir:
+        assert rel_l2(g_n, o_n) <= tol
+
+
+@pytest.mark.parametrize("precision", [C64, C128])
+@pytest.mark.parametrize("case", ["spinor_zero", "spinor_periodic_res", "driven"])
+def test_dopri5_small_parity_replayed(case, precision):
+    """Both precisions: the oracle replays the GPU's attempts; states compared at the
+    same time."""
+    args, dt0 = small_case(case)
+    out = run_both(*args, precision, 25, 1e-6, 1e-6, dt0, replay=True)
+    assert out[0]["steps_accepted"] == 25
+    check_replay(precision, *out, label=f"{case} p{precision}")
+
+
+@pytest.mark.parametrize("precision", [C64, C128])
+def test_dopri5_long_spinor_run(precision):
+    """The spinor workload's physics (zero boundaries, g, g_x = -0.1 g, Delta_LT = 0.1,
+    disorder V of rms 0.05, tol 1e-6) at 256^2 for 2000 accepted steps: the oracle
+    replays all of the GPU's attempts."""
+    ph, psi, V = inputs.spinor(256)
+    psi = psi + inputs.random_state(psi.shape, 19, 0.01)
+    out = run_both(ph, psi, None, V, None, precision, 2000, 1e-6, 1e-6, 1e-3, replay=True)
+    assert out[0]["steps_accepted"] == 2000
+    check_replay(precision, *out, label=f"spinor 256^2 p{precision}")
 
 
 def test_dopri5_rejections_match():
