@@ -8,13 +8,19 @@ pump 2 P_th, seeded noise start.  Inputs are generated on the host and resident 
 HBM before the timed region starts.
 
 Metric: grid-point RK4 updates per second, U = Nx Ny steps / seconds (Sec. 4 of
-the paper).  Printed as one JSON line together with
+the paper).  The timed steps are replays of one captured hipGraph (the solver's
+default way of stepping; the graph is captured after the warmup, outside the timed
+region).  Printed as one JSON line together with
   roofline      the dominant kernel's algorithmic bytes per launch over its mean
-                launch time (HIP events on the solver's stream) against 8 TB/s;
-                traffic = HBM bytes per launch from rocprofv3 counters when a
-                measurement for the current kernel source is on file;
+                launch time, from a separate pass of direct launches bracketed by
+                HIP events on the solver's stream, against 8 TB/s; traffic = HBM
+                bytes per launch from rocprofv3 counters when a measurement for the
+                current kernel source is on file;
+  copy_kernel_GBps  the library's streaming copy kernel on a 1 GiB buffer (read +
+                write bytes over HIP-event time): the attainable-bandwidth reference;
   cpu_baseline  the CPU oracle (complex128, OpenMP) timed on a bounded sample of
-                the same workload.
+                the same workload on all its threads and on one thread, with the
+                host's CPU model.
 """
 from __future__ import annotations
 
@@ -48,39 +54,74 @@ def measured_traffic(kernel: str, workload: str):
 
 
 def copy_bandwidth_gbps(torch, nbytes=COPY_BYTES, reps=20):
-    """Read+write bandwidth of a plain device-to-device copy (calibration)."""
+    """Read+write bandwidth of the library's streaming copy kernel (phx_stream_copy)
+    over a 1 GiB buffer, timed with HIP events on the stream it runs on."""
+    from paper_2411_18341_amd import phx
     src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
     src.fill_(1.0)
     for _ in range(3):
-        dst.copy_(src)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
+        phx.stream_copy(dst, src)
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
     for _ in range(reps):
-        dst.copy_(src)
+        phx.stream_copy(dst, src)
+    stop.record()
     torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
+    ms = start.elapsed_time(stop)
+    ok = bool(torch.equal(dst[:1 << 20], src[:1 << 20]))
     del src, dst
-    return 2.0 * nbytes * reps / dt / 1e9
+    if not ok:
+        raise RuntimeError("streaming copy kernel produced wrong data")
+    return 2.0 * nbytes * reps / (ms * 1e-3) / 1e9
 
 
-def cpu_baseline(ph, psi, n0, P, steps: int, noise: float = 0.0, imag: bool = False, V=None) -> dict:
+def cpu_model() -> str:
+    """Host CPU model name (the 'model name' field lscpu reports)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(ph, psi, n0, P, steps: int, noise: float = 0.0, imag: bool = False, V=None,
+                 steps_1t: int = 0) -> dict:
+    """The oracle timed on this host: `steps` steps with all its OpenMP threads, then
+    `steps_1t` steps on one thread (same workload and grid)."""
     import oracle
     op = oracle.Physics(**{k: getattr(ph, k) for k in (
         "nx", "ny", "dx", "dy", "bc_x", "bc_y", "components", "reservoir", "hbar", "mass", "g",
         "g_x", "g_r", "R", "gamma_c", "gamma_r", "delta_lt")})
-    t0 = time.perf_counter()
-    if imag:
-        oracle.rk4_imag(op, psi, V=V, dt=ph.dt, steps=steps)
-    elif noise > 0:
-        oracle.rk4_noise(op, psi, n0, None, P, dt=ph.dt, steps=steps, nu=noise, seed=1)
-    else:
-        oracle.rk4(op, psi, n0, None, P, dt=ph.dt, steps=steps)
-    dt = time.perf_counter() - t0
-    return {"value": ph.nx * ph.ny * steps / dt, "unit": "UP/s", "cores": oracle.num_threads(),
-            "kind": "oracle",
-            "sample": f"full {ph.nx}x{ph.ny} grid of the same workload, {steps} RK4 steps, "
-                      f"complex128 plain C oracle, {dt:.1f} s"}
+
+    def run(k):
+        t0 = time.perf_counter()
+        if imag:
+            oracle.rk4_imag(op, psi, V=V, dt=ph.dt, steps=k)
+        elif noise > 0:
+            oracle.rk4_noise(op, psi, n0, None, P, dt=ph.dt, steps=k, nu=noise, seed=1)
+        else:
+            oracle.rk4(op, psi, n0, None, P, dt=ph.dt, steps=k)
+        return time.perf_counter() - t0
+
+    threads = oracle.num_threads()
+    dt = run(steps)
+    out = {"value": ph.nx * ph.ny * steps / dt, "unit": "UP/s", "cores": threads, "kind": "oracle",
+           "sample": f"full {ph.nx}x{ph.ny} grid of the same workload, {steps} RK4 steps, "
+                     f"complex128 plain C oracle on {threads} OpenMP threads, {dt:.1f} s",
+           "cpu_model": cpu_model(), "host_threads": os.cpu_count()}
+    if steps_1t > 0:
+        oracle.set_num_threads(1)
+        try:
+            d1 = run(steps_1t)
+        finally:
+            oracle.set_num_threads(threads)
+        out["one_thread"] = {"value": ph.nx * ph.ny * steps_1t / d1, "unit": "UP/s",
+                             "sample": f"{steps_1t} RK4 steps of the same grid on 1 thread, {d1:.1f} s"}
+    return out
 
 
 def main():
@@ -91,6 +132,10 @@ def main():
     ap.add_argument("--n", type=int, default=4096, help="grid side (default 4096)")
     ap.add_argument("--precision", choices=["c64", "c128"], default="c64")
     ap.add_argument("--cpu-steps", type=int, default=50, help="oracle steps for the CPU baseline (about 10-30 s)")
+    ap.add_argument("--cpu-steps-1t", type=int, default=3,
+                    help="oracle steps for the one-thread CPU figure (0: skip)")
+    ap.add_argument("--event-steps", type=int, default=100,
+                    help="steps of the separate pass that times each kernel launch with HIP events")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel", choices=["auto", "stage", "step"], default="auto",
                     help="RK4 kernel family (auto: whole-step kernel)")
@@ -151,8 +196,11 @@ def main():
     Pd = None if P is None else torch.from_numpy(P).to(dtype=rdt, device=dev).contiguous()
     Vd = None if V0 is None else torch.from_numpy(V0).to(dtype=rdt, device=dev).contiguous()
     family = {"auto": phx.PHX_KERNEL_AUTO, "stage": phx.PHX_KERNEL_STAGE, "step": phx.PHX_KERNEL_STEP}[args.kernel]
+    # the timed steps are replays of one captured graph of G steps (G even, dividing K)
+    G = next((g for g in range(min(64, args.steps), 1, -1) if g % 2 == 0 and args.steps % g == 0), 0)
     cfg = phx.config_from_physics(ph, precision=precision, kernel=family, noise=args.noise, seed=1,
-                                  drive=E is not None, drive_omega=args.drive or 0.0, imag_time=args.imag)
+                                  drive=E is not None, drive_omega=args.drive or 0.0, imag_time=args.imag,
+                                  graph_steps=G if G else -1)
     if args.tile:
         cfg.tile_wx, cfg.tile_rows = args.tile
     solver = phx.Solver(cfg, psi, n, Vd, Pd, E=E)
@@ -164,14 +212,18 @@ def main():
     copy_gbps = copy_bandwidth_gbps(torch)
 
     solver.step(args.warmup)
-    torch.cuda.synchronize()
-    solver.set_timing(True)
+    if G:  # capture the graph before the timed region
+        solver.step(G)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     solver.step(args.steps)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    # per-kernel launch times: a separate pass of direct launches bracketed by HIP events
+    solver.set_timing(True)
+    solver.step(args.event_steps)
     times = solver.kernel_times()
+    solver.set_timing(False)
     obs = solver.observables()
     solver.close()
 
@@ -216,11 +268,12 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(ph, psi0, n0, P, args.cpu_steps, args.noise, args.imag, V0)
+        cpu = cpu_baseline(ph, psi0, n0, P, args.cpu_steps, args.noise, args.imag, V0, args.cpu_steps_1t)
 
     line = {
         "metric": METRIC, "value": value, "unit": "UP/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True,
+        "warmup": args.warmup, "graph_capture_steps": G, "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32" if real_bytes == 4 else "f64",
         "data": "synthetic",
         "config": {"workload": workload, "grid": [args.n, args.n], "integrator": "rk4", "noise": args.noise,
@@ -231,7 +284,8 @@ def main():
         "cpu_baseline": cpu,
         "step_model_bytes_per_point": step_bytes,
         "step_algorithmic_GBps": round(step_gbps, 1),
-        "copy_bandwidth_GBps": round(copy_gbps, 1),
+        "copy_kernel_GBps": round(copy_gbps, 1),
+        "event_pass_steps": args.event_steps,
         "kernels": {k: {kk: round(vv, 2) if isinstance(vv, float) else vv for kk, vv in v.items()}
                     for k, v in kernels.items()},
         "final_norm": obs["norm"][0], "nonfinite": obs["nonfinite"],

@@ -81,10 +81,16 @@ typedef struct phx_config {
     double dt_min, dt_max;  /* RK45 step bounds (0 < dt_min <= dt_max; dt_max may be inf) */
     int32_t kernel;         /* PHX_KERNEL_AUTO picks the fastest applicable kernel family */
     int32_t tile_wx;        /* 0 = automatic; stage-fused kernels: waves across x (1, 2, 4);
-                               whole-step kernel: waves per workgroup of the region form,
-                               or 1 for the streaming form (a tuned shape)                 */
-    int32_t tile_rows;      /* 0 = automatic; rows per wave (stage-fused: 1..64); streaming
-                               form: rows per band (40, 64, 88, 112; state under 2 GiB)    */
+                               whole-step kernel: waves per workgroup of the region form
+                               (4, 8, 12, 16), 1 for the streaming form, 2 or 3 for the wide
+                               streaming form (two columns per lane; complex64, one
+                               component, no drive or imaginary time, even nx; 2: 8-row
+                               input ring, 3: 12-row ring)                                 */
+    int32_t tile_rows;      /* rows per wave (stage-fused: 1..64); streaming form: rows per
+                               band (40, 64, 88, 112); wide streaming form: rows per band
+                               (8..4096), or 0 for the height that fills the device with
+                               one wave per band; streaming forms need a state under 2 GiB;
+                               0 with tile_wx 0 = automatic                                 */
     int32_t graph_steps;    /* RK4 steps per captured hipGraph chunk replayed by phx_step:
                                0 = default (64), < 0 = launch every kernel directly        */
     double noise;           /* intensity nu of the complex Wiener noise dW (Sec. 5, truncated
@@ -104,13 +110,17 @@ typedef struct phx_config {
                                E_s(r) from phx_fields.E, evaluated at every stage's own time
                                (RK4: t + {0, 1/2, 1/2, 1} dt; Dormand-Prince: its nodes c_s);
                                t is phx_info.t (a step taken k steps after the last
-                               phx_set_info or phx_create starts at t_set + k dt).  Stage-fused
-                               RK4 and RK45 (PHX_KERNEL_AUTO picks the stage-fused family;
-                               the whole-step kernel and batches: PHX_EUNSUPPORTED).  0: none */
+                               phx_set_info or phx_create starts at t_set + k dt).  RK4 on
+                               the streaming whole-step kernel (one component, bands of 40
+                               or 64 rows; PHX_KERNEL_AUTO picks it when the state is under
+                               2 GiB) or the stage-fused kernels (two components, or on
+                               request), and RK45; batches: PHX_EUNSUPPORTED.  0: none      */
     int32_t imag_time;      /* 1: imaginary-time propagation (t -> -i tau, named in Sec. 6)
                                of the conservative equation (reservoir, gamma_c, R, noise and
                                drive all off, else PHX_EINVAL): RK4 steps of
-                               d psi/d tau = -(1/hbar) H psi on the stage-fused kernels, each
+                               d psi/d tau = -(1/hbar) H psi (one component: the streaming
+                               whole-step kernel when the state is under 2 GiB, else the
+                               stage-fused kernels; two components: stage-fused), each
                                followed by scaling psi so that its total norm
                                dx dy sum_s,cells |psi_s|^2 equals the value it had when the
                                phx_step call began (deterministic FP64 reduction on the
@@ -247,7 +257,7 @@ phx_status phx_kernel_times(phx_handle *h, phx_timing *out);
  * unchanged.  The fastest shape is adopted for later phx_step calls and reported
  * in the phx_config encoding (stage-fused: tile_wx = waves across x, tile_rows =
  * rows per wave; whole-step: tile_wx = waves per workgroup, tile_rows = rows per
- * wave, or tile_wx = 1 and tile_rows = band rows for the streaming form), so that a
+ * wave, or tile_wx = 1, 2, 3 and tile_rows = band rows for the streaming forms), so that a
  * caller can cache it and pass it to phx_create next time.
  * Synchronizes the stream.  PHX_EUNSUPPORTED for RK45 handles. */
 typedef struct phx_tune_result {
@@ -382,6 +392,14 @@ phx_status phx_corrector_residual(int32_t precision, const void *psi_ref, const 
 /* Correction: psi += s_psi (y0 + i y1), n += s_n y2 (n may be NULL). */
 phx_status phx_corrector_apply(int32_t precision, void *psi, void *n, const float *y, int32_t nx, int32_t ny,
                                double s_psi, double s_n, void *hip_stream);
+
+/* ---------------------------------------------------------------- measurement
+ * Copies `bytes` from src to dst (device arrays, 16-byte aligned, bytes a multiple
+ * of 16, not overlapping) with a streaming copy kernel, enqueued on hip_stream.  It
+ * is the attainable-bandwidth reference beside which the solver kernels' HBM rates
+ * are reported (2 * bytes moved per call); it plays no part in the solver.
+ * PHX_EINVAL on bad arguments, PHX_EHIP if the launch fails. */
+phx_status phx_stream_copy(void *dst, const void *src, size_t bytes, void *hip_stream);
 
 #ifdef __cplusplus
 }

@@ -352,3 +352,11 @@ def num_threads() -> int:
     lib = _load()
     lib.orc_num_threads.restype = ctypes.c_int
     return int(lib.orc_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads for the oracle's later loops (for timing it on fewer cores)."""
+    lib = _load()
+    lib.orc_set_num_threads.argtypes = [ctypes.c_int]
+    lib.orc_set_num_threads.restype = None
+    lib.orc_set_num_threads(int(n))

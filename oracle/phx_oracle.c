@@ -577,5 +577,7 @@ void orc_rk4_noise(const orc_params *p, cplx *psi, double *n, const double *V, c
     }
 }
 
-/* Threads the OpenMP loops above use (reported beside timings of this oracle). */
+/* Threads the OpenMP loops above use (reported beside timings of this oracle), and
+   a setter for timing it on fewer threads (n >= 1). */
 int orc_num_threads(void) { return omp_get_max_threads(); }
+void orc_set_num_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }

@@ -96,8 +96,12 @@ static hipError_t launch_step_t(const StepArgs<R>& a, hipStream_t s)
 // recompute less halo, shorter ones need fewer registers per lane (more waves
 // per SIMD).  The first entry is the default; phx_autotune measures them all.
 // Shapes {1, B} are the streaming kernel with bands of B rows (B + 8 a multiple of 24).
+// Shapes {2, B} and {3, B} are the wide streaming kernel (two columns per lane) with
+// bands of B rows, B = 0 choosing the height that fills the device in one wave of
+// workgroups (complex64 only).
 static const StepShapeId kFloatShapes[] = {{8, 4}, {16, 4}, {8, 8}, {12, 4}, {12, 6}, {8, 6}, {4, 8}, {16, 6},
-                                           {1, 40}, {1, 64}, {1, 88}, {1, 112}};
+                                           {1, 40}, {1, 64}, {1, 88}, {1, 112},
+                                           {2, 0}, {3, 0}, {2, 40}, {2, 64}, {3, 64}, {3, 96}};
 static const StepShapeId kDoubleShapes[] = {{8, 4}, {16, 2}, {8, 2}, {12, 4}, {4, 4}, {1, 40}, {1, 64}};
 
 int step_shapes(int precision, const StepShapeId** out)
@@ -137,6 +141,13 @@ hipError_t launch_rk4_step(bool reservoir, bool has_v, const StepShapeId& sh, co
                            hipStream_t s)
 {
     if (a.E) return sh.waves == 1 ? launch_stream_drive<R>(reservoir, has_v, sh.rows, a, s) : hipErrorInvalidValue;
+    if (wide_shape(sh.waves)) {
+        if constexpr (sizeof(R) == 4) {
+            if (a.comps != 1 || a.imag_partials) return hipErrorInvalidValue;
+            return launch_stream_wide(reservoir, has_v, sh.waves == 2 ? 8 : 12, a, s);
+        }
+        return hipErrorInvalidValue;
+    }
     if (a.comps == 2)
         return sh.waves == 1 ? launch_stream_spinor<R>(reservoir, has_v, sh.rows, a, s) : hipErrorInvalidValue;
     if (reservoir) return has_v ? launch_step_shape<R, true, true>(sh, a, s) : launch_step_shape<R, true, false>(sh, a, s);
@@ -156,7 +167,11 @@ static StepArgs<R> step_args(const phx_handle* h, const StepShapeId& sh, const v
     a.bcx = c.bc_x;
     a.bcy = c.bc_y;
     a.tiles_x = (c.nx + 55) / 56;
-    if (sh.waves == 1) {  // streaming: strips of 56 columns, workgroups of 4 strips x one band
+    if (wide_shape(sh.waves)) {  // wide streaming: strips of 120 columns, one wave per band of a strip
+        a.tiles_x = wide_strips(c.nx);
+        a.band_rows = wide_band_rows(c, sh, h->f.V != nullptr, h->cus);
+        a.tiles = a.tiles_x * ((c.ny + a.band_rows - 1) / a.band_rows);
+    } else if (sh.waves == 1) {  // streaming: strips of 56 columns, workgroups of 4 strips x one band
         a.tiles = ((a.tiles_x + 3) / 4) * ((c.ny + sh.rows - 1) / sh.rows);
     } else {
         const int oh = sh.waves * sh.rows - 8;

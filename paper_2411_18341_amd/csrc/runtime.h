@@ -77,6 +77,7 @@ struct phx_handle {
     void* cur_n;
     void* other_n;
     phx::StepShapeId step_shape;  // whole-step RK4 region shape in use
+    int cus;                      // compute units of the handle's device
     phx::TilePlan stage_tiles;    // stage-fused RK4 tile plan in use
     int step_parity;              // whole-step family: buffer holding the state (0 = caller's)
     // coherent drive: time and step index of the last phx_create / phx_set_info
@@ -137,6 +138,15 @@ bool step_shape_fits(const phx_config& c, int waves);
 // the spinor on bands of 40 and 64 rows).
 bool step_shape_allowed(const phx_config& c, const StepShapeId& sh);
 bool drive_stream_rows(int rows);
+// Wide streaming form (shapes {2, B}: 8-row input ring, {3, B}: 12-row ring; B = 0
+// chooses the band height that fills the device): strips of 120 output columns and
+// the band height in rows for this grid on a device with `cus` compute units.
+template <typename R> struct StepArgs;
+bool wide_shape(int waves);
+int wide_strips(int nx);
+int wide_band_rows(const phx_config& c, const StepShapeId& sh, bool has_v, int cus);
+int wide_waves_per_simd(int ring, bool reservoir, bool has_v, bool ghosts);
+hipError_t launch_stream_wide(bool reservoir, bool has_v, int ring, const StepArgs<float>& a, hipStream_t s);
 int rk4_family(const phx_config& c);
 phx_status step_rk45(phx_handle* h, int64_t n, phx_info* out);
 phx_status set_info_rk45(phx_handle* h, const phx_info* in);

@@ -57,7 +57,9 @@ phx_status validate_config(const phx_config* c)
         (c->integrator != PHX_RK4 || (c->components == 2 && (c->drive || c->imag_time))))
         return fail(PHX_EUNSUPPORTED, "the whole-step kernel covers RK4 with one component, or two without the "
                                       "drive and imaginary time");
-    if ((c->tile_wx == 0) != (c->tile_rows == 0)) return fail(PHX_EINVAL, "tile_wx and tile_rows: both 0 or both set");
+    if ((c->tile_wx == 0) != (c->tile_rows == 0) && !(wide_shape(c->tile_wx) && c->kernel != PHX_KERNEL_STAGE))
+        return fail(PHX_EINVAL, "tile_wx and tile_rows: both 0 or both set (tile_rows 0 with tile_wx 2 or 3: "
+                                "the wide streaming form with the device-filling band height)");
     if (c->tile_wx != 0) {
         if (c->integrator == PHX_RK4 && rk4_family(*c) == PHX_KERNEL_STEP) {
             if ((c->imag_time || c->drive || c->components == 2) && c->tile_wx != 1)
@@ -68,7 +70,8 @@ phx_status validate_config(const phx_config* c)
             if (!valid_step_shape(c->precision, c->tile_wx, c->tile_rows))
                 return fail(PHX_EINVAL, "tile %d x %d is not a whole-step kernel shape", c->tile_wx, c->tile_rows);
             if (!step_shape_fits(*c, c->tile_wx))
-                return fail(PHX_EINVAL, "streaming shapes (tile_wx 1) need a state array under 2 GiB");
+                return fail(PHX_EINVAL, "streaming shapes (tile_wx 1, 2, 3) need a state array under 2 GiB; the "
+                                        "wide ones (tile_wx 2, 3) complex64 and an even nx");
         } else if ((c->tile_wx != 1 && c->tile_wx != 2 && c->tile_wx != 4) || c->tile_rows < 1 || c->tile_rows > 64) {
             return fail(PHX_EINVAL, "tile_wx must be 1, 2 or 4 and tile_rows 1..64");
         }
@@ -165,13 +168,35 @@ Layout make_layout(const phx_config& c)
     return L;
 }
 
-// The streaming shapes (waves == 1) address their output through 32-bit buffer
-// offsets: the complex state array must stay below 2 GiB.
+// The streaming shapes (waves 1, and 2 or 3 for the wide form) address their arrays
+// through 32-bit buffer offsets: the complex state array must stay below 2 GiB.  The
+// wide form runs complex64 with one component (no drive, no imaginary time) on grids
+// of even width.
 bool step_shape_fits(const phx_config& c, int waves)
 {
     const double bytes = (double)c.nx * c.ny * c.components * (c.precision == PHX_C64 ? 8.0 : 16.0);
     if ((c.imag_time || c.drive || c.components == 2) && waves != 1) return false;  // streaming form only
-    return waves != 1 || bytes < 2147483648.0 - 256.0;
+    if (wide_shape(waves) && (c.precision != PHX_C64 || c.nx % 2 != 0)) return false;
+    return waves > 3 || bytes < 2147483648.0 - 256.0;
+}
+
+bool wide_shape(int waves) { return waves == 2 || waves == 3; }
+
+int wide_strips(int nx) { return (nx + 119) / 120; }
+
+// Band height of a wide shape.  rows > 0 is taken as given; rows = 0 picks the
+// smallest height whose bands, one wave each, fit on the device at once (at the
+// kernel's waves per SIMD), at least 16 rows.
+int wide_band_rows(const phx_config& c, const StepShapeId& sh, bool has_v, int cus)
+{
+    if (sh.rows > 0) return sh.rows;
+    const bool ghosts = c.bc_x == PHX_BC_ZERO || c.bc_y == PHX_BC_ZERO;
+    const int per_simd = wide_waves_per_simd(sh.waves == 2 ? 8 : 12, c.reservoir != 0, has_v, ghosts);
+    const int slots = (cus > 0 ? cus : 256) * 4 * per_simd;
+    const int per_strip = slots / wide_strips(c.nx);
+    const int bands = per_strip > 0 ? per_strip : 1;
+    const int b = (c.ny + bands - 1) / bands;
+    return b < 16 ? 16 : b;
 }
 
 bool step_shape_allowed(const phx_config& c, const StepShapeId& sh)
@@ -182,6 +207,7 @@ bool step_shape_allowed(const phx_config& c, const StepShapeId& sh)
 
 bool valid_step_shape(int precision, int waves, int rows)
 {
+    if (wide_shape(waves)) return precision == PHX_C64 && (rows == 0 || (rows >= 8 && rows <= 4096));
     const StepShapeId* sh;
     const int n = step_shapes(precision, &sh);
     for (int k = 0; k < n; ++k)
@@ -305,6 +331,14 @@ phx_status phx_create(const phx_config* cfg, const phx_fields* f, void* stream,
     if (e == hipSuccess) e = hipEventCreateWithFlags(&h->flag_ready, hipEventDisableTiming);
     h->drive_t0 = 0.0;
     h->drive_k0 = 0;
+    {
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+            h->cus = cus;
+        else
+            h->cus = 256;
+    }
     if (e == hipSuccess) e = hipMemsetAsync(h->ws + L.flag, 0, 256, h->stream);
     if (e == hipSuccess) e = hipMemsetAsync(h->ws + L.zeros, 0, 256, h->stream);
     if (e == hipSuccess && uses_step_index(*cfg)) e = set_noise_step(h, 0, h->stream);

@@ -131,7 +131,8 @@ ENTRY_POINTS = ("phx_workspace_bytes", "phx_create", "phx_step", "phx_observable
                 "phx_autotune", "phx_batch_workspace_bytes", "phx_batch_step", "phx_cnn_sizes",
                 "phx_cnn_param_offsets", "phx_cnn_create", "phx_cnn_destroy", "phx_cnn_forward",
                 "phx_cnn_gradients", "phx_cnn_adam", "phx_cnn_train_step", "phx_coarsen",
-                "phx_corrector_features", "phx_corrector_residual", "phx_corrector_apply")
+                "phx_corrector_features", "phx_corrector_residual", "phx_corrector_apply",
+                "phx_stream_copy")
 
 _lib = None
 
@@ -191,6 +192,8 @@ def load(path: str | None = None):
     lib.phx_corrector_features.argtypes = [i32, vp, vp, vp, i32, i32, dbl, dbl, dbl, vp, vp]
     lib.phx_corrector_residual.argtypes = [i32, vp, vp, vp, vp, i32, i32, dbl, dbl, vp, vp]
     lib.phx_corrector_apply.argtypes = [i32, vp, vp, vp, i32, i32, dbl, dbl, vp]
+    lib.phx_stream_copy.argtypes = [vp, vp, ctypes.c_size_t, vp]
+    lib.phx_stream_copy.restype = st
     for name in ("phx_cnn_sizes", "phx_cnn_param_offsets", "phx_cnn_create", "phx_cnn_forward",
                  "phx_cnn_gradients", "phx_cnn_adam", "phx_cnn_train_step", "phx_coarsen",
                  "phx_corrector_features", "phx_corrector_residual", "phx_corrector_apply"):
@@ -287,6 +290,20 @@ def phx_batch_workspace_bytes(desc: phx_batch_desc) -> int:
 
 def phx_batch_step(desc: phx_batch_desc, n_steps: int, stream: int | None) -> None:
     _check(load().phx_batch_step(ctypes.byref(desc), int(n_steps), stream or None))
+
+
+def phx_stream_copy(dst, src, nbytes: int, stream: int | None) -> None:
+    _check(load().phx_stream_copy(dst, src, int(nbytes), stream or None))
+
+
+def stream_copy(dst, src, stream=None) -> None:
+    """Copy tensor src into tensor dst (same byte size, CUDA, contiguous) with the
+    library's streaming copy kernel on `stream` (default: torch's current stream)."""
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes or not (src.is_contiguous() and dst.is_contiguous()):
+        raise ValueError("dst and src must be contiguous and of equal byte size")
+    phx_stream_copy(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()), nbytes,
+                    _stream_handle(stream, src.device))
 
 
 # ------------------------------------------------------------ conveniences

@@ -113,7 +113,7 @@ def test_workspace_bytes_scale_with_precision_and_reservoir():
     ("nx", 0), ("ny", -3), ("dx", 0.0), ("dy", float("nan")), ("bc_x", 2), ("components", 3),
     ("reservoir", 2), ("precision", 5), ("integrator", 9), ("hbar", 0.0), ("mass", -1.0),
     ("g", float("inf")), ("dt", 0.0), ("dt", 1.0), ("kernel", 7),
-    ("tile_wx", 3), ("tile_rows", 5), ("tile_rows", 65), ("noise", -1.0), ("noise", float("nan")),
+    ("tile_wx", 5), ("tile_rows", 5), ("tile_rows", 65), ("noise", -1.0), ("noise", float("nan")),
     ("drive", 2), ("drive_omega", float("inf")), ("imag_time", 2),
 ])
 def test_invalid_config_rejected(field, value):
@@ -254,6 +254,21 @@ def test_tile_shape_validation_per_family():
     for bad in [(1, 44), (1, 16)]:
         with pytest.raises(phx.PhxError):
             phx.phx_workspace_bytes(good_config(tile_wx=bad[0], tile_rows=bad[1]))
+    # wide streaming form: tile_wx 2 (8-row ring) or 3 (12-row ring), bands of 8..4096
+    # rows or 0 (chosen per device), complex64 on grids of even width
+    for shape in [(2, 0), (3, 0), (2, 40), (3, 200), (2, 4096)]:
+        phx.phx_workspace_bytes(good_config(tile_wx=shape[0], tile_rows=shape[1]))
+    for bad in [(2, 3), (3, 5000), (2, -1)]:
+        with pytest.raises(phx.PhxError) as e:
+            phx.phx_workspace_bytes(good_config(tile_wx=bad[0], tile_rows=bad[1]))
+        assert e.value.status == phx.PHX_EINVAL
+    with pytest.raises(phx.PhxError):
+        phx.phx_workspace_bytes(good_config(precision=phx.PHX_C128, tile_wx=2, tile_rows=40))
+    odd = good_config(tile_wx=3, tile_rows=64)
+    odd.nx = 255
+    with pytest.raises(phx.PhxError) as e:
+        phx.phx_workspace_bytes(odd)
+    assert e.value.status == phx.PHX_EINVAL
     big = good_config(tile_wx=1, tile_rows=40)
     big.nx, big.ny = 16384, 16384          # 2 GiB of complex64 state
     with pytest.raises(phx.PhxError) as e:

@@ -194,27 +194,34 @@ def _patch(a, j, i, r):
     return a[..., rows[:, None], cols[None, :]]
 
 
-@pytest.mark.parametrize("family", FAMILIES)
+@pytest.mark.parametrize("family,tile", [(phx.PHX_KERNEL_STAGE, None), (phx.PHX_KERNEL_AUTO, None),
+                                         (phx.PHX_KERNEL_STEP, (1, 40)), (phx.PHX_KERNEL_STEP, (2, 0)),
+                                         (phx.PHX_KERNEL_STEP, (3, 0))])
 @pytest.mark.parametrize("steps", [1, 3])
-def test_driven_4096_sampled(steps, family):
-    """The benchmark workload (driven, 4096^2, complex64, automatic tile plan):
-    sampled cells after `steps` steps against the oracle on patches of radius 4*steps
-    (zero boundary outside the patch cannot reach the centre in time)."""
+def test_driven_4096_sampled(steps, family, tile):
+    """The benchmark workload (driven, 4096^2, complex64) on the automatic tile plan,
+    the stage-fused kernels and the streaming shapes the benchmark may adopt (one
+    column per lane with bands of 40 rows; two per lane with the device-filling band
+    height of either ring): sampled cells after `steps` steps against the oracle on
+    patches of radius 4*steps (zero boundary outside the patch cannot reach the
+    centre in time)."""
     precision = C64
+    kw = {} if tile is None else dict(tile_wx=tile[0], tile_rows=tile[1])
     ph, psi, n0, P = inputs.driven(4096)
     # a state that has some structure: noise plus a condensate-like blob
     X, Y = inputs.coords(4096, 4096, ph.dx, ph.dy)
     psi = psi + (3.0 * np.exp(-(X * X + Y * Y) / 400.0))[None]
     n0 = n0 + 10.0 * np.exp(-(X * X + Y * Y) / 900.0)[None]
     q = quantize(precision, psi, n0, None, P)
-    run = GpuRun(ph, *q, precision=precision, kernel=family)
+    run = GpuRun(ph, *q, precision=precision, kernel=family, **kw)
     run.step(steps)
     g_psi, g_n = run.state()
     run.close()
     r = 4 * steps
     rng = np.random.default_rng(11)
     pts = [(int(a), int(b)) for a, b in rng.integers(0, 4096, (48, 2))]
-    pts += [(0, 0), (0, 4095), (4095, 0), (4095, 4095), (2048, 2048), (2047, 100), (13, 2048)]
+    pts += [(0, 0), (0, 4095), (4095, 0), (4095, 4095), (2048, 2048), (2047, 100), (13, 2048),
+            (47, 119), (48, 120), (95, 4079), (96, 4080), (1000, 239), (1001, 240)]
     op = oracle_physics(ph)
     op.nx = op.ny = 2 * r + 1
     op.bc_x = op.bc_y = oracle.BC_ZERO
@@ -300,8 +307,9 @@ def test_checkpoint_resume_bitwise(family):
     assert np.array_equal(out[0], ref[0]) and np.array_equal(out[1], ref[1])
 
 
+WIDE_SHAPES = [(2, 0), (3, 0), (2, 40), (2, 64), (3, 64), (3, 96)]
 STEP_SHAPES = {C64: [(8, 4), (16, 4), (8, 8), (12, 4), (12, 6), (8, 6), (4, 8), (16, 6),
-                     (1, 40), (1, 64), (1, 88), (1, 112)],
+                     (1, 40), (1, 64), (1, 88), (1, 112)] + WIDE_SHAPES,
                C128: [(8, 4), (16, 2), (8, 2), (12, 4), (4, 4), (1, 40), (1, 64)]}
 
 
@@ -320,22 +328,42 @@ def test_stream_kernel_edges(shape, bc, precision):
         assert e_psi <= TOL[precision] and e_n <= TOL[precision], (steps, e_psi, e_n)
 
 
+@pytest.mark.parametrize("precision", PREC)
 @pytest.mark.parametrize("bc", [(0, 0), (1, 1), (0, 1)])
-def test_stream_and_region_kernels_bitwise(bc):
-    """The streaming and the region whole-step kernels apply the same per-cell
-    arithmetic in the same order: their states agree bit for bit."""
-    for precision in PREC:
-        ph, psi, n, V, P = workload("driven_v", 300, 211, bc, seed=19)
-        q = quantize(precision, psi, n, V, P)
-        out = []
-        for shape in [(8, 4), (1, 40), (1, 64)]:
-            run = GpuRun(ph, *q, precision=precision, kernel=phx.PHX_KERNEL_STEP, tile_wx=shape[0],
-                         tile_rows=shape[1])
-            run.step(9)
-            out.append(run.state())
-            run.close()
-        for p_, n_ in out[1:]:
-            assert np.array_equal(p_, out[0][0]) and np.array_equal(n_, out[0][1])
+@pytest.mark.parametrize("kind", ["driven_v", "driven", "conservative"])
+def test_stream_and_region_kernels_bitwise(kind, bc, precision):
+    """The streaming (one and two columns per lane) and the region whole-step kernels
+    apply the same per-cell arithmetic in the same order: their states agree bit for
+    bit, with and without the reservoir and the potential."""
+    shapes = [(8, 4), (1, 40), (1, 64)] + ([(2, 0), (3, 0), (2, 40), (3, 16)] if precision == C64 else [])
+    ph, psi, n, V, P = workload(kind, 300, 211, bc, seed=19)
+    q = quantize(precision, psi, n, V, P)
+    out = []
+    for shape in shapes:
+        run = GpuRun(ph, *q, precision=precision, kernel=phx.PHX_KERNEL_STEP, tile_wx=shape[0],
+                     tile_rows=shape[1])
+        run.step(9)
+        out.append(run.state())
+        run.close()
+    for shape, (p_, n_) in zip(shapes[1:], out[1:]):
+        assert np.array_equal(p_, out[0][0]), shape
+        assert (n_ is None and out[0][1] is None) or np.array_equal(n_, out[0][1]), shape
+
+
+@pytest.mark.parametrize("bc", BCS)
+@pytest.mark.parametrize("shape", [(120, 40), (122, 41), (240, 131), (118, 39), (2, 1), (2, 5), (4, 1),
+                                   (64, 1), (126, 3), (2, 65), (8, 17), (360, 8)])
+@pytest.mark.parametrize("tile", [(2, 0), (3, 8), (2, 16)])
+def test_wide_stream_kernel_edges(tile, shape, bc):
+    """Wide streaming kernel (two columns per lane, strips of 120 columns) on even
+    widths around multiples of the strip, single rows, narrow grids and bands taller
+    than the grid, for 1, 2 and 7 steps."""
+    nx, ny = shape
+    ph, psi, n, V, P = workload("driven_v", nx, ny, bc, seed=28)
+    for steps in (1, 2, 7):
+        e_psi, e_n = compare(ph, psi, n, V, P, steps, C64, kernel=phx.PHX_KERNEL_STEP,
+                             tile_wx=tile[0], tile_rows=tile[1])
+        assert e_psi <= TOL[C64] and e_n <= TOL[C64], (steps, e_psi, e_n)
 
 
 @pytest.mark.parametrize("precision", PREC)
