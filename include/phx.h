@@ -393,6 +393,22 @@ phx_status phx_corrector_residual(int32_t precision, const void *psi_ref, const 
 phx_status phx_corrector_apply(int32_t precision, void *psi, void *n, const float *y, int32_t nx, int32_t ny,
                                double s_psi, double s_n, void *hip_stream);
 
+/* ---------------------------------------------------------------- without allocation
+ * phx_observables for callers that cannot allocate device memory (code under hipGraph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the observables of
+ * the given fields (bound as in phx_create; workspace ignored) for configuration
+ * cfg, at time t (the drive's phase in the steady residual).  The same kernels,
+ * block partition and summation order as phx_observables, so the results agree bit
+ * for bit; the per-workgroup partials (at most PHX_STATIC_OBS_BLOCKS workgroups, 128
+ * KiB) live in one array of static device memory per GPU that the library holds
+ * until the process ends.  Calls no allocator.  Calls that overlap on one GPU race
+ * on that array (serialize them, e.g. on one stream).  Synchronizes hip_stream.
+ * PHX_EINVAL on bad arguments, PHX_EWORKSPACE if the grid needs more partials than
+ * the array holds, PHX_EHIP on a runtime failure. */
+#define PHX_STATIC_OBS_BLOCKS 1024
+phx_status phx_observables_static(const phx_config *cfg, const phx_fields *f, double t, void *hip_stream,
+                                  phx_obs *out);
+
 /* ---------------------------------------------------------------- measurement
  * Copies `bytes` from src to dst (device arrays, 16-byte aligned, bytes a multiple
  * of 16, not overlapping) with a streaming copy kernel, enqueued on hip_stream.  It

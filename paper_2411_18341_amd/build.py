@@ -19,7 +19,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 OUT = os.path.join(HERE, "libphx.so")
 BUILD_DIR = os.path.join(HERE, "_build")
-SOURCES = ["rk4_step.hip", "rk4_stream_spinor_res_f40.hip", "rk4_stream_spinor_res_f64.hip", "rk4_stream_spinor_res_d40.hip", "rk4_stream_spinor_res_d64.hip", "runtime.hip", "rk4.hip", "reduce.hip", "dopri5.hip", "batch.hip", "autotune.hip", "cnn.hip", "noise.hip", "drive.hip", "imag.hip", "rk4_stream_drive.hip", "rk4_stream_spinor.hip", "rk4_stream_wide.hip", "copy.hip"]
+SOURCES = ["rk4_step.hip", "rk4_stream_spinor_res_f40.hip", "rk4_stream_spinor_res_f64.hip", "rk4_stream_spinor_res_d40.hip", "rk4_stream_spinor_res_d64.hip", "runtime.hip", "rk4.hip", "reduce.hip", "dopri5.hip", "batch.hip", "autotune.hip", "cnn.hip", "noise.hip", "drive.hip", "imag.hip", "rk4_stream_drive.hip", "rk4_stream_spinor.hip", "rk4_stream_wide.hip", "copy.hip", "static_obs.hip"]
 
 ARCH = "gfx950"
 FLAGS = [

@@ -132,7 +132,7 @@ ENTRY_POINTS = ("phx_workspace_bytes", "phx_create", "phx_step", "phx_observable
                 "phx_cnn_param_offsets", "phx_cnn_create", "phx_cnn_destroy", "phx_cnn_forward",
                 "phx_cnn_gradients", "phx_cnn_adam", "phx_cnn_train_step", "phx_coarsen",
                 "phx_corrector_features", "phx_corrector_residual", "phx_corrector_apply",
-                "phx_stream_copy")
+                "phx_stream_copy", "phx_observables_static")
 
 _lib = None
 
@@ -194,6 +194,8 @@ def load(path: str | None = None):
     lib.phx_corrector_apply.argtypes = [i32, vp, vp, vp, i32, i32, dbl, dbl, vp]
     lib.phx_stream_copy.argtypes = [vp, vp, ctypes.c_size_t, vp]
     lib.phx_stream_copy.restype = st
+    lib.phx_observables_static.argtypes = [P(phx_config), P(phx_fields), ctypes.c_double, vp, P(phx_obs)]
+    lib.phx_observables_static.restype = st
     for name in ("phx_cnn_sizes", "phx_cnn_param_offsets", "phx_cnn_create", "phx_cnn_forward",
                  "phx_cnn_gradients", "phx_cnn_adam", "phx_cnn_train_step", "phx_coarsen",
                  "phx_corrector_features", "phx_corrector_residual", "phx_corrector_apply"):
@@ -290,6 +292,21 @@ def phx_batch_workspace_bytes(desc: phx_batch_desc) -> int:
 
 def phx_batch_step(desc: phx_batch_desc, n_steps: int, stream: int | None) -> None:
     _check(load().phx_batch_step(ctypes.byref(desc), int(n_steps), stream or None))
+
+
+def phx_observables_static(cfg: phx_config, fields: phx_fields, t: float, stream: int | None) -> phx_obs:
+    out = phx_obs()
+    _check(load().phx_observables_static(ctypes.byref(cfg), ctypes.byref(fields), float(t), stream or None,
+                                         ctypes.byref(out)))
+    return out
+
+
+def observables_static(cfg: phx_config, psi, n=None, V=None, P=None, E=None, t: float = 0.0, stream=None) -> dict:
+    """Observables of the given device tensors without a handle or workspace (the
+    library's allocation-free entry point), on `stream` (default: torch's current)."""
+    ptr = lambda x: None if x is None else x.data_ptr()
+    fields = phx_fields(ptr(psi), ptr(n), ptr(V), ptr(P), None, 0, ptr(E))
+    return phx_observables_static(cfg, fields, t, _stream_handle(stream, psi.device)).as_dict()
 
 
 def phx_stream_copy(dst, src, nbytes: int, stream: int | None) -> None:
