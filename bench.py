@@ -250,7 +250,10 @@ def main():
     dom = max(kernels, key=lambda k: kernels[k]["avg_us"] * kernels[k]["launches"])
     d = kernels[dom]
     # counter measurements of the whole-step kernel are kept per region shape
-    shape_key = dom if dom != "rk4_step" or tune is None else f"rk4_step_{tune['tile_wx']}x{tune['tile_rows']}"
+    shape_key = dom
+    if dom == "rk4_step" and tune is not None:
+        wx, rows = tune["tile_wx"], tune["tile_rows"]
+        shape_key = f"rk4_step_wide{8 if wx == 2 else 12}" if wx in (2, 3) else f"rk4_step_{wx}x{rows}"
     # the drive and imaginary time change what the stage kernels read: their counter records
     # are separate files
     traffic = measured_traffic(shape_key, step_workload) if args.drive is None and not args.imag else None

@@ -12,19 +12,19 @@
 
 namespace phx {
 
-template <bool RES, bool HASV, bool GHOSTS, bool YZERO, int K, int PF, int WPE>
+template <bool RES, bool HASV, bool GHOSTS, bool YZERO, int K, int PF, int WPE, bool CHECK>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE)))
 void rk4_stream_wide_kernel(const StepArgs<float> a)
 {
     const int t = xcd_tile(blockIdx.x, gridDim.x);
     const int band = t / a.tiles_x, strip = t - band * a.tiles_x;
-    if (stream_band_wide<RES, HASV, GHOSTS, YZERO, K, PF>(a, strip, band, a.band_rows, (band & 1) ? -1 : 1))
+    if (stream_band_wide<RES, HASV, GHOSTS, YZERO, K, PF, CHECK>(a, strip, band, a.band_rows, (band & 1) ? -1 : 1))
         a.flag[0] = 1u;  // benign race: every writer stores 1
 }
 
-// Waves per SIMD the register budget is set for: 3 with the 8-row ring (2 when the
-// reservoir comes with a potential or a zero boundary, whose extra registers would
-// not fit in 168), 2 with the 12-row ring.
+// Waves per SIMD the register budget of the (non-checking) kernel is set for: 3 with
+// the 8-row ring (2 when the reservoir comes with a potential or a zero boundary,
+// whose extra registers would not fit in 168), 2 with the 12-row ring.
 int wide_waves_per_simd(int ring, bool reservoir, bool has_v, bool ghosts)
 {
     return ring == 8 && !(reservoir && (has_v || ghosts)) ? 3 : 2;
@@ -34,7 +34,13 @@ template <bool RES, bool HASV, bool GHOSTS, bool YZERO, int K, int PF>
 static void launch_wide_k(const StepArgs<float>& a, hipStream_t s)
 {
     constexpr int WPE = (K == 8 && !(RES && (HASV || GHOSTS))) ? 3 : 2;
-    rk4_stream_wide_kernel<RES, HASV, GHOSTS, YZERO, K, PF, WPE><<<a.tiles, 64, 0, s>>>(a);
+    // the checking variant (the last step of a run) needs a few more registers: with
+    // the reservoir it is built for 2 waves per SIMD
+    constexpr int WPE_CHECK = RES ? 2 : WPE;
+    if (a.check)
+        rk4_stream_wide_kernel<RES, HASV, GHOSTS, YZERO, K, PF, WPE_CHECK, true><<<a.tiles, 64, 0, s>>>(a);
+    else
+        rk4_stream_wide_kernel<RES, HASV, GHOSTS, YZERO, K, PF, WPE, false><<<a.tiles, 64, 0, s>>>(a);
 }
 
 template <bool RES, bool HASV, int K, int PF>

@@ -45,6 +45,7 @@ struct StepArgs {
     int comps;  // 2: the spinor streaming kernel (component stride nx*ny)
     const double* zeros;  // streaming form: 32 zero bytes that ghost cells read
     int band_rows;        // wide streaming form: rows per band (a launch argument)
+    int check;            // wide streaming form: test the stored values for non-finite ones
 };
 
 // value held by lane-1 (lane 0 receives 0) and by lane+1 (lane 63 receives 0):

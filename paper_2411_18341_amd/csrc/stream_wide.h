@@ -54,9 +54,11 @@ __device__ __forceinline__ void wstore2(wf2 v, __amdgpu_buffer_rsrc_t r, int vof
 }
 
 // One band of `B` rows of strip `strip`; K is the length of the input ring (rows
-// j-4 .. j+PF must fit: PF <= K - 5) and must divide 24.  Returns true when a stored
-// value is not finite.
-template <bool RES, bool HASV, bool GHOSTS, bool YZERO, int K, int PF>
+// j-4 .. j+PF must fit: PF <= K - 5) and must divide 24.  CHECK: returns true when a
+// stored value is not finite (else false without testing: a non-finite value never
+// becomes finite again in later steps, so testing the last step of a run of steps
+// detects it).
+template <bool RES, bool HASV, bool GHOSTS, bool YZERO, int K, int PF, bool CHECK>
 __device__ __forceinline__ bool stream_band_wide(const StepArgs<float>& a, int strip, int band, int B, int dir)
 {
     using C = float2;
@@ -77,6 +79,7 @@ __device__ __forceinline__ bool stream_band_wide(const StepArgs<float>& a, int s
     const __amdgpu_buffer_rsrc_t rV = buffer_of(a.V, HASV ? cells * 4 : 0);
     const __amdgpu_buffer_rsrc_t rpo = buffer_of(a.psi_out, cells * 8);
     const __amdgpu_buffer_rsrc_t rno = buffer_of(a.n_out, RES ? cells * 4 : 0);
+    const __amdgpu_buffer_rsrc_t rnull = buffer_of(a.psi_out, 0);  // every access out of range
     // column offsets within a row; a ghost pair reads past the buffer (0)
     const int v8 = gcol ? kOutOfRange : (ci < 0 ? 0 : ci) * 8;
     const int v4 = gcol ? kOutOfRange : (ci < 0 ? 0 : ci) * 4;
@@ -178,7 +181,7 @@ __device__ __forceinline__ bool stream_band_wide(const StepArgs<float>& a, int s
                              fx[1], fy[1], fn[1]);
     };
 
-    bool bad = false;
+    unsigned bad = 0u;
     for (int base = 0; base < npos; base += 24) {
 #pragma unroll
         for (int u = 0; u < 24; ++u) {
@@ -247,20 +250,24 @@ __device__ __forceinline__ bool stream_band_wide(const StepArgs<float>& a, int s
                     y[2 * e + 1] = fmaf(a.dt6, ac.y + fy[e], p0.y);
                     yn[e] = fmaf(a.dt6, accn[slot<4>(u, 4)][e] + fn[e], sn[s0][e]);
                 }
+                // Stores are issued at every position (no branch: the memory counters
+                // then stay the same on every path through the loop); a row outside
+                // the band goes to a descriptor of size 0, whose stores are dropped.
                 const int r = j - 4 * dir;
-                if (r >= b0 && r < b0 + B && r < a.ny) {  // uniform
-                    wstore4(wf4{y[0], y[1], y[2], y[3]}, rpo, o8, r * row8);
-                    bool b = !(isfinite(y[0]) && isfinite(y[1]) && isfinite(y[2]) && isfinite(y[3]));
-                    if (RES) {
-                        wstore2(wf2{yn[0], yn[1]}, rno, o4, r * row4);
-                        b = b || !(isfinite(yn[0]) && isfinite(yn[1]));
-                    }
-                    bad = bad || (out_col && b);
+                const bool st = r >= b0 && r < b0 + B && r < a.ny;  // uniform
+                const int rr = st ? r : 0;
+                wstore4(wf4{y[0], y[1], y[2], y[3]}, st ? rpo : rnull, o8, rr * row8);
+                if (RES) wstore2(wf2{yn[0], yn[1]}, st ? rno : rnull, o4, rr * row4);
+                if (CHECK) {
+                    unsigned nf = (unsigned)!isfinite(y[0]) | (unsigned)!isfinite(y[1]) |
+                                  (unsigned)!isfinite(y[2]) | (unsigned)!isfinite(y[3]);
+                    if (RES) nf |= (unsigned)!isfinite(yn[0]) | (unsigned)!isfinite(yn[1]);
+                    bad |= (st && out_col) ? nf : 0u;
                 }
             }
         }
     }
-    return bad;
+    return bad != 0u;
 }
 
 }  // namespace phx

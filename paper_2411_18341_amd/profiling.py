@@ -28,7 +28,8 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 # sources whose change invalidates a stored counter measurement of the RK4 kernels
 KERNEL_SOURCES = ["paper_2411_18341_amd/csrc/rk4.hip", "paper_2411_18341_amd/csrc/stencil.h",
                   "paper_2411_18341_amd/csrc/phx_kernels.h", "paper_2411_18341_amd/csrc/rk4_step.hip",
-                  "paper_2411_18341_amd/csrc/step_body.h", "paper_2411_18341_amd/csrc/stream_body.h"]
+                  "paper_2411_18341_amd/csrc/step_body.h", "paper_2411_18341_amd/csrc/stream_body.h",
+                  "paper_2411_18341_amd/csrc/stream_wide.h", "paper_2411_18341_amd/csrc/rk4_stream_wide.hip"]
 
 
 def kernel_source_hash(sources=None) -> str:
@@ -46,11 +47,15 @@ def kernel_source_hash(sources=None) -> str:
 def kernel_kind(name: str) -> str:
     """Kernel kind as the solver's timing API names it (rk4_stage2, dp_stage7, ...),
     the whole-step kernel with its shape (rk4_step_8x6: 8 waves x 6 rows; the
-    streaming form rk4_step_1x40: bands of 40 rows), or a shortened name for other
-    kernels."""
+    streaming form rk4_step_1x40: bands of 40 rows; the wide streaming form
+    rk4_step_wide8 / rk4_step_wide12 by its input ring, whatever its band height),
+    or a shortened name for other kernels."""
     m = re.search(r"(rk4_stage_kernel|dp_stage_kernel)<[^>]*?(\d+)>", name)
     if m:
         return ("rk4_stage" if m.group(1).startswith("rk4") else "dp_stage") + m.group(2)
+    m = re.search(r"rk4_stream_wide_kernel<[^>]*?, (\d+), \d+, \d+>", name)
+    if m:  # wide streaming form: named by its input ring (8: shapes 2 x B, 12: shapes 3 x B)
+        return f"rk4_step_wide{m.group(1)}"
     m = re.search(r"rk4_step_kernel<[^>]*?(\d+), (\d+)>", name)
     if m:
         return f"rk4_step_{m.group(1)}x{m.group(2)}"
