@@ -10,7 +10,8 @@ with the GPU path.
 
 Layouts: activations are [batch, channels, H, W]; weights are
 [c_out, c_in, 3, 3]; biases [c_out].  Each function states what it computes in
-plain loops or a direct sum over the nine taps.
+plain loops or a direct sum over the nine taps (the channel contractions of each
+tap go through numpy's einsum with BLAS, in double precision).
 
 Parity: conv3x3 / its backward are pinned by a pure-Python loop on tiny inputs,
 by central finite differences of the loss, by the delta-input identity and by
@@ -37,7 +38,7 @@ def conv3x3(x: np.ndarray, w: np.ndarray, b: np.ndarray) -> np.ndarray:
     y = np.zeros((x.shape[0], w.shape[0], x.shape[2], x.shape[3]))
     for dy, dx in TAPS:
         xs = np.roll(x, shift=(-dy, -dx), axis=(2, 3))  # xs[..., i, j] = x[..., i+dy, j+dx]
-        y += np.einsum("oc,ncij->noij", w[:, :, dy + 1, dx + 1], xs)
+        y += np.einsum("oc,ncij->noij", w[:, :, dy + 1, dx + 1], xs, optimize=True)
     return y + np.asarray(b, np.float64)[None, :, None, None]
 
 
@@ -50,9 +51,10 @@ def conv3x3_backward(x, w, dy_out):
     dw = np.zeros_like(w)
     for dy, dxx in TAPS:
         xs = np.roll(x, shift=(-dy, -dxx), axis=(2, 3))
-        dw[:, :, dy + 1, dxx + 1] = np.einsum("noij,ncij->oc", g, xs)
+        dw[:, :, dy + 1, dxx + 1] = np.einsum("noij,ncij->oc", g, xs, optimize=True)
         # y[i] uses x[i+dy]: the gradient flows back to x[i+dy] = shift g by +dy
-        dx += np.roll(np.einsum("oc,noij->ncij", w[:, :, dy + 1, dxx + 1], g), shift=(dy, dxx), axis=(2, 3))
+        dx += np.roll(np.einsum("oc,noij->ncij", w[:, :, dy + 1, dxx + 1], g, optimize=True), shift=(dy, dxx),
+                      axis=(2, 3))
     db = g.sum(axis=(0, 2, 3))
     return dx, dw, db
 

@@ -77,6 +77,34 @@ def test_gradients_parity():
     net.close()
 
 
+def test_forward_and_gradients_parity_256_batch16():
+    """The workload's size: 16 images of 256 x 256, so that the persistent forward and
+    weight-gradient kernels walk many tiles per workgroup and sum partials from many
+    workgroups.  Forward output, loss and every layer's weight and bias gradient
+    against the reference on the same bfloat16-rounded inputs and weights."""
+    import torch
+    net, x, t, xd, td = make(16, H=256, W=256, seed=21)
+    layers = [(conv_ref.to_bf16(w), b) for w, b in net.get_weights()]
+    y = net.forward(xd).cpu().numpy()
+    xr = x.transpose(0, 3, 1, 2)
+    ref = ref_forward_bf16(layers, xr).transpose(0, 2, 3, 1)
+    e = rel_l2(y, ref)
+    print(f"256^2 x 16 forward rel L2 {e:.2e}")
+    assert e < 1e-2
+    assert np.max(np.abs(y - ref)) < 2.0 ** -6 * np.max(np.abs(ref))
+    g = net.gradients(xd, td)
+    torch.cuda.synchronize()
+    got = net.unpack(g.cpu().numpy())
+    loss_ref, grads_ref = conv_ref.loss_and_grads(layers, conv_ref.to_bf16(xr), t.transpose(0, 3, 1, 2))
+    assert abs(net.loss.item() - loss_ref) < 1e-2 * loss_ref
+    for l in range(4):
+        ew = rel_l2(got[l][0], grads_ref[l][0])
+        eb = rel_l2(got[l][1], grads_ref[l][1])
+        print(f"256^2 x 16 layer {l}: dW rel L2 {ew:.2e}, db rel L2 {eb:.2e}")
+        assert ew < 3e-2 and eb < 3e-2
+    net.close()
+
+
 def test_adam_parity():
     net, x, t, xd, td = make(2, seed=5)
     import torch
