@@ -14,13 +14,15 @@
 #include "philox.h"
 #include "runtime.h"
 #include "step_body.h"
+#include "stream_body.h"
 
 namespace phx {
 
 template <typename R>
 struct BatchInst {
     int nx, ny, bcx, bcy;
-    int tiles_x, tile0;  // regions across x; first work item of this instance
+    int tiles_x, tile0;  // regions across x; first work item of this instance (region form)
+    int s_tile0;         // first work item of this instance in the streaming form
     int64_t offset;      // element offset in the packed arrays
     Coef<R> c;
     R half_dt, dt, dt6;
@@ -92,6 +94,81 @@ __global__ __launch_bounds__(WAVES * 64) void batch_step_kernel(
 
 // region shape of the batched kernel per precision (8 waves x 4 rows)
 constexpr int BW = 8, BR = 4;
+
+// Streaming form of the batched step (the band walk of stream_body.h): a work item is
+// one band of SB rows of a group of 4 adjacent strips of one instance, one workgroup
+// per item (consecutive items on one XCD); tiles_x counts an instance's strips of 56
+// columns.  YZERO: every instance has a zero y boundary (else every one is periodic
+// in y).  `zeros` is 32 zero bytes that ghost cells read.
+constexpr int SB = 40;
+
+template <typename R, bool RES, bool HASV, bool GHOSTS, bool YZERO>
+__global__ __launch_bounds__(256) void batch_stream_kernel(
+    const BatchInst<R>* __restrict__ inst, int count, const typename cvec<R>::type* psi_in, const R* n_in,
+    typename cvec<R>::type* psi_out, R* n_out, const R* V, const R* P, unsigned int* flag, const double* zeros)
+{
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int t = xcd_tile(blockIdx.x, gridDim.x);
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (inst[mid].s_tile0 <= t) lo = mid; else hi = mid - 1;
+    }
+    const BatchInst<R>& I = inst[lo];
+    const int lt = t - I.s_tile0;
+    const int gx = (I.tiles_x + 3) / 4;
+    const int band = lt / gx, strip = (lt - band * gx) * 4 + wave;
+    if (strip >= I.tiles_x) return;
+    StepArgs<R> a{};
+    a.nx = I.nx;
+    a.ny = I.ny;
+    a.bcx = I.bcx;
+    a.bcy = I.bcy;
+    a.tiles_x = I.tiles_x;
+    a.c = I.c;
+    a.half_dt = I.half_dt;
+    a.dt = I.dt;
+    a.dt6 = I.dt6;
+    a.psi_in = psi_in + I.offset;
+    a.n_in = RES ? n_in + I.offset : nullptr;
+    a.psi_out = psi_out + I.offset;
+    a.n_out = RES ? n_out + I.offset : nullptr;
+    a.V = HASV ? V + I.offset : nullptr;
+    a.P = RES ? P + I.offset : nullptr;
+    a.comps = 1;
+    a.zeros = zeros;
+    if (stream_band<R, RES, HASV, GHOSTS, YZERO, SB>(a, strip, band, (band & 1) ? -1 : 1))
+        flag[0] = 1u;  // benign race: every writer stores 1
+}
+
+template <typename R, bool RES, bool HASV, bool GHOSTS, bool YZERO>
+static hipError_t launch_batch_stream_t(int total, const BatchInst<R>* inst, int count, const void* pi,
+                                        const void* ni, void* po, void* no, const void* V, const void* P,
+                                        unsigned int* flag, const double* zeros, hipStream_t s)
+{
+    using C = typename cvec<R>::type;
+    batch_stream_kernel<R, RES, HASV, GHOSTS, YZERO><<<total, 256, 0, s>>>(
+        inst, count, (const C*)pi, (const R*)ni, (C*)po, (R*)no, (const R*)V, (const R*)P, flag, zeros);
+    return hipGetLastError();
+}
+
+template <typename R>
+static hipError_t launch_batch_stream(bool res, bool hv, bool ghosts, bool yzero, int total, const BatchInst<R>* inst,
+                                      int count, const void* pi, const void* ni, void* po, void* no, const void* V,
+                                      const void* P, unsigned int* flag, const double* zeros, hipStream_t s)
+{
+#define PHX_BS(RS, HV, G, Y) \
+    if (res == RS && hv == HV && ghosts == G && yzero == Y) \
+        return launch_batch_stream_t<R, RS, HV, G, Y>(total, inst, count, pi, ni, po, no, V, P, flag, zeros, s)
+    PHX_BS(true, false, false, false); PHX_BS(true, true, false, false);
+    PHX_BS(false, false, false, false); PHX_BS(false, true, false, false);
+    PHX_BS(true, false, true, false); PHX_BS(true, true, true, false);
+    PHX_BS(false, false, true, false); PHX_BS(false, true, true, false);
+    PHX_BS(true, false, true, true); PHX_BS(true, true, true, true);
+    PHX_BS(false, false, true, true); PHX_BS(false, true, true, true);
+#undef PHX_BS
+    return hipErrorInvalidValue;
+}
 
 template <typename R, bool RES, bool HASV, bool GHOSTS>
 static hipError_t launch_batch_t(int grid, const BatchInst<R>* inst, int count, int total, const void* pi,
@@ -209,8 +286,12 @@ static phx_status batch_run(const phx_batch_desc* d, int64_t n, hipStream_t stre
     const int res = d->params[0].reservoir;
     std::vector<BatchInst<R>> table(d->count);
     int tile0 = 0;
+    int64_t s_tile0 = 0;
     std::vector<int> block_inst;
     bool ghosts = false, noisy = false;
+    // the streaming form needs every instance's state under 2 GiB (32-bit buffer
+    // offsets) and one y boundary rule for all instances
+    bool use_stream = true, all_zero_y = true, all_periodic_y = true;
     for (int k = 0; k < d->count; ++k) {
         const phx_instance& I = d->instances[k];
         phx_config c = d->params[I.param_index];
@@ -229,6 +310,11 @@ static phx_status batch_run(const phx_batch_desc* d, int64_t n, hipStream_t stre
         b.dt = (R)c.dt;
         b.dt6 = (R)(c.dt / 6.0);
         tile0 += b.tiles_x * ((I.ny + BW * BR - 9) / (BW * BR - 8));
+        b.s_tile0 = (int)std::min<int64_t>(s_tile0, INT32_MAX);
+        s_tile0 += (int64_t)((b.tiles_x + 3) / 4) * ((I.ny + SB - 1) / SB);
+        use_stream = use_stream && (double)I.nx * I.ny * 2.0 * sizeof(R) < 2147483648.0 - 256.0;
+        all_zero_y = all_zero_y && c.bc_y == PHX_BC_ZERO;
+        all_periodic_y = all_periodic_y && c.bc_y == PHX_BC_PERIODIC;
         ghosts = ghosts || c.bc_x == PHX_BC_ZERO || c.bc_y == PHX_BC_ZERO;
         const double scale = c.noise * c.dt / (4.0 * c.dx * c.dy);  // as the single-grid pass forms it
         b.noise_a = (R)(scale * c.R);
@@ -241,6 +327,8 @@ static phx_status batch_run(const phx_batch_desc* d, int64_t n, hipStream_t stre
         noisy = noisy || c.noise > 0.0;
     }
     const int total = tile0;
+    use_stream = use_stream && (all_zero_y || all_periodic_y) && s_tile0 < INT32_MAX;
+    const int s_total = (int)std::min<int64_t>(s_tile0, INT32_MAX);
     hipError_t e = hipMemcpyAsync(ws + L.table, table.data(), table.size() * sizeof(BatchInst<R>),
                                   hipMemcpyHostToDevice, stream);
     if (e == hipSuccess && noisy)
@@ -277,9 +365,14 @@ static phx_status batch_run(const phx_batch_desc* d, int64_t n, hipStream_t stre
     }
     const BatchInst<R>* dtab = (const BatchInst<R>*)(ws + L.table);
     unsigned int* flag = (unsigned int*)(ws + L.flag);
+    const double* zeros = (const double*)(ws + L.flag + 64);  // zeroed with the flag block
     for (int64_t k = 0; k < n; ++k) {
-        e = launch_batch<R>(res != 0, d->V != nullptr, ghosts, grid, dtab, d->count, total, S[cur], SN[cur],
-                            S[cur ^ 1], SN[cur ^ 1], d->V, d->P, flag, stream);
+        if (use_stream)
+            e = launch_batch_stream<R>(res != 0, d->V != nullptr, ghosts, all_zero_y, s_total, dtab, d->count,
+                                       S[cur], SN[cur], S[cur ^ 1], SN[cur ^ 1], d->V, d->P, flag, zeros, stream);
+        else
+            e = launch_batch<R>(res != 0, d->V != nullptr, ghosts, grid, dtab, d->count, total, S[cur], SN[cur],
+                                S[cur ^ 1], SN[cur ^ 1], d->V, d->P, flag, stream);
         if (e != hipSuccess) return fail(PHX_EHIP, "batch step launch: %s", hipGetErrorString(e));
         cur ^= 1;
         if (noisy) {

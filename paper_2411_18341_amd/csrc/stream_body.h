@@ -94,6 +94,32 @@ __device__ __forceinline__ void buf_store_nt(double2 v, __amdgpu_buffer_rsrc_t r
                                            r, off, 0, kNonTemporal);
 }
 
+// Raw buffer loads of one element (an offset past the buffer's size reads 0).
+template <typename T>
+__device__ __forceinline__ T buf_load(__amdgpu_buffer_rsrc_t r, int voff, int soff);
+template <>
+__device__ __forceinline__ float buf_load<float>(__amdgpu_buffer_rsrc_t r, int voff, int soff)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+template <>
+__device__ __forceinline__ double buf_load<double>(__amdgpu_buffer_rsrc_t r, int voff, int soff)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+template <>
+__device__ __forceinline__ float2 buf_load<float2>(__amdgpu_buffer_rsrc_t r, int voff, int soff)
+{
+    // reinterpret the loaded bits as the whole vector (a bit cast of one element of an
+    // extended vector has been compiled into a copy of its first element)
+    return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+template <>
+__device__ __forceinline__ double2 buf_load<double2>(__amdgpu_buffer_rsrc_t r, int voff, int soff)
+{
+    return __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+}
+
 // YZERO: the y boundary is zero (ghost rows); else periodic in y.  dir = +1 walks the
 // band downwards (rows b0-4 .. b0+B+3), dir = -1 upwards (rows b0+B+3 .. b0-4): odd
 // bands walk up, so that neighbouring bands reach the 8 rows they both read at the same

@@ -79,11 +79,18 @@ __device__ __forceinline__ bool stream_band_spinor(const StepArgs<R>& a, int str
     const size_t cells = (size_t)a.nx * a.ny;
     const __amdgpu_buffer_rsrc_t rpo = buffer_of(a.psi_out, 2 * cells * sizeof(C));
     const __amdgpu_buffer_rsrc_t rno = buffer_of(a.n_out, RES ? 2 * cells * sizeof(R) : 0);
+    // inputs through buffer loads: the lane's column offset in a VGPR (past the buffer
+    // for a ghost column, which then reads 0), the row and component offsets in
+    // scalars; a ghost row (zero y boundary) reads through a descriptor of size 0
+    const __amdgpu_buffer_rsrc_t rpi = buffer_of(a.psi_in, 2 * cells * sizeof(C));
+    const __amdgpu_buffer_rsrc_t rni = buffer_of(a.n_in, RES ? 2 * cells * sizeof(R) : 0);
+    const __amdgpu_buffer_rsrc_t rP = buffer_of(a.P, RES ? 2 * cells * sizeof(R) : 0);
+    const __amdgpu_buffer_rsrc_t rV = buffer_of(a.V, HASV ? cells * sizeof(R) : 0);
+    const __amdgpu_buffer_rsrc_t rnull = buffer_of(a.psi_in, 0);
 
     C sp[2][8];
     R sk[8];
     R sn[2][8], sP[2][8];
-    R rowk[8];  // 0 for ghost rows (zero y boundary), else 1
     C acc[2][4];
     R accn[2][4];
     C w2[2][3], w3[2][3], w4[2][3];
@@ -93,7 +100,6 @@ __device__ __forceinline__ bool stream_band_spinor(const StepArgs<R>& a, int str
         sp[0][s] = sp[1][s] = czero<C>();
         sn[0][s] = sn[1][s] = sP[0][s] = sP[1][s] = R(0);
         sk[s] = kdiag;
-        rowk[s] = R(1);
     }
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
@@ -113,25 +119,26 @@ __device__ __forceinline__ bool stream_band_spinor(const StepArgs<R>& a, int str
     int g = start;
     int rw = wrap_any(g, a.ny, a.bcy);
     const int ci0 = ci < 0 ? 0 : ci;
+    const int vc = gcol ? kOutOfRange : ci0 * (int)sizeof(C);
+    const int vr = gcol ? kOutOfRange : ci0 * (int)sizeof(R);
+    const int comp_c = (int)(cells * sizeof(C)), comp_r = (int)(cells * sizeof(R));
+    const int row_c = a.nx * (int)sizeof(C), row_r = a.nx * (int)sizeof(R);
     auto fetch = [&](int s, bool use) {
-        const bool gh = GHOSTS && (gcol || rw < 0);
-        const int idx = gh ? 0 : rw * a.nx + ci0;
-        // ghost cells read a block of zeros instead of the arrays
-        const C* z = (const C*)a.zeros;
-        sp[0][s] = *(gh ? z : a.psi_in + idx);
-        sp[1][s] = *(gh ? z : a.psi_in + cells + idx);
+        const bool grow = YZERO && rw < 0;  // uniform
+        const int rr = grow ? 0 : rw;
+        sp[0][s] = buf_load<C>(grow ? rnull : rpi, vc, rr * row_c);
+        sp[1][s] = buf_load<C>(grow ? rnull : rpi, vc, comp_c + rr * row_c);
         if (RES) {
 #pragma unroll
             for (int m = 0; m < 2; ++m) {
-                sn[m][s] = *(gh ? (const R*)a.zeros : a.n_in + m * cells + idx);
-                sP[m][s] = *(gh ? (const R*)a.zeros : a.P + m * cells + idx);
+                sn[m][s] = buf_load<R>(grow ? rnull : rni, vr, m * comp_r + rr * row_r);
+                sP[m][s] = buf_load<R>(grow ? rnull : rP, vr, m * comp_r + rr * row_r);
             }
         }
         if (HASV) {
-            const R vv = *(gh ? (const R*)a.zeros : a.V + idx);
+            const R vv = buf_load<R>(grow ? rnull : rV, vr, rr * row_r);
             sk[s] = fma(c.inv_hbar, vv, kdiag);
         }
-        if (YZERO) rowk[s] = rw < 0 ? R(0) : R(1);
         const int gn = g + dir;
         int rn;
         if (YZERO) {
@@ -145,6 +152,9 @@ __device__ __forceinline__ bool stream_band_spinor(const StepArgs<R>& a, int str
     };
 #pragma unroll
     for (int t = 0; t < PF; ++t) fetch(t, true);
+
+    // 0 for a ghost row (zero y boundary), else 1: the row is uniform over the wave
+    auto row_keep = [&](int r) { return (YZERO && (unsigned)r >= (unsigned)a.ny) ? R(0) : R(1); };
 
     // neighbour sums and y-differences of one stage argument (rows above, at, below
     // in walking order) for both components
@@ -179,7 +189,7 @@ __device__ __forceinline__ bool stream_band_spinor(const StepArgs<R>& a, int str
                     pv[m] = sP[m][s0];
                 }
                 spinor_rhs<R, RES>(c, cur, lr, ud, dy, sk[s0], rdir, nn, pv, f, fn);
-                const R kk = YZERO ? keep * rowk[s0] : keep;
+                const R kk = YZERO ? keep * row_keep(j - 1 * dir) : keep;
 #pragma unroll
                 for (int m = 0; m < 2; ++m) {
                     acc[m][slot<4>(u, 1)] = f[m];
@@ -203,7 +213,7 @@ __device__ __forceinline__ bool stream_band_spinor(const StepArgs<R>& a, int str
                     pv[m] = sP[m][s0];
                 }
                 spinor_rhs<R, RES>(c, cur, lr, ud, dy, sk[s0], rdir, nn, pv, f, fn);
-                const R kk = YZERO ? keep * rowk[s0] : keep;
+                const R kk = YZERO ? keep * row_keep(j - 2 * dir) : keep;
 #pragma unroll
                 for (int m = 0; m < 2; ++m) {
                     C& ac = acc[m][slot<4>(u, 2)];
@@ -229,7 +239,7 @@ __device__ __forceinline__ bool stream_band_spinor(const StepArgs<R>& a, int str
                     pv[m] = sP[m][s0];
                 }
                 spinor_rhs<R, RES>(c, cur, lr, ud, dy, sk[s0], rdir, nn, pv, f, fn);
-                const R kk = YZERO ? keep * rowk[s0] : keep;
+                const R kk = YZERO ? keep * row_keep(j - 3 * dir) : keep;
 #pragma unroll
                 for (int m = 0; m < 2; ++m) {
                     C& ac = acc[m][slot<4>(u, 3)];

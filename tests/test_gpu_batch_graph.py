@@ -94,6 +94,33 @@ def test_batch_vs_oracle(precision):
         assert rel_l2(got_psi, o_psi[0]) <= TOL[precision] and rel_l2(got_n, o_n[0]) <= TOL[precision]
 
 
+@pytest.mark.parametrize("bcs", [[(0, 1), (1, 1), (0, 1)], [(0, 1), (1, 0), (0, 0)]])
+def test_batch_boundary_mixes_vs_oracle(bcs):
+    """Per-instance boundary rules: every instance with a zero y boundary (the
+    streaming batched kernel's zero-y form) and a mix of y rules (the region form):
+    each instance against the oracle with its own rules."""
+    grids = [(70, 50), (128, 96), (41, 140)]
+    params, states, phs = [], [], []
+    for k, ((nx, ny), bc) in enumerate(zip(grids, bcs)):
+        ph, psi, n0, V, P = driven_small(nx, ny, 40 + k, bc)
+        params.append(phx.config_from_physics(ph, precision=C64))
+        states.append(quantize(C64, psi, n0, None, P))
+        phs.append(ph)
+    b = phx.Batch(grids, params, list(range(len(grids))), precision=C64)
+    import torch
+    for k, (psi, n0, _, P) in enumerate(states):
+        b.view(b.psi, k).copy_(torch.from_numpy(psi[0]).to(torch.complex64))
+        b.view(b.n, k).copy_(torch.from_numpy(n0[0]).to(torch.float32))
+        b.view(b.P, k).copy_(torch.from_numpy(P[0]).to(torch.float32))
+    b.step(9)
+    torch.cuda.synchronize()
+    for k, ph in enumerate(phs):
+        o_psi, o_n = oracle.rk4(oracle_physics(ph), *states[k], dt=ph.dt, steps=9)
+        got_psi = b.view(b.psi, k).cpu().numpy().astype(np.complex128)
+        got_n = b.view(b.n, k).cpu().numpy().astype(np.float64)
+        assert rel_l2(got_psi, o_psi[0]) <= TOL[C64] and rel_l2(got_n, o_n[0]) <= TOL[C64], (k, bcs[k])
+
+
 def test_batch_sweep_full_size():
     """The batched sweep workload: 256 instances on square grids drawn
     log-uniformly in [128, 1024], pump p P_th with p ~ U(0.5, 3), Gaussian spot of
