@@ -99,13 +99,13 @@ constexpr int BW = 8, BR = 4;
 // one band of SB rows of a group of 4 adjacent strips of one instance, one workgroup
 // per item (consecutive items on one XCD); tiles_x counts an instance's strips of 56
 // columns.  YZERO: every instance has a zero y boundary (else every one is periodic
-// in y).  `zeros` is 32 zero bytes that ghost cells read.
+// in y).
 constexpr int SB = 40;
 
 template <typename R, bool RES, bool HASV, bool GHOSTS, bool YZERO>
 __global__ __launch_bounds__(256) void batch_stream_kernel(
     const BatchInst<R>* __restrict__ inst, int count, const typename cvec<R>::type* psi_in, const R* n_in,
-    typename cvec<R>::type* psi_out, R* n_out, const R* V, const R* P, unsigned int* flag, const double* zeros)
+    typename cvec<R>::type* psi_out, R* n_out, const R* V, const R* P, unsigned int* flag)
 {
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int t = xcd_tile(blockIdx.x, gridDim.x);
@@ -136,7 +136,6 @@ __global__ __launch_bounds__(256) void batch_stream_kernel(
     a.V = HASV ? V + I.offset : nullptr;
     a.P = RES ? P + I.offset : nullptr;
     a.comps = 1;
-    a.zeros = zeros;
     if (stream_band<R, RES, HASV, GHOSTS, YZERO, SB>(a, strip, band, (band & 1) ? -1 : 1))
         flag[0] = 1u;  // benign race: every writer stores 1
 }
@@ -144,22 +143,22 @@ __global__ __launch_bounds__(256) void batch_stream_kernel(
 template <typename R, bool RES, bool HASV, bool GHOSTS, bool YZERO>
 static hipError_t launch_batch_stream_t(int total, const BatchInst<R>* inst, int count, const void* pi,
                                         const void* ni, void* po, void* no, const void* V, const void* P,
-                                        unsigned int* flag, const double* zeros, hipStream_t s)
+                                        unsigned int* flag, hipStream_t s)
 {
     using C = typename cvec<R>::type;
     batch_stream_kernel<R, RES, HASV, GHOSTS, YZERO><<<total, 256, 0, s>>>(
-        inst, count, (const C*)pi, (const R*)ni, (C*)po, (R*)no, (const R*)V, (const R*)P, flag, zeros);
+        inst, count, (const C*)pi, (const R*)ni, (C*)po, (R*)no, (const R*)V, (const R*)P, flag);
     return hipGetLastError();
 }
 
 template <typename R>
 static hipError_t launch_batch_stream(bool res, bool hv, bool ghosts, bool yzero, int total, const BatchInst<R>* inst,
                                       int count, const void* pi, const void* ni, void* po, void* no, const void* V,
-                                      const void* P, unsigned int* flag, const double* zeros, hipStream_t s)
+                                      const void* P, unsigned int* flag, hipStream_t s)
 {
 #define PHX_BS(RS, HV, G, Y) \
     if (res == RS && hv == HV && ghosts == G && yzero == Y) \
-        return launch_batch_stream_t<R, RS, HV, G, Y>(total, inst, count, pi, ni, po, no, V, P, flag, zeros, s)
+        return launch_batch_stream_t<R, RS, HV, G, Y>(total, inst, count, pi, ni, po, no, V, P, flag, s)
     PHX_BS(true, false, false, false); PHX_BS(true, true, false, false);
     PHX_BS(false, false, false, false); PHX_BS(false, true, false, false);
     PHX_BS(true, false, true, false); PHX_BS(true, true, true, false);
@@ -365,11 +364,10 @@ static phx_status batch_run(const phx_batch_desc* d, int64_t n, hipStream_t stre
     }
     const BatchInst<R>* dtab = (const BatchInst<R>*)(ws + L.table);
     unsigned int* flag = (unsigned int*)(ws + L.flag);
-    const double* zeros = (const double*)(ws + L.flag + 64);  // zeroed with the flag block
     for (int64_t k = 0; k < n; ++k) {
         if (use_stream)
             e = launch_batch_stream<R>(res != 0, d->V != nullptr, ghosts, all_zero_y, s_total, dtab, d->count,
-                                       S[cur], SN[cur], S[cur ^ 1], SN[cur ^ 1], d->V, d->P, flag, zeros, stream);
+                                       S[cur], SN[cur], S[cur ^ 1], SN[cur ^ 1], d->V, d->P, flag, stream);
         else
             e = launch_batch<R>(res != 0, d->V != nullptr, ghosts, grid, dtab, d->count, total, S[cur], SN[cur],
                                 S[cur ^ 1], SN[cur ^ 1], d->V, d->P, flag, stream);

@@ -189,7 +189,6 @@ static StepArgs<R> step_args(const phx_handle* h, const StepShapeId& sh, const v
     a.psi_out = (C*)dst;
     a.n_out = (R*)dst_n;
     a.comps = c.components;
-    a.zeros = (const double*)(h->ws + h->L.zeros);
     if (c.imag_time) {
         a.imag_slots = (const double*)(h->ws + h->L.imag);
         a.imag_partials = (double*)(h->ws + h->L.imag_partials);

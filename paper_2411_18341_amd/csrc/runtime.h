@@ -38,7 +38,6 @@ struct Layout {
     size_t drive_ph;    // RK4 with drive: the four stage phasors of the current step
     size_t imag;        // imaginary time: [0] target norm of the call, [1] restoring scale
     size_t imag_partials;  // imaginary time: per-workgroup norm partials
-    size_t zeros;       // 256 zero bytes (ghost cells of the streaming kernels read them)
     int family;         // PHX_KERNEL_STAGE or PHX_KERNEL_STEP for RK4
     size_t err;         // Dormand-Prince error partials
     int obs_blocks;

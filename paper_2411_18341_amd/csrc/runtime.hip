@@ -124,7 +124,6 @@ Layout make_layout(const phx_config& c)
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o = off; off += align_up(bytes); return o; };
     L.flag = take(256);
-    L.zeros = take(256);
     L.obs = take(OBS_SLOTS * sizeof(double));
     const bool stage_tiles = c.integrator == PHX_RK4 && rk4_family(c) == PHX_KERNEL_STAGE;
     L.tiles = plan_tiles(c.nx, c.ny, stage_tiles ? c.tile_wx : 0, stage_tiles ? c.tile_rows : 0);
@@ -340,7 +339,6 @@ phx_status phx_create(const phx_config* cfg, const phx_fields* f, void* stream,
             h->cus = 256;
     }
     if (e == hipSuccess) e = hipMemsetAsync(h->ws + L.flag, 0, 256, h->stream);
-    if (e == hipSuccess) e = hipMemsetAsync(h->ws + L.zeros, 0, 256, h->stream);
     if (e == hipSuccess && uses_step_index(*cfg)) e = set_noise_step(h, 0, h->stream);
     if (e == hipSuccess && cfg->drive && cfg->integrator == PHX_RK4)  // valid phasors before any launch
         e = cfg->precision == PHX_C64 ? launch_drive_phasors<float>(h, 0, h->stream)

@@ -43,7 +43,6 @@ struct StepArgs {
     const C* E;
     const C* drive_ph;
     int comps;  // 2: the spinor streaming kernel (component stride nx*ny)
-    const double* zeros;  // streaming form: 32 zero bytes that ghost cells read
     int band_rows;        // wide streaming form: rows per band (a launch argument)
     int check;            // wide streaming form: test the stored values for non-finite ones
 };

@@ -143,9 +143,6 @@ __device__ __forceinline__ bool stream_band(const StepArgs<R>& a, int strip, int
     const int ci = wrap_any(gi, a.nx, a.bcx);
     const bool gcol = GHOSTS && ci < 0;
     const R keep = gcol ? R(0) : R(1);  // ghost columns stay 0 in every stage
-    R rowk[8];                           // 0 for ghost rows (zero y boundary), else 1
-#pragma unroll
-    for (int s = 0; s < 8; ++s) rowk[s] = R(1);
     const int b0 = band * B;
     const R kdiag = R(2) * (c.ax + c.ay);
     const size_t cells = (size_t)a.nx * a.ny;
@@ -170,10 +167,18 @@ __device__ __forceinline__ bool stream_band(const StepArgs<R>& a, int strip, int
         fy = fma(-c.inv_hbar, zx, fy);
     };
 
-    // 8-row ring of inputs.  Zero boundaries: ghost cells load from a block of zeros
-    // (a.zeros), and every stage argument is multiplied by keep (0 in ghost columns)
-    // and by the row factor of its ring slot (0 in ghost rows), which leaves the other
-    // cells' values unchanged.
+    // 8-row ring of inputs, read through buffer loads: the lane's column offset in a
+    // VGPR, the row offset in a scalar.  Zero boundaries: a ghost column's offset lies
+    // past the buffer and a ghost row reads through a descriptor of size 0, so both
+    // read 0; every stage argument is multiplied by keep (0 in ghost columns) and by
+    // the factor of its row (0 in ghost rows), which leaves the other cells' values
+    // unchanged.
+    const __amdgpu_buffer_rsrc_t rpi = buffer_of(a.psi_in, cells * sizeof(C));
+    const __amdgpu_buffer_rsrc_t rni = buffer_of(a.n_in, RES ? cells * sizeof(R) : 0);
+    const __amdgpu_buffer_rsrc_t rP = buffer_of(a.P, RES ? cells * sizeof(R) : 0);
+    const __amdgpu_buffer_rsrc_t rV = buffer_of(a.V, HASV ? cells * sizeof(R) : 0);
+    const __amdgpu_buffer_rsrc_t rE = buffer_of(a.E, DRIVE ? cells * sizeof(C) : 0);
+    const __amdgpu_buffer_rsrc_t rnull = buffer_of(a.psi_in, 0);
     C sp[8];
     R sn[8], sP[8], sk[8];
     C acc[4];
@@ -205,29 +210,26 @@ __device__ __forceinline__ bool stream_band(const StepArgs<R>& a, int strip, int
     int g = start;
     int rw = wrap_any(g, a.ny, a.bcy);
     const int ci0 = ci < 0 ? 0 : ci;
+    const int vc = gcol ? kOutOfRange : ci0 * (int)sizeof(C);
+    const int vr = gcol ? kOutOfRange : ci0 * (int)sizeof(R);
+    const int row_c = a.nx * (int)sizeof(C), row_r = a.nx * (int)sizeof(R);
     auto fetch = [&](int s, bool use) {
-        const bool gh = GHOSTS && (gcol || rw < 0);
-        const int idx = gh ? 0 : rw * a.nx + ci0;
-        // ghost cells read a block of zeros instead of the arrays
-        const C* pp = gh ? (const C*)a.zeros : a.psi_in + idx;
-        const C v = *pp;
+        const bool grow = YZERO && rw < 0;  // uniform
+        const int rr = grow ? 0 : rw;
+        const C v = buf_load<C>(grow ? rnull : rpi, vc, rr * row_c);
         if constexpr (IMAG)
             sp[s] = C{v.x * sc, v.y * sc};
         else
             sp[s] = v;
         if (RES) {
-            sn[s] = *(gh ? (const R*)a.zeros : a.n_in + idx);
-            sP[s] = *(gh ? (const R*)a.zeros : a.P + idx);
+            sn[s] = buf_load<R>(grow ? rnull : rni, vr, rr * row_r);
+            sP[s] = buf_load<R>(grow ? rnull : rP, vr, rr * row_r);
         }
         if (HASV) {
-            const R vv = *(gh ? (const R*)a.zeros : a.V + idx);
+            const R vv = buf_load<R>(grow ? rnull : rV, vr, rr * row_r);
             sk[s] = fma(c.inv_hbar, vv, kdiag);
         }
-        if constexpr (DRIVE) {
-            const C ev = a.E[idx];
-            sE[s] = gh ? czero<C>() : ev;
-        }
-        if (YZERO) rowk[s] = rw < 0 ? R(0) : R(1);
+        if constexpr (DRIVE) sE[s] = buf_load<C>(grow ? rnull : rE, vc, rr * row_c);
         const int gn = g + dir;
         int rn;
         if (YZERO) {
@@ -241,6 +243,9 @@ __device__ __forceinline__ bool stream_band(const StepArgs<R>& a, int strip, int
     };
 #pragma unroll
     for (int t = 0; t < PF; ++t) fetch(t, true);
+
+    // 0 for a ghost row (zero y boundary), else 1: the row is uniform over the wave
+    auto row_keep = [&](int r) { return (YZERO && (unsigned)r >= (unsigned)a.ny) ? R(0) : R(1); };
 
     bool bad = false;
     const bool out_col = lane >= 4 && lane < 60 && gi < a.nx;
@@ -259,7 +264,7 @@ __device__ __forceinline__ bool stream_band(const StepArgs<R>& a, int strip, int
                 const R lry = lane_prev(cur.y) + lane_next(cur.y);
                 cell_rhs<R, RES, IMAG>(c, cur, lrx, lry, up.x + dn.x, up.y + dn.y, sn[s0], sP[s0], sk[s0], fx, fy, fn);
                 if constexpr (DRIVE) drive(fx, fy, sE[s0], ph[0]);
-                const R kk = YZERO ? keep * rowk[s0] : keep;
+                const R kk = YZERO ? keep * row_keep(j - 1 * dir) : keep;
                 acc[slot<4>(u, 1)] = C{fx, fy};
                 accn[slot<4>(u, 1)] = fn;
                 w2[slot<3>(u, 1)] = C{kk * fma(a.half_dt, fx, cur.x), kk * fma(a.half_dt, fy, cur.y)};
@@ -275,7 +280,7 @@ __device__ __forceinline__ bool stream_band(const StepArgs<R>& a, int strip, int
                 const R lry = lane_prev(cur.y) + lane_next(cur.y);
                 cell_rhs<R, RES, IMAG>(c, cur, lrx, lry, up.x + dn.x, up.y + dn.y, nn, sP[s0], sk[s0], fx, fy, fn);
                 if constexpr (DRIVE) drive(fx, fy, sE[s0], ph[1]);
-                const R kk = YZERO ? keep * rowk[s0] : keep;
+                const R kk = YZERO ? keep * row_keep(j - 2 * dir) : keep;
                 C& ac = acc[slot<4>(u, 2)];
                 ac = C{fma(R(2), fx, ac.x), fma(R(2), fy, ac.y)};
                 accn[slot<4>(u, 2)] = fma(R(2), fn, accn[slot<4>(u, 2)]);
@@ -293,7 +298,7 @@ __device__ __forceinline__ bool stream_band(const StepArgs<R>& a, int strip, int
                 const R lry = lane_prev(cur.y) + lane_next(cur.y);
                 cell_rhs<R, RES, IMAG>(c, cur, lrx, lry, up.x + dn.x, up.y + dn.y, nn, sP[s0], sk[s0], fx, fy, fn);
                 if constexpr (DRIVE) drive(fx, fy, sE[s0], ph[2]);
-                const R kk = YZERO ? keep * rowk[s0] : keep;
+                const R kk = YZERO ? keep * row_keep(j - 3 * dir) : keep;
                 C& ac = acc[slot<4>(u, 3)];
                 ac = C{fma(R(2), fx, ac.x), fma(R(2), fy, ac.y)};
                 accn[slot<4>(u, 3)] = fma(R(2), fn, accn[slot<4>(u, 3)]);

@@ -53,7 +53,7 @@ def kernel_kind(name: str) -> str:
     m = re.search(r"(rk4_stage_kernel|dp_stage_kernel)<[^>]*?(\d+)>", name)
     if m:
         return ("rk4_stage" if m.group(1).startswith("rk4") else "dp_stage") + m.group(2)
-    m = re.search(r"rk4_stream_wide_kernel<[^>]*?, (\d+), \d+, \d+>", name)
+    m = re.search(r"rk4_stream_wide_kernel<[^>]*?, (\d+), \d+, \d+(?:, (?:true|false))?>", name)
     if m:  # wide streaming form: named by its input ring (8: shapes 2 x B, 12: shapes 3 x B)
         return f"rk4_step_wide{m.group(1)}"
     m = re.search(r"rk4_step_kernel<[^>]*?(\d+), (\d+)>", name)
@@ -119,19 +119,22 @@ def traffic_summary(fetch_csv: str, write_csv: str, copy_bytes: float, workload:
     med = lambda v: sorted(v)[len(v) // 2]
     f_scale = copy_bytes / (1024.0 * med(copy_f))
     w_scale = copy_bytes / (1024.0 * med(copy_w))
-    kernels = {}
+    # dispatches of every instantiation of one kernel kind are pooled (the wide
+    # streaming kernel has a variant that also tests for non-finite values)
+    by_kind_f, by_kind_w = defaultdict(list), defaultdict(list)
     for k in sorted(set(fetch) | set(write)):
-        if "copy" in k:
+        if "copy" in k or not fetch.get(k) or not write.get(k):
             continue
-        fr = fetch.get(k, [])
-        wr = write.get(k, [])
-        if not fr or not wr:
-            continue
+        by_kind_f[kernel_kind(k)] += fetch[k]
+        by_kind_w[kernel_kind(k)] += write[k]
+    kernels = {}
+    for kind in sorted(by_kind_f):
+        fr, wr = by_kind_f[kind], by_kind_w[kind]
         rd = sum(fr) / len(fr) * 1024.0 * f_scale
         wb = sum(wr) / len(wr) * 1024.0 * w_scale
-        kernels[kernel_kind(k)] = {"read_bytes": rd, "write_bytes": wb, "bytes_per_launch": rd + wb,
-                                   "dispatches": len(fr), "fetch_kib_raw": sum(fr) / len(fr),
-                                   "write_kib_raw": sum(wr) / len(wr)}
+        kernels[kind] = {"read_bytes": rd, "write_bytes": wb, "bytes_per_launch": rd + wb,
+                         "dispatches": len(fr), "fetch_kib_raw": sum(fr) / len(fr),
+                         "write_kib_raw": sum(wr) / len(wr)}
     return {"workload": workload, "source_hash": kernel_source_hash(sources), "fetch_scale": f_scale,
             "write_scale": w_scale, "copy_bytes": copy_bytes, "kernels": kernels}
 

@@ -336,9 +336,9 @@ def test_profile_kernel_names():
         "void phx::rk4_step_kernel<float, true, false, false, 12, 6>(phx::StepArgs<float>)": "rk4_step_12x6",
         "void phx::rk4_stage_kernel<float, 1, true, false, 3>(phx::Rk4Args<float>)": "rk4_stage3",
         "void (anonymous namespace)::wiener_noise_kernel<float, true>(float2*, float const*)": "wiener_noise",
-        "void phx::rk4_stream_wide_kernel<true, false, false, false, 8, 3, 3>(phx::StepArgs<float>)":
+        "void phx::rk4_stream_wide_kernel<true, false, false, false, 8, 3, 3, false>(phx::StepArgs<float>)":
             "rk4_step_wide8",
-        "void phx::rk4_stream_wide_kernel<false, true, true, true, 12, 6, 2>(phx::StepArgs<float>)":
+        "void phx::rk4_stream_wide_kernel<false, true, true, true, 12, 6, 2, true>(phx::StepArgs<float>)":
             "rk4_step_wide12",
     }
     for name, kind in cases.items():
