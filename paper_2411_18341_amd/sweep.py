@@ -5,11 +5,12 @@ For each side N the driven-dissipative workload (complex64 psi, float32 n, ring
 pump, RK4 dt 0.02, periodic) runs on one GPU with each RK4 kernel family:
   stage  four stage-fused launches per step (220 B/pt of algorithmic traffic)
   step   one whole-step launch per step (28 B/pt)
-after a tile-shape search for that size.  Reported per (N, family): grid-point
-updates per second, the algorithmic GB/s of the step, and the mean time of every
-kernel launched (HIP events on the solver's stream).  Small grids fit the 256 MB
-Infinity Cache and launch overhead dominates the smallest; large ones stream
-from HBM.
+after a tile-shape search for that size (--precisions c64 c128 adds complex128 psi
+with float64 n).  Reported per (N, family): grid-point updates per second from the
+wall clock with kernel timing off, the algorithmic GB/s of the step, and the mean
+time of every kernel launched (HIP events on the solver's stream, in a separate
+pass).  Small grids fit the 256 MB Infinity Cache and launch overhead dominates the
+smallest; large ones stream from HBM.
 
     python -m paper_2411_18341_amd.sweep --sizes 128 256 512 1024 2048 4096 8192 --out sweep.md
 
@@ -51,12 +52,15 @@ def measure(n: int, family: str, precision=phx.PHX_C64, warmup: int = 20, tune_r
         steps = steps_for(n)
         solver.step(warmup)
         torch.cuda.synchronize()
-        solver.set_timing(True)
-        torch.cuda.synchronize()
+        # wall clock with kernel timing off (graph replays as in production), then a
+        # separate pass with HIP events around every launch for the per-kernel times
         t0 = time.perf_counter()
         solver.step(steps)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
+        solver.set_timing(True)
+        solver.step(min(steps, 200))
+        torch.cuda.synchronize()
         times = solver.kernel_times()
     finally:
         solver.close()
@@ -65,7 +69,8 @@ def measure(n: int, family: str, precision=phx.PHX_C64, warmup: int = 20, tune_r
         real_bytes, reservoir=True, has_v=False)
     cells = n * n
     return {
-        "n": n, "family": family, "steps": steps, "tile": [tune["tile_wx"], tune["tile_rows"]],
+        "n": n, "family": family, "precision": "c64" if precision == phx.PHX_C64 else "c128",
+        "steps": steps, "tile": [tune["tile_wx"], tune["tile_rows"]],
         "UPs": cells * steps / wall, "us_per_step": wall / steps * 1e6,
         "algorithmic_GBps": model["step"] * cells * steps / wall / 1e9,
         "kernels_us": {k: v["ms_total"] / v["launches"] * 1e3 for k, v in times.items()},
@@ -304,11 +309,11 @@ def measure_ensemble(count: int = 128, n: int = 256, nu: float = 1.0, steps: int
 
 
 def table(rows) -> str:
-    out = ["| N | family | tile | steps | µs/step | G UP/s | algorithmic GB/s | mean launch µs per kernel |",
-           "|---|---|---|---|---|---|---|---|"]
+    out = ["| N | precision | family | tile | steps | µs/step | G UP/s | algorithmic GB/s | mean launch µs per kernel |",
+           "|---|---|---|---|---|---|---|---|---|"]
     for r in rows:
         ks = ", ".join(f"{k} {v:.2f}" for k, v in sorted(r["kernels_us"].items()))
-        out.append(f"| {r['n']} | {r['family']} | {r['tile'][0]}x{r['tile'][1]} | {r['steps']} | "
+        out.append(f"| {r['n']} | {r['precision']} | {r['family']} | {r['tile'][0]}x{r['tile'][1]} | {r['steps']} | "
                    f"{r['us_per_step']:.2f} | {r['UPs'] / 1e9:.2f} | {r['algorithmic_GBps']:.0f} | {ks} |")
     return "\n".join(out)
 
@@ -317,6 +322,7 @@ def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--sizes", type=int, nargs="*", default=[128, 256, 512, 1024, 2048, 4096, 8192])
     ap.add_argument("--families", nargs="+", default=["stage", "step"], choices=["stage", "step"])
+    ap.add_argument("--precisions", nargs="+", default=["c64"], choices=["c64", "c128"])
     ap.add_argument("--out", default=None, help="write the markdown table here")
     ap.add_argument("--batch", action="store_true", help="also measure the 256-instance batched workload")
     ap.add_argument("--spinor", action="store_true", help="also measure the 4096^2 spinor workload (RK4, RK45)")
@@ -363,11 +369,13 @@ def main():
             with open(args.out + ".batch.json", "w") as f:
                 json.dump(r, f, indent=1)
     rows = []
-    for n in args.sizes:
-        for fam in args.families:
-            r = measure(n, fam)
-            rows.append(r)
-            print(json.dumps(r), flush=True)
+    precs = {"c64": phx.PHX_C64, "c128": phx.PHX_C128}
+    for prec in args.precisions:
+        for n in args.sizes:
+            for fam in args.families:
+                r = measure(n, fam, precision=precs[prec])
+                rows.append(r)
+                print(json.dumps(r), flush=True)
     md = table(rows)
     print(md, flush=True)
     if args.out:

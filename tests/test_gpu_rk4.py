@@ -494,9 +494,13 @@ def test_spinor_reservoir_4096_sampled(rows):
     """The 4096^2 spinor workload with a reservoir and ring pump per component
     (inputs.spinor_driven, complex64) on the streaming whole-step kernel in both band
     heights: after 2 steps, sampled cells (corners, edges, the pump ring) of psi and n
-    against the oracle on patches of radius 8 cut at the grid's edges."""
+    against the oracle on patches of radius 8 cut at the grid's edges.  The start has
+    a populated reservoir (uniform in [0, 2 gamma_c / R]) and psi of unit amplitude, so
+    that the g_r n psi, R n psi and R n |psi|^2 couplings act from the first stage."""
     steps = 2
-    ph, psi0, n0, V, P = inputs.spinor_driven(4096)
+    ph, _, _, V, P = inputs.spinor_driven(4096)
+    psi0 = inputs.random_state((2, 4096, 4096), 31, 1.0)
+    n0 = inputs.random_field((2, 4096, 4096), 32, 0.0, 2.0 * ph.gamma_c / ph.R)
     q = quantize(C64, psi0, n0, V, P)
     run = GpuRun(ph, q[0], q[1], q[2], q[3], precision=C64, kernel=phx.PHX_KERNEL_STEP, tile_wx=1,
                  tile_rows=rows)
