@@ -55,6 +55,77 @@ def _scratch_kernels(stderr: str) -> list:
     return out
 
 
+# A store of more than 64 bits must not have its data registers rewritten by the very
+# next instruction: on gfx950 the store may still be reading them (the compiler keeps
+# a wait state only when the store's scalar offset is a constant).  The streaming
+# kernels put the whole offset of such stores in the VGPR operand; this finds any
+# store in the device assembly whose data a VALU instruction rewrites within
+# `min_gap` instructions of straight-line code.
+_WIDE_STORE = re.compile(r"^(buffer|global|flat)_store_dwordx(3|4)\s+(\S+)")
+_VREGS = re.compile(r"v\[(\d+):(\d+)\]|(?<![\w\[])v(\d+)\b")
+
+
+def _vregs(operand: str) -> set:
+    out = set()
+    for m in _VREGS.finditer(operand):
+        if m.group(3) is not None:
+            out.add(int(m.group(3)))
+        else:
+            out.update(range(int(m.group(1)), int(m.group(2)) + 1))
+    return out
+
+
+def store_data_hazards(asm: str, min_gap: int = 1) -> list:
+    """(function, store, writer) for each store of more than 64 bits followed, with fewer
+    than `min_gap` instructions in between, by a VALU write to one of its data VGPRs."""
+    found, func, body = [], None, []
+
+    def scan():
+        for i, inst in enumerate(body):
+            m = _WIDE_STORE.match(inst)
+            if not m:
+                continue
+            ops = [o.strip() for o in inst.split(None, 1)[1].split(",")]
+            data = _vregs(ops[0] if m.group(1) == "buffer" else ops[1])
+            for k, nxt in enumerate(body[i + 1:i + 1 + min_gap]):
+                if nxt == "<label>" or nxt.startswith(("s_branch", "s_cbranch", "s_setpc")):
+                    break
+                op = nxt.split(None, 1)
+                if (op[0].startswith("v_") and not op[0].startswith(("v_cmp", "v_readlane", "v_readfirstlane"))
+                        and len(op) > 1 and _vregs(op[1].split(",")[0]) & data):
+                    found.append((func, inst, nxt))
+                    break
+
+    for line in asm.splitlines():
+        s = line.strip()
+        head = re.match(r"^([A-Za-z_.$][\w.$]*):", s)
+        if head and not s.startswith("."):
+            scan()
+            func, body = head.group(1), []
+            continue
+        if head:  # a block label
+            body.append("<label>")
+            continue
+        if not s or s.startswith((";", ".")):
+            continue
+        body.append(s.split(";")[0].strip())
+    scan()
+    return found
+
+
+def device_asm(src: str) -> str:
+    """gfx950 assembly of one source of the library, compiled with the build's flags."""
+    out = os.path.join(BUILD_DIR, os.path.splitext(src)[0] + ".s")
+    os.makedirs(BUILD_DIR, exist_ok=True)
+    cmd = [hipcc(), *FLAGS, *EXTRA_FLAGS.get(src, []), "--cuda-device-only", "-S",
+           os.path.join(CSRC, src), "-o", out]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc -S failed on {src}:\n{r.stderr}")
+    with open(out) as f:
+        return f.read()
+
+
 def hipcc() -> str:
     path = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
     if not os.path.exists(path):

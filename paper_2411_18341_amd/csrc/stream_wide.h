@@ -44,9 +44,18 @@ __device__ __forceinline__ wf2 wload2(__amdgpu_buffer_rsrc_t r, int voff, int so
 {
     return __builtin_bit_cast(wf2, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
 }
+// The pair of complex values a lane stores per row: one 128-bit store whose whole
+// offset (column and row) is in the VGPR operand.  With the row offset in the scalar
+// operand instead, the compiler puts no wait state between the store and a following
+// VALU write to its data registers, and on gfx950 such a write can reach the data
+// while the store still reads it (the stored row then holds wrong values in the last
+// four lanes of some 16-lane rows); with a constant scalar offset it keeps the wait
+// state.  The sum is formed unsigned: a masked lane's offset (kOutOfRange) plus a row
+// offset below 2 GiB stays out of range and never wraps.
 __device__ __forceinline__ void wstore4(wf4 v, __amdgpu_buffer_rsrc_t r, int voff, int soff)
 {
-    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(wu4, v), r, voff, soff, kNonTemporal);
+    const int off = (int)((unsigned)voff + (unsigned)soff);
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(wu4, v), r, off, 0, kNonTemporal);
 }
 __device__ __forceinline__ void wstore2(wf2 v, __amdgpu_buffer_rsrc_t r, int voff, int soff)
 {

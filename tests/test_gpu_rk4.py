@@ -366,6 +366,35 @@ def test_wide_stream_kernel_edges(tile, shape, bc):
         assert e_psi <= TOL[C64] and e_n <= TOL[C64], (steps, e_psi, e_n)
 
 
+@pytest.mark.parametrize("tile", [(2, 0), (3, 0), (2, 40), (2, 64), (3, 64), (3, 88)])
+def test_wide_stream_kernel_long_walks_bitwise(tile):
+    """Wide streaming kernel with bands of 40 to 88 rows, i.e. walks of two to four
+    24-row chunks, on the 4096^2 driven grid with a populated reservoir and a pump on
+    every cell: after a run of 3 steps in one call (direct launches: the last step is
+    the one that tests for non-finite values) and after 8 steps as replays of 4-step
+    graphs, every cell of psi and n equals the one-column walk's bit for bit (the same
+    arithmetic in the same order).  The first row that each chunk of a walk stores is
+    covered here; the small-grid tests walk a single chunk."""
+    n = 4096
+    ph, psi0, _, P = inputs.driven(n)
+    n0 = inputs.random_field((1, n, n), 41, 0.0, 2.0 * ph.gamma_c / ph.R)
+    P = P + inputs.random_field((1, n, n), 42, 0.0, 0.5)
+    psi0 = psi0 + inputs.random_state((1, n, n), 43, 0.1)
+    q = quantize(C64, psi0, n0, None, P)
+    for graph_steps, steps in ((-1, 3), (4, 8)):
+        out = []
+        for wx, rows in ((1, 40), tile):
+            run = GpuRun(ph, q[0], q[1], None, q[3], precision=C64, kernel=phx.PHX_KERNEL_STEP,
+                         tile_wx=wx, tile_rows=rows, graph_steps=graph_steps)
+            run.step(steps)
+            out.append(run.state())
+            run.close()
+        bad_psi = int(np.sum(out[0][0] != out[1][0]))
+        bad_n = int(np.sum(out[0][1] != out[1][1]))
+        print(f"wide {tile}, {steps} steps, graph_steps {graph_steps}: cells differing psi {bad_psi}, n {bad_n}")
+        assert bad_psi == 0 and bad_n == 0
+
+
 @pytest.mark.parametrize("precision", PREC)
 @pytest.mark.parametrize("bc", [(0, 0), (1, 0)])
 def test_step_kernel_every_shape(precision, bc):
