@@ -18,6 +18,10 @@ region).  Printed as one JSON line together with
                 current kernel source is on file;
   copy_kernel_GBps  the library's streaming copy kernel on a 1 GiB buffer (read +
                 write bytes over HIP-event time): the attainable-bandwidth reference;
+  walk_pattern  (complex64 with the reservoir) the step kernel's bytes moved in the
+                wide walk's access pattern with none of its arithmetic (phx_walk_pattern,
+                HIP events): the floor that pattern sets, and the step kernel's launch
+                time over it;
   cpu_baseline  the CPU oracle (complex128, OpenMP) timed on a bounded sample of
                 the same workload on all its threads and on one thread, with the
                 host's CPU model.
@@ -74,6 +78,38 @@ def copy_bandwidth_gbps(torch, nbytes=COPY_BYTES, reps=20):
     if not ok:
         raise RuntimeError("streaming copy kernel produced wrong data")
     return 2.0 * nbytes * reps / (ms * 1e-3) / 1e9
+
+
+def walk_pattern_us(torch, psi, n, P, reps=20):
+    """Mean time of the walk-pattern kernel (the wide step kernel's loads and stores
+    without its arithmetic) from HIP events on torch's current stream.  As the solver
+    does between steps, the timed launches alternate between two sets of arrays (each
+    launch reads what the previous one wrote; only P is read every time), so that no
+    launch finds its inputs in the caches because they were read unchanged the time
+    before.  The first launch is checked: psi copied, n + P written."""
+    from paper_2411_18341_amd import phx
+    psi_a, n_a = psi.clone(), n.clone()
+    psi_b, n_b = torch.empty_like(psi), torch.empty_like(n)
+    phx.walk_pattern(psi_b, n_b, psi_a, n_a, P)
+    torch.cuda.synchronize()
+    ok = bool(torch.equal(psi_b, psi_a)) and bool(torch.equal(n_b, n_a + P))
+    if not ok:
+        raise RuntimeError("walk-pattern kernel produced wrong data")
+    for _ in range(3):
+        phx.walk_pattern(psi_a, n_a, psi_b, n_b, P)
+        phx.walk_pattern(psi_b, n_b, psi_a, n_a, P)
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    for k in range(reps):
+        if k % 2 == 0:
+            phx.walk_pattern(psi_a, n_a, psi_b, n_b, P)
+        else:
+            phx.walk_pattern(psi_b, n_b, psi_a, n_a, P)
+    stop.record()
+    torch.cuda.synchronize()
+    us = start.elapsed_time(stop) * 1e3 / reps
+    del psi_a, n_a, psi_b, n_b
+    return us
 
 
 def cpu_model() -> str:
@@ -269,6 +305,13 @@ def main():
         step_bytes += per_launch["imag_norm"] + per_launch["imag_scale"]
     step_gbps = step_bytes * cells * args.steps / wall / 1e9
 
+    walk = None
+    if real_bytes == 4 and res and E is None and args.n % 2 == 0:
+        wus = walk_pattern_us(torch, psi, n, Pd)
+        walk = {"us": round(wus, 2), "GBps": round(step_model["step"] * cells / (wus * 1e-6) / 1e9, 1),
+                "band_rows": "the 8-row ring's device-filling height",
+                "step_kernel_over_pattern": round(d["avg_us"] / wus, 3) if dom == "rk4_step" else None}
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(ph, psi0, n0, P, args.cpu_steps, args.noise, args.imag, V0, args.cpu_steps_1t)
@@ -288,6 +331,7 @@ def main():
         "step_model_bytes_per_point": step_bytes,
         "step_algorithmic_GBps": round(step_gbps, 1),
         "copy_kernel_GBps": round(copy_gbps, 1),
+        "walk_pattern": walk,
         "event_pass_steps": args.event_steps,
         "kernels": {k: {kk: round(vv, 2) if isinstance(vv, float) else vv for kk, vv in v.items()}
                     for k, v in kernels.items()},

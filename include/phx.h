@@ -417,6 +417,19 @@ phx_status phx_observables_static(const phx_config *cfg, const phx_fields *f, do
  * PHX_EINVAL on bad arguments, PHX_EHIP if the launch fails. */
 phx_status phx_stream_copy(void *dst, const void *src, size_t bytes, void *hip_stream);
 
+/* Replays the memory traffic of the complex64 wide whole-step walk (tile_wx 2: one wave
+ * per band of a 120-column strip, an 8-row input ring filled 3 rows ahead) with none of
+ * its arithmetic, enqueued on hip_stream: psi_out = psi_in and n_out = n_in + P on
+ * every cell of a periodic nx x ny grid (psi interleaved complex64, n and P float32,
+ * [ny][nx], caller-owned device arrays, 256-byte aligned, outputs not overlapping the
+ * inputs or each other).  Its 28 bytes per point in the step kernel's access pattern
+ * time the floor that pattern sets for that kernel (the RK4 step of Eqs. rk4_K1 to
+ * rk4_final moves the same bytes); it plays no part in the solver.  band_rows: 8..4096,
+ * or 0 for the height the step kernel picks for this grid.  PHX_EINVAL on bad arguments
+ * (odd nx, psi of 2 GiB or more, overlap), PHX_EHIP if the launch fails. */
+phx_status phx_walk_pattern(void *psi_out, void *n_out, const void *psi_in, const void *n_in, const void *P,
+                            int32_t nx, int32_t ny, int32_t band_rows, void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

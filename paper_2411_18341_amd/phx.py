@@ -132,7 +132,7 @@ ENTRY_POINTS = ("phx_workspace_bytes", "phx_create", "phx_step", "phx_observable
                 "phx_cnn_param_offsets", "phx_cnn_create", "phx_cnn_destroy", "phx_cnn_forward",
                 "phx_cnn_gradients", "phx_cnn_adam", "phx_cnn_train_step", "phx_coarsen",
                 "phx_corrector_features", "phx_corrector_residual", "phx_corrector_apply",
-                "phx_stream_copy", "phx_observables_static")
+                "phx_stream_copy", "phx_walk_pattern", "phx_observables_static")
 
 _lib = None
 
@@ -194,6 +194,8 @@ def load(path: str | None = None):
     lib.phx_corrector_apply.argtypes = [i32, vp, vp, vp, i32, i32, dbl, dbl, vp]
     lib.phx_stream_copy.argtypes = [vp, vp, ctypes.c_size_t, vp]
     lib.phx_stream_copy.restype = st
+    lib.phx_walk_pattern.argtypes = [vp, vp, vp, vp, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp]
+    lib.phx_walk_pattern.restype = st
     lib.phx_observables_static.argtypes = [P(phx_config), P(phx_fields), ctypes.c_double, vp, P(phx_obs)]
     lib.phx_observables_static.restype = st
     for name in ("phx_cnn_sizes", "phx_cnn_param_offsets", "phx_cnn_create", "phx_cnn_forward",
@@ -321,6 +323,26 @@ def stream_copy(dst, src, stream=None) -> None:
         raise ValueError("dst and src must be contiguous and of equal byte size")
     phx_stream_copy(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()), nbytes,
                     _stream_handle(stream, src.device))
+
+
+def phx_walk_pattern(psi_out, n_out, psi_in, n_in, P, nx: int, ny: int, band_rows: int, stream: int | None) -> None:
+    _check(load().phx_walk_pattern(psi_out, n_out, psi_in, n_in, P, int(nx), int(ny), int(band_rows),
+                                   stream or None))
+
+
+def walk_pattern(psi_out, n_out, psi_in, n_in, P, band_rows: int = 0, stream=None) -> None:
+    """The wide whole-step walk's loads and stores without its arithmetic (psi_out =
+    psi_in, n_out = n_in + P) on complex64 psi and float32 n, P tensors of shape
+    [ny, nx] or [1, ny, nx] (CUDA, contiguous), on `stream` (default: torch's current)."""
+    import torch
+    ny, nx = psi_in.shape[-2:]
+    for t, dt in ((psi_out, torch.complex64), (psi_in, torch.complex64), (n_out, torch.float32),
+                  (n_in, torch.float32), (P, torch.float32)):
+        if t.dtype != dt or tuple(t.shape[-2:]) != (ny, nx) or t.numel() != nx * ny or not t.is_contiguous():
+            raise ValueError("walk_pattern takes contiguous complex64 psi and float32 n, P of one shape")
+    v = lambda t: ctypes.c_void_p(t.data_ptr())
+    phx_walk_pattern(v(psi_out), v(n_out), v(psi_in), v(n_in), v(P), nx, ny, band_rows,
+                     _stream_handle(stream, psi_in.device))
 
 
 # ------------------------------------------------------------ conveniences

@@ -343,3 +343,25 @@ def test_profile_kernel_names():
     }
     for name, kind in cases.items():
         assert kernel_kind(name) == kind, name
+
+
+def test_walk_pattern_rejects_bad_arguments_without_touching_the_gpu():
+    """phx_walk_pattern (measurement only) validates on the host: NULL or unaligned
+    pointers, odd or empty grids, band heights outside 8..4096, a psi of 2 GiB or
+    more, outputs that overlap the inputs."""
+    vp = lambda a: phx.ctypes.c_void_p(a)
+    base = [vp(0x100000), vp(0x200000), vp(0x300000), vp(0x400000), vp(0x500000)]
+    cases = [
+        ([None] + base[1:], 64, 64, 0),
+        ([vp(0x100010)] + base[1:], 64, 64, 0),
+        (base, 63, 64, 0),
+        (base, 64, 0, 0),
+        (base, 64, 64, 7),
+        (base, 64, 64, 5000),
+        (base, 16384, 16384, 0),
+        ([vp(0x300000)] + base[1:], 64, 64, 0),   # psi_out on psi_in
+    ]
+    for ptrs, nx, ny, rows in cases:
+        with pytest.raises(phx.PhxError) as e:
+            phx.phx_walk_pattern(*ptrs, nx, ny, rows, None)
+        assert e.value.status == phx.PHX_EINVAL, (nx, ny, rows)

@@ -462,6 +462,26 @@ def test_step_and_stage_families_agree():
     assert rel_l2(out[0][0], out[1][0]) < 1e-13 and rel_l2(out[0][1], out[1][1]) < 1e-13
 
 
+@pytest.mark.parametrize("shape, rows", [((4096, 4096), 0), ((242, 131), 16), ((240, 97), 40), ((2, 9), 8)])
+def test_walk_pattern_kernel(shape, rows):
+    """The walk-pattern measurement kernel (the wide step kernel's loads and stores
+    without its arithmetic) reaches every cell exactly once: psi copied and n + P
+    written bit for bit, over ragged strips and bands."""
+    import torch
+    nx, ny = shape
+    dev = torch.device("cuda:0")
+    g = torch.Generator().manual_seed(nx * 7 + ny)
+    psi = torch.randn(1, ny, nx, dtype=torch.complex64, generator=g).to(dev)
+    n = torch.rand(1, ny, nx, generator=g).to(dev)
+    P = torch.rand(1, ny, nx, generator=g).to(dev)
+    psi_out = torch.full_like(psi, float("nan"))
+    n_out = torch.full_like(n, float("nan"))
+    phx.walk_pattern(psi_out, n_out, psi, n, P, band_rows=rows)
+    torch.cuda.synchronize()
+    assert torch.equal(psi_out, psi)
+    assert torch.equal(n_out, n + P)
+
+
 def test_kernel_timing_api():
     ph, psi, n, V, P = workload("driven", 512, 256, (0, 0))
     run = GpuRun(ph, psi, n, V, P, precision=C64, kernel=phx.PHX_KERNEL_STAGE)
