@@ -37,7 +37,7 @@ EXTRA_FLAGS = {f"rk4_stream_spinor{t}.hip": _FULL_UNROLL
                for t in ("", "_res_f40", "_res_f64", "_res_d40", "_res_d64")}
 # Units whose streaming kernels are checked for private (scratch) memory: a ring
 # that is not in registers makes the walk several times slower.
-STREAM_SOURCES = {"rk4_step.hip", "rk4_stream_drive.hip", "rk4_stream_wide.hip"} | set(EXTRA_FLAGS)
+STREAM_SOURCES = {"rk4_step.hip", "rk4_stream_drive.hip", "rk4_stream_wide.hip", "batch.hip"} | set(EXTRA_FLAGS)
 _USAGE = "-Rpass-analysis=kernel-resource-usage"
 
 
@@ -48,7 +48,7 @@ def _scratch_kernels(stderr: str) -> list:
     for line in stderr.splitlines():
         if "Function Name:" in line:
             name = line.split("Function Name:")[1].split("[")[0].strip()
-        elif "ScratchSize [bytes/lane]:" in line and name and "stream" in name:
+        elif "ScratchSize [bytes/lane]:" in line and name and ("stream" in name or "batch_wide" in name):
             size = int(line.split("ScratchSize [bytes/lane]:")[1].split("[")[0])
             if size:
                 out.append((name, size))

@@ -9,12 +9,14 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "philox.h"
 #include "runtime.h"
 #include "step_body.h"
 #include "stream_body.h"
+#include "stream_wide.h"
 
 namespace phx {
 
@@ -23,6 +25,9 @@ struct BatchInst {
     int nx, ny, bcx, bcy;
     int tiles_x, tile0;  // regions across x; first work item of this instance (region form)
     int s_tile0;         // first work item of this instance in the streaming form
+    int w_strips;        // wide streaming form (complex64): strips of 120 columns, else 0
+    int w_band;          // wide streaming form: rows per band
+    int w_tile0;         // first work item of this instance in the wide streaming form
     int64_t offset;      // element offset in the packed arrays
     Coef<R> c;
     R half_dt, dt, dt6;
@@ -169,6 +174,93 @@ static hipError_t launch_batch_stream(bool res, bool hv, bool ghosts, bool yzero
     return hipErrorInvalidValue;
 }
 
+// Wide streaming form of the batched step (the two-column walk of stream_wide.h) for
+// complex64 instances of even width: a work item is one band of an instance's w_band
+// rows of one 120-column strip, one single-wave workgroup per item (consecutive items
+// on one XCD).  The register budget per wave and the testing variant (CHECK, the last
+// step of a call) follow the single-grid wide kernel with the 8-row ring.
+template <bool RES, bool HASV, bool GHOSTS, bool YZERO, int WPE, bool CHECK>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE)))
+void batch_wide_kernel(const BatchInst<float>* __restrict__ inst, int count, const float2* psi_in, const float* n_in,
+                       float2* psi_out, float* n_out, const float* V, const float* P, unsigned int* flag)
+{
+    const int t = xcd_tile(blockIdx.x, gridDim.x);
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (inst[mid].w_tile0 <= t) lo = mid; else hi = mid - 1;
+    }
+    const BatchInst<float>& I = inst[lo];
+    const int lt = t - I.w_tile0;
+    const int band = lt / I.w_strips, strip = lt - band * I.w_strips;
+    StepArgs<float> a{};
+    a.nx = I.nx;
+    a.ny = I.ny;
+    a.bcx = I.bcx;
+    a.bcy = I.bcy;
+    a.tiles_x = I.w_strips;
+    a.c = I.c;
+    a.half_dt = I.half_dt;
+    a.dt = I.dt;
+    a.dt6 = I.dt6;
+    a.psi_in = psi_in + I.offset;
+    a.n_in = RES ? n_in + I.offset : nullptr;
+    a.psi_out = psi_out + I.offset;
+    a.n_out = RES ? n_out + I.offset : nullptr;
+    a.V = HASV ? V + I.offset : nullptr;
+    a.P = RES ? P + I.offset : nullptr;
+    a.comps = 1;
+    a.band_rows = I.w_band;
+    if (stream_band_wide<RES, HASV, GHOSTS, YZERO, 8, 3, CHECK>(a, strip, band, I.w_band, (band & 1) ? -1 : 1))
+        flag[0] = 1u;  // benign race: every writer stores 1
+}
+
+template <bool RES, bool HASV, bool GHOSTS, bool YZERO>
+static hipError_t launch_batch_wide_t(int total, const BatchInst<float>* inst, int count, const void* pi,
+                                      const void* ni, void* po, void* no, const void* V, const void* P,
+                                      unsigned int* flag, bool check, hipStream_t s)
+{
+    constexpr int WPE = !(RES && (HASV || GHOSTS)) ? 3 : 2;
+    constexpr int WPE_CHECK = RES ? 2 : WPE;
+    if (check)
+        batch_wide_kernel<RES, HASV, GHOSTS, YZERO, WPE_CHECK, true><<<total, 64, 0, s>>>(
+            inst, count, (const float2*)pi, (const float*)ni, (float2*)po, (float*)no, (const float*)V,
+            (const float*)P, flag);
+    else
+        batch_wide_kernel<RES, HASV, GHOSTS, YZERO, WPE, false><<<total, 64, 0, s>>>(
+            inst, count, (const float2*)pi, (const float*)ni, (float2*)po, (float*)no, (const float*)V,
+            (const float*)P, flag);
+    return hipGetLastError();
+}
+
+static hipError_t launch_batch_wide(bool res, bool hv, bool ghosts, bool yzero, int total,
+                                    const BatchInst<float>* inst, int count, const void* pi, const void* ni, void* po,
+                                    void* no, const void* V, const void* P, unsigned int* flag, bool check,
+                                    hipStream_t s)
+{
+#define PHX_BW(RS, HV, G, Y) \
+    if (res == RS && hv == HV && ghosts == G && yzero == Y) \
+        return launch_batch_wide_t<RS, HV, G, Y>(total, inst, count, pi, ni, po, no, V, P, flag, check, s)
+    PHX_BW(true, false, false, false); PHX_BW(true, true, false, false);
+    PHX_BW(false, false, false, false); PHX_BW(false, true, false, false);
+    PHX_BW(true, false, true, false); PHX_BW(true, true, true, false);
+    PHX_BW(false, false, true, false); PHX_BW(false, true, true, false);
+    PHX_BW(true, false, true, true); PHX_BW(true, true, true, true);
+    PHX_BW(false, false, true, true); PHX_BW(false, true, true, true);
+#undef PHX_BW
+    return hipErrorInvalidValue;
+}
+
+// Band height of the batched wide walk: about 48 rows, evened out over an instance's
+// bands (the walk's 8 halo rows per band then cover no empty rows).
+constexpr int kBatchWideRows = 48;
+static int batch_wide_band(int ny)
+{
+    const int bands = (ny + kBatchWideRows - 1) / kBatchWideRows;
+    const int b = (ny + bands - 1) / bands;
+    return b < 8 ? 8 : b;
+}
+
 template <typename R, bool RES, bool HASV, bool GHOSTS>
 static hipError_t launch_batch_t(int grid, const BatchInst<R>* inst, int count, int total, const void* pi,
                                  const void* ni, void* po, void* no, const void* V, const void* P,
@@ -277,6 +369,34 @@ static phx_status validate_batch(const phx_batch_desc* d)
     return PHX_OK;
 }
 
+// When a batch has instances on both walks, the one-column launch of each step runs on
+// a second stream of the device (created once, default priority), forked from the
+// caller's stream before the step and joined back into it after, so that the two
+// launches fill the device together rather than one after the other.
+static hipStream_t side_stream(int dev)
+{
+    static std::mutex mu;
+    static hipStream_t streams[64];
+    if (dev < 0 || dev >= 64) return nullptr;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!streams[dev] && hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking) != hipSuccess)
+        streams[dev] = nullptr;
+    return streams[dev];
+}
+
+// fork / join events of one call; they are released only after the last join has
+// completed (the call then returns with its work finished)
+struct ForkJoin {
+    hipEvent_t fork = nullptr, join = nullptr;
+    bool used = false;
+    ~ForkJoin()
+    {
+        if (used && join) (void)hipEventSynchronize(join);
+        if (fork) (void)hipEventDestroy(fork);
+        if (join) (void)hipEventDestroy(join);
+    }
+};
+
 template <typename R>
 static phx_status batch_run(const phx_batch_desc* d, int64_t n, hipStream_t stream)
 {
@@ -291,6 +411,7 @@ static phx_status batch_run(const phx_batch_desc* d, int64_t n, hipStream_t stre
     // the streaming form needs every instance's state under 2 GiB (32-bit buffer
     // offsets) and one y boundary rule for all instances
     bool use_stream = true, all_zero_y = true, all_periodic_y = true;
+    int64_t w_tile0 = 0;  // work items of the wide streaming form (complex64 instances of even width)
     for (int k = 0; k < d->count; ++k) {
         const phx_instance& I = d->instances[k];
         phx_config c = d->params[I.param_index];
@@ -309,8 +430,19 @@ static phx_status batch_run(const phx_batch_desc* d, int64_t n, hipStream_t stre
         b.dt = (R)c.dt;
         b.dt6 = (R)(c.dt / 6.0);
         tile0 += b.tiles_x * ((I.ny + BW * BR - 9) / (BW * BR - 8));
+        // the one-column and the wide work lists give each instance a range in one of
+        // them and an empty range in the other
+        // complex64 instances of even width take the wide walk, the others the
+        // one-column walk (on a second stream when both occur)
+        const bool wide = sizeof(R) == 4 && I.nx % 2 == 0;
+        b.w_strips = wide ? wide_strips(I.nx) : 0;
+        b.w_band = batch_wide_band(I.ny);
         b.s_tile0 = (int)std::min<int64_t>(s_tile0, INT32_MAX);
-        s_tile0 += (int64_t)((b.tiles_x + 3) / 4) * ((I.ny + SB - 1) / SB);
+        b.w_tile0 = (int)std::min<int64_t>(w_tile0, INT32_MAX);
+        if (wide)
+            w_tile0 += (int64_t)b.w_strips * ((I.ny + b.w_band - 1) / b.w_band);
+        else
+            s_tile0 += (int64_t)((b.tiles_x + 3) / 4) * ((I.ny + SB - 1) / SB);
         use_stream = use_stream && (double)I.nx * I.ny * 2.0 * sizeof(R) < 2147483648.0 - 256.0;
         all_zero_y = all_zero_y && c.bc_y == PHX_BC_ZERO;
         all_periodic_y = all_periodic_y && c.bc_y == PHX_BC_PERIODIC;
@@ -326,8 +458,9 @@ static phx_status batch_run(const phx_batch_desc* d, int64_t n, hipStream_t stre
         noisy = noisy || c.noise > 0.0;
     }
     const int total = tile0;
-    use_stream = use_stream && (all_zero_y || all_periodic_y) && s_tile0 < INT32_MAX;
+    use_stream = use_stream && (all_zero_y || all_periodic_y) && s_tile0 < INT32_MAX && w_tile0 < INT32_MAX;
     const int s_total = (int)std::min<int64_t>(s_tile0, INT32_MAX);
+    const int w_total = (int)std::min<int64_t>(w_tile0, INT32_MAX);
     hipError_t e = hipMemcpyAsync(ws + L.table, table.data(), table.size() * sizeof(BatchInst<R>),
                                   hipMemcpyHostToDevice, stream);
     if (e == hipSuccess && noisy)
@@ -364,11 +497,39 @@ static phx_status batch_run(const phx_batch_desc* d, int64_t n, hipStream_t stre
     }
     const BatchInst<R>* dtab = (const BatchInst<R>*)(ws + L.table);
     unsigned int* flag = (unsigned int*)(ws + L.flag);
+    // both walks in use: the one-column launch goes to the device's second stream
+    hipStream_t side = nullptr;
+    ForkJoin fj;
+    if (use_stream && w_total > 0 && s_total > 0) {
+        side = side_stream(dev);
+        if (side && (hipEventCreateWithFlags(&fj.fork, hipEventDisableTiming) != hipSuccess ||
+                     hipEventCreateWithFlags(&fj.join, hipEventDisableTiming) != hipSuccess))
+            side = nullptr;
+    }
     for (int64_t k = 0; k < n; ++k) {
-        if (use_stream)
-            e = launch_batch_stream<R>(res != 0, d->V != nullptr, ghosts, all_zero_y, s_total, dtab, d->count,
-                                       S[cur], SN[cur], S[cur ^ 1], SN[cur ^ 1], d->V, d->P, flag, stream);
-        else
+        if (use_stream) {
+            e = hipSuccess;
+            hipStream_t s_narrow = stream;
+            if (side) {
+                fj.used = true;
+                e = hipEventRecord(fj.fork, stream);
+                if (e == hipSuccess) e = hipStreamWaitEvent(side, fj.fork, 0);
+                s_narrow = side;
+            }
+            if constexpr (sizeof(R) == 4) {
+                if (e == hipSuccess && w_total > 0)
+                    e = launch_batch_wide(res != 0, d->V != nullptr, ghosts, all_zero_y, w_total,
+                                          (const BatchInst<float>*)dtab, d->count, S[cur], SN[cur], S[cur ^ 1],
+                                          SN[cur ^ 1], d->V, d->P, flag, k == n - 1, stream);
+            }
+            if (e == hipSuccess && s_total > 0)
+                e = launch_batch_stream<R>(res != 0, d->V != nullptr, ghosts, all_zero_y, s_total, dtab, d->count,
+                                           S[cur], SN[cur], S[cur ^ 1], SN[cur ^ 1], d->V, d->P, flag, s_narrow);
+            if (e == hipSuccess && side) {
+                e = hipEventRecord(fj.join, side);
+                if (e == hipSuccess) e = hipStreamWaitEvent(stream, fj.join, 0);
+            }
+        } else
             e = launch_batch<R>(res != 0, d->V != nullptr, ghosts, grid, dtab, d->count, total, S[cur], SN[cur],
                                 S[cur ^ 1], SN[cur ^ 1], d->V, d->P, flag, stream);
         if (e != hipSuccess) return fail(PHX_EHIP, "batch step launch: %s", hipGetErrorString(e));
