@@ -71,6 +71,35 @@ enum ConvMode { CONV_RELU_BF16 = 0, CONV_LINEAR_F32 = 1, CONV_MASK_BF16 = 2 };
 //       CONV_LINEAR_F32 -> out_f32[P][out_stride], channels < out_stride, acc + bias
 //       CONV_MASK_BF16 -> out_bf16[P][COUTP] = acc if mask[P][COUTP] > 0 else 0
 // Requires W % TW == 0.
+// The 16-byte chunks of one staged input tile (TR + 2 rows of TW + 2 pixels with the
+// circular halo, CINP channels) that this thread moves: chunk threadIdx.x + 256 k.
+// XCD-aware tile order (tile t = xcd_tile(v)): each XCD walks a contiguous band of
+// tiles, so the halo rows shared by vertically adjacent tiles are read through one L2.
+typedef unsigned int chunk16 __attribute__((ext_vector_type(4)));  // 16 bytes of a staged tile
+
+template <int CINP, int TR, int TW, int NPER>
+__device__ __forceinline__ void conv_fetch_tile(chunk16 (&stage)[NPER], const u16* __restrict__ in, int t, int H, int W,
+                                                int tx_n, int ty_n)
+{
+    constexpr int C8 = CINP / 8, NE = (TR + 2) * (TW + 2) * C8;
+    const int img = t / (ty_n * tx_n);
+    const int rt = t - img * (ty_n * tx_n);
+    const int y0 = (rt / tx_n) * TR, x0 = (rt - (rt / tx_n) * tx_n) * TW;
+#pragma unroll
+    for (int k = 0; k < NPER; ++k) {
+        const int e = threadIdx.x + 256 * k;
+        if (e < NE) {
+            const int c8 = e % C8, pix = e / C8;
+            const int r = pix / (TW + 2), c = pix - (pix / (TW + 2)) * (TW + 2);
+            int yy = y0 - 1 + r, xx = x0 - 1 + c;
+            if (yy < 0) yy += H;
+            if (yy >= H) yy %= H;
+            xx += (xx < 0) ? W : (xx >= W ? -W : 0);
+            stage[k] = *(const chunk16*)&in[((size_t)(img * H + yy) * W + xx) * CINP + 8 * c8];
+        }
+    }
+}
+
 template <int CINP, int COUTP, int MODE, int MT>
 __global__ __launch_bounds__(256) void conv_fwd_kernel(const u16* __restrict__ in, const u16* __restrict__ w,
                                                        const float* __restrict__ bias, int H, int W, int images,
@@ -93,25 +122,29 @@ __global__ __launch_bounds__(256) void conv_fwd_kernel(const u16* __restrict__ i
     }
     const int tx_n = W / TW, ty_n = (H + TR - 1) / TR;
     const int tiles = images * ty_n * tx_n;
+    // The next tile's input is loaded into registers while the current one is
+    // computed, then written to LDS after the barrier that ends the current tile's
+    // reads.
+    constexpr int NE = (TR + 2) * (TW + 2) * C8;  // 16-byte chunks of a staged tile
+    constexpr int NPER = (NE + 255) / 256;
+    chunk16 stage[NPER];
+    // (the last tile of a workgroup fetches its own tile again: no branch around the loads)
+    if ((int)blockIdx.x < tiles)
+        conv_fetch_tile<CINP, TR, TW, NPER>(stage, in, xcd_tile(blockIdx.x, tiles), H, W, tx_n, ty_n);
     for (int v = blockIdx.x; v < tiles; v += gridDim.x) {
-        // XCD-aware order: each XCD walks a contiguous band of tiles, so the halo rows
-        // shared by vertically adjacent tiles are read through one L2
         const int t = xcd_tile(v, tiles);
         const int img = t / (ty_n * tx_n);
         const int rt = t - img * (ty_n * tx_n);
         const int y0 = (rt / tx_n) * TR, x0 = (rt - (rt / tx_n) * tx_n) * TW;
         __syncthreads();  // the previous tile's reads of sx are done
-        for (int e = threadIdx.x; e < (TR + 2) * (TW + 2) * C8; e += 256) {
-            const int c8 = e % C8, pix = e / C8;
-            const int r = pix / (TW + 2), c = pix - (pix / (TW + 2)) * (TW + 2);
-            int yy = y0 - 1 + r, xx = x0 - 1 + c;
-            if (yy < 0) yy += H;
-            if (yy >= H) yy %= H;
-            xx += (xx < 0) ? W : (xx >= W ? -W : 0);
-            *(uint4*)&sx[(r * (TW + 2) + c) * CS + 8 * c8] =
-                *(const uint4*)&in[((size_t)(img * H + yy) * W + xx) * CINP + 8 * c8];
+#pragma unroll
+        for (int k = 0; k < NPER; ++k) {
+            const int e = threadIdx.x + 256 * k;
+            if (e < NE) *(chunk16*)&sx[(e / C8) * CS + 8 * (e % C8)] = stage[k];
         }
         __syncthreads();
+        const int vn = v + (int)gridDim.x < tiles ? v + (int)gridDim.x : v;
+        conv_fetch_tile<CINP, TR, TW, NPER>(stage, in, xcd_tile(vn, tiles), H, W, tx_n, ty_n);
         f32x4 acc[MT][NT];
 #pragma unroll
         for (int i = 0; i < MT; ++i)
