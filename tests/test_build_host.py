@@ -5,6 +5,8 @@ streaming kernels without it pass), and no store of more than 64 bits in the wid
 streaming kernel has its data registers rewritten by the next instruction."""
 import os
 
+import pytest
+
 from paper_2411_18341_amd import build
 
 REMARKS = """\
@@ -65,10 +67,11 @@ def test_store_hazard_scan_on_a_listing():
     assert [st.split()[1] for _, st, _ in wider] == ["v[8:11],", "v[12:15],", "v[24:27],"]
 
 
-def test_wide_kernel_stores_keep_their_data():
-    """Every 128-bit store of the wide streaming kernel has at least one instruction
-    before a VALU write to its data registers (device assembly of the unit, built with
-    the library's flags)."""
-    asm = build.device_asm("rk4_stream_wide.hip")
+@pytest.mark.parametrize("unit", ["rk4_stream_wide.hip", "batch.hip"])
+def test_wide_kernel_stores_keep_their_data(unit):
+    """Every 128-bit store of the wide streaming walk (single grid and batched) has at
+    least one instruction before a VALU write to its data registers (device assembly
+    of the unit, built with the library's flags)."""
+    asm = build.device_asm(unit)
     assert "buffer_store_dwordx4" in asm
     assert build.store_data_hazards(asm) == []
