@@ -26,12 +26,13 @@ namespace phx {
 //   T_s = ax lr_s + ay ud_s - 2(ax + ay) p_s - bx (lr_o - 2 q) + by (ud_o - 2 q),
 //   om_s = V/hbar + gh rho_s + gxh rho_o + grh n_s (the -2(ax + ay) p_s term folded into kv),
 //   fn_s = P_s - (gamma_r + R rho_s) n_s,
-// X_o = dir (next(dy_o) - prev(dy_o)), sgn = +1 for psi_+, -1 for psi_-.
+// X_o = dir (next(dy_o) - prev(dy_o)), sgn = +1 for psi_+, -1 for psi_-; dir bxy is passed in as
+// bxyd (dir is +-1: the same value bit for bit as multiplying X by dir).
 template <typename R, bool RES>
 __device__ __forceinline__ void spinor_rhs(const Coef<R>& c, const typename cvec<R>::type (&cur)[2],
                                            const typename cvec<R>::type (&lr)[2],
                                            const typename cvec<R>::type (&ud)[2],
-                                           const typename cvec<R>::type (&dy)[2], R kv, R dir,
+                                           const typename cvec<R>::type (&dy)[2], R kv, R bxyd,
                                            const R (&nn)[2], const R (&pv)[2], typename cvec<R>::type (&f)[2],
                                            R (&fn)[2])
 {
@@ -53,9 +54,11 @@ __device__ __forceinline__ void spinor_rhs(const Coef<R>& c, const typename cvec
         const R oy = fma(-c.bx, lr[o].y, fma(c.by, ud[o].y, cb * q.y));
         const R tx = fma(c.ax, lr[s].x, fma(c.ay, ud[s].x, ox));
         const R ty = fma(c.ax, lr[s].y, fma(c.ay, ud[s].y, oy));
-        const R xx = dir * (lane_next(dy[o].x) - lane_prev(dy[o].x));
-        const R xy = dir * (lane_next(dy[o].y) - lane_prev(dy[o].y));
-        const R sb = s == 0 ? -c.bxy : c.bxy;
+        // the walking direction's sign rides on the coefficient (bxyd = dir bxy, chosen
+        // once per band), not on each difference
+        const R xx = lane_next(dy[o].x) - lane_prev(dy[o].x);
+        const R xy = lane_next(dy[o].y) - lane_prev(dy[o].y);
+        const R sb = s == 0 ? -bxyd : bxyd;
         f[s].x = fma(sb, xx, fma(u, p.x, fma(om, p.y, -ty)));
         f[s].y = fma(sb, xy, fma(u, p.y, fma(-om, p.x, tx)));
     }
@@ -75,7 +78,7 @@ __device__ __forceinline__ bool stream_band_spinor(const StepArgs<R>& a, int str
     const R keep = gcol ? R(0) : R(1);  // ghost columns stay 0 in every stage
     const int b0 = band * B;
     const R kdiag = R(2) * (c.ax + c.ay);
-    const R rdir = (R)dir;
+    const R bxyd = dir > 0 ? c.bxy : -c.bxy;  // uniform over the wave
     const size_t cells = (size_t)a.nx * a.ny;
     const __amdgpu_buffer_rsrc_t rpo = buffer_of(a.psi_out, 2 * cells * sizeof(C));
     const __amdgpu_buffer_rsrc_t rno = buffer_of(a.n_out, RES ? 2 * cells * sizeof(R) : 0);
@@ -188,7 +191,7 @@ __device__ __forceinline__ bool stream_band_spinor(const StepArgs<R>& a, int str
                     nn[m] = sn[m][s0];
                     pv[m] = sP[m][s0];
                 }
-                spinor_rhs<R, RES>(c, cur, lr, ud, dy, sk[s0], rdir, nn, pv, f, fn);
+                spinor_rhs<R, RES>(c, cur, lr, ud, dy, sk[s0], bxyd, nn, pv, f, fn);
                 const R kk = YZERO ? keep * row_keep(j - 1 * dir) : keep;
 #pragma unroll
                 for (int m = 0; m < 2; ++m) {
@@ -212,7 +215,7 @@ __device__ __forceinline__ bool stream_band_spinor(const StepArgs<R>& a, int str
                     nn[m] = n2[m][slot<2>(u, 2)];
                     pv[m] = sP[m][s0];
                 }
-                spinor_rhs<R, RES>(c, cur, lr, ud, dy, sk[s0], rdir, nn, pv, f, fn);
+                spinor_rhs<R, RES>(c, cur, lr, ud, dy, sk[s0], bxyd, nn, pv, f, fn);
                 const R kk = YZERO ? keep * row_keep(j - 2 * dir) : keep;
 #pragma unroll
                 for (int m = 0; m < 2; ++m) {
@@ -238,7 +241,7 @@ __device__ __forceinline__ bool stream_band_spinor(const StepArgs<R>& a, int str
                     nn[m] = n3[m][slot<2>(u, 3)];
                     pv[m] = sP[m][s0];
                 }
-                spinor_rhs<R, RES>(c, cur, lr, ud, dy, sk[s0], rdir, nn, pv, f, fn);
+                spinor_rhs<R, RES>(c, cur, lr, ud, dy, sk[s0], bxyd, nn, pv, f, fn);
                 const R kk = YZERO ? keep * row_keep(j - 3 * dir) : keep;
 #pragma unroll
                 for (int m = 0; m < 2; ++m) {
@@ -265,7 +268,7 @@ __device__ __forceinline__ bool stream_band_spinor(const StepArgs<R>& a, int str
                     nn[m] = n4[m][slot<2>(u, 4)];
                     pv[m] = sP[m][s0];
                 }
-                spinor_rhs<R, RES>(c, cur, lr, ud, dy, sk[s0], rdir, nn, pv, f, fn);
+                spinor_rhs<R, RES>(c, cur, lr, ud, dy, sk[s0], bxyd, nn, pv, f, fn);
                 const int r = j - 4 * dir;
                 const bool st = out_col && r >= b0 && r < b0 + B && r < a.ny;
                 const int cell = r * a.nx + gi;
