@@ -75,7 +75,11 @@ __device__ __forceinline__ bool stream_band_spinor(const StepArgs<R>& a, int str
     const int gi = strip * 56 - 4 + lane;
     const int ci = wrap_any(gi, a.nx, a.bcx);
     const bool gcol = GHOSTS && ci < 0;
-    const R keep = gcol ? R(0) : R(1);  // ghost columns stay 0 in every stage
+    // Ghost columns and rows stay 0 in every stage: their inputs read as 0, so the stage
+    // argument p0 + h f is 0 there when the step h is taken as 0 (the lane's h values,
+    // and per row a uniform choice between them and 0).
+    const R kh2 = gcol ? R(0) : a.half_dt;
+    const R kh = gcol ? R(0) : a.dt;
     const int b0 = band * B;
     const R kdiag = R(2) * (c.ax + c.ay);
     const R bxyd = dir > 0 ? c.bxy : -c.bxy;  // uniform over the wave
@@ -156,8 +160,8 @@ __device__ __forceinline__ bool stream_band_spinor(const StepArgs<R>& a, int str
 #pragma unroll
     for (int t = 0; t < PF; ++t) fetch(t, true);
 
-    // 0 for a ghost row (zero y boundary), else 1: the row is uniform over the wave
-    auto row_keep = [&](int r) { return (YZERO && (unsigned)r >= (unsigned)a.ny) ? R(0) : R(1); };
+    // the lane's step h, or 0 on a ghost row (zero y boundary; uniform over the wave)
+    auto row_h = [&](int r, R h) { return (YZERO && (unsigned)r >= (unsigned)a.ny) ? R(0) : h; };
 
     // neighbour sums and y-differences of one stage argument (rows above, at, below
     // in walking order) for both components
@@ -192,14 +196,14 @@ __device__ __forceinline__ bool stream_band_spinor(const StepArgs<R>& a, int str
                     pv[m] = sP[m][s0];
                 }
                 spinor_rhs<R, RES>(c, cur, lr, ud, dy, sk[s0], bxyd, nn, pv, f, fn);
-                const R kk = YZERO ? keep * row_keep(j - 1 * dir) : keep;
+                const R hk = row_h(j - 1 * dir, kh2);
 #pragma unroll
                 for (int m = 0; m < 2; ++m) {
                     acc[m][slot<4>(u, 1)] = f[m];
-                    w2[m][slot<3>(u, 1)] = C{kk * fma(a.half_dt, f[m].x, cur[m].x), kk * fma(a.half_dt, f[m].y, cur[m].y)};
+                    w2[m][slot<3>(u, 1)] = C{fma(hk, f[m].x, cur[m].x), fma(hk, f[m].y, cur[m].y)};
                     if (RES) {
                         accn[m][slot<4>(u, 1)] = fn[m];
-                        n2[m][slot<2>(u, 1)] = kk * fma(a.half_dt, fn[m], sn[m][s0]);
+                        n2[m][slot<2>(u, 1)] = fma(hk, fn[m], sn[m][s0]);
                     }
                 }
             }
@@ -216,16 +220,16 @@ __device__ __forceinline__ bool stream_band_spinor(const StepArgs<R>& a, int str
                     pv[m] = sP[m][s0];
                 }
                 spinor_rhs<R, RES>(c, cur, lr, ud, dy, sk[s0], bxyd, nn, pv, f, fn);
-                const R kk = YZERO ? keep * row_keep(j - 2 * dir) : keep;
+                const R hk = row_h(j - 2 * dir, kh2);
 #pragma unroll
                 for (int m = 0; m < 2; ++m) {
                     C& ac = acc[m][slot<4>(u, 2)];
                     ac = C{fma(R(2), f[m].x, ac.x), fma(R(2), f[m].y, ac.y)};
                     const C p0 = sp[m][s0];
-                    w3[m][slot<3>(u, 2)] = C{kk * fma(a.half_dt, f[m].x, p0.x), kk * fma(a.half_dt, f[m].y, p0.y)};
+                    w3[m][slot<3>(u, 2)] = C{fma(hk, f[m].x, p0.x), fma(hk, f[m].y, p0.y)};
                     if (RES) {
                         accn[m][slot<4>(u, 2)] = fma(R(2), fn[m], accn[m][slot<4>(u, 2)]);
-                        n3[m][slot<2>(u, 2)] = kk * fma(a.half_dt, fn[m], sn[m][s0]);
+                        n3[m][slot<2>(u, 2)] = fma(hk, fn[m], sn[m][s0]);
                     }
                 }
             }
@@ -242,16 +246,16 @@ __device__ __forceinline__ bool stream_band_spinor(const StepArgs<R>& a, int str
                     pv[m] = sP[m][s0];
                 }
                 spinor_rhs<R, RES>(c, cur, lr, ud, dy, sk[s0], bxyd, nn, pv, f, fn);
-                const R kk = YZERO ? keep * row_keep(j - 3 * dir) : keep;
+                const R hk = row_h(j - 3 * dir, kh);
 #pragma unroll
                 for (int m = 0; m < 2; ++m) {
                     C& ac = acc[m][slot<4>(u, 3)];
                     ac = C{fma(R(2), f[m].x, ac.x), fma(R(2), f[m].y, ac.y)};
                     const C p0 = sp[m][s0];
-                    w4[m][slot<3>(u, 3)] = C{kk * fma(a.dt, f[m].x, p0.x), kk * fma(a.dt, f[m].y, p0.y)};
+                    w4[m][slot<3>(u, 3)] = C{fma(hk, f[m].x, p0.x), fma(hk, f[m].y, p0.y)};
                     if (RES) {
                         accn[m][slot<4>(u, 3)] = fma(R(2), fn[m], accn[m][slot<4>(u, 3)]);
-                        n4[m][slot<2>(u, 3)] = kk * fma(a.dt, fn[m], sn[m][s0]);
+                        n4[m][slot<2>(u, 3)] = fma(hk, fn[m], sn[m][s0]);
                     }
                 }
             }
