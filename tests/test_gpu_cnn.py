@@ -49,6 +49,38 @@ def test_forward_parity():
     net.close()
 
 
+@pytest.mark.parametrize("H,W", [(20, 64), (5, 32), (1, 96)])
+def test_forward_parity_ragged_height(H, W):
+    """Heights that are not a multiple of the forward kernel's tile height (the last
+    tile's missing rows wrap circularly when staged and are not stored), down to a
+    single row whose vertical neighbours are itself."""
+    net, x, t, xd, td = make(3, H=H, W=W, seed=13)
+    layers = [(conv_ref.to_bf16(w), b) for w, b in net.get_weights()]
+    y = net.forward(xd).cpu().numpy()
+    ref = ref_forward_bf16(layers, x.transpose(0, 3, 1, 2)).transpose(0, 2, 3, 1)
+    e = rel_l2(y, ref)
+    print(f"{H} x {W} forward rel L2 {e:.2e}")
+    assert e < 1e-2
+    assert np.max(np.abs(y - ref)) < 2.0 ** -6 * np.max(np.abs(ref))
+    net.close()
+
+
+def test_forward_input_paths_agree():
+    """The first layer reads 16-byte-aligned float32 features itself and packs other
+    inputs to bfloat16 first; training packs them too.  All give the same bits."""
+    import torch
+    net, x, t, xd, td = make(2, seed=17)
+    y0 = net.forward(xd).clone()
+    buf = torch.empty(xd.numel() + 1, dtype=torch.float32, device="cuda")
+    xu = buf[1:].view(xd.shape)
+    xu.copy_(xd)
+    assert xu.data_ptr() % 16 != 0
+    y1 = net.forward(xu)
+    torch.cuda.synchronize()
+    assert torch.equal(y0, y1)
+    net.close()
+
+
 def test_gradients_parity():
     net, x, t, xd, td = make(2, seed=3)
     layers = [(conv_ref.to_bf16(w), b) for w, b in net.get_weights()]
