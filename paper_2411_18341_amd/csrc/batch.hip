@@ -101,14 +101,15 @@ __global__ __launch_bounds__(WAVES * 64) void batch_step_kernel(
 constexpr int BW = 8, BR = 4;
 
 // Streaming form of the batched step (the band walk of stream_body.h): a work item is
-// one band of SB rows of a group of 4 adjacent strips of one instance, one workgroup
-// per item (consecutive items on one XCD); tiles_x counts an instance's strips of 56
-// columns.  YZERO: every instance has a zero y boundary (else every one is periodic
-// in y).
-constexpr int SB = 40;
+// one band of SB rows of SG adjacent strips of one instance, one workgroup per item
+// (consecutive items on one XCD); tiles_x counts an instance's strips of 56 columns.
+// Single-strip items (one wave each) measured 1 % faster on the batched workload than
+// groups of 2 or 4 strips, whose waves share nothing.  YZERO: every instance has a
+// zero y boundary (else every one is periodic in y).
+constexpr int SB = 40, SG = 1;
 
 template <typename R, bool RES, bool HASV, bool GHOSTS, bool YZERO>
-__global__ __launch_bounds__(256) void batch_stream_kernel(
+__global__ __launch_bounds__(64 * SG) void batch_stream_kernel(
     const BatchInst<R>* __restrict__ inst, int count, const typename cvec<R>::type* psi_in, const R* n_in,
     typename cvec<R>::type* psi_out, R* n_out, const R* V, const R* P, unsigned int* flag)
 {
@@ -121,8 +122,8 @@ __global__ __launch_bounds__(256) void batch_stream_kernel(
     }
     const BatchInst<R>& I = inst[lo];
     const int lt = t - I.s_tile0;
-    const int gx = (I.tiles_x + 3) / 4;
-    const int band = lt / gx, strip = (lt - band * gx) * 4 + wave;
+    const int gx = (I.tiles_x + SG - 1) / SG;
+    const int band = lt / gx, strip = (lt - band * gx) * SG + wave;
     if (strip >= I.tiles_x) return;
     StepArgs<R> a{};
     a.nx = I.nx;
@@ -151,7 +152,7 @@ static hipError_t launch_batch_stream_t(int total, const BatchInst<R>* inst, int
                                         unsigned int* flag, hipStream_t s)
 {
     using C = typename cvec<R>::type;
-    batch_stream_kernel<R, RES, HASV, GHOSTS, YZERO><<<total, 256, 0, s>>>(
+    batch_stream_kernel<R, RES, HASV, GHOSTS, YZERO><<<total, 64 * SG, 0, s>>>(
         inst, count, (const C*)pi, (const R*)ni, (C*)po, (R*)no, (const R*)V, (const R*)P, flag);
     return hipGetLastError();
 }
@@ -442,7 +443,7 @@ static phx_status batch_run(const phx_batch_desc* d, int64_t n, hipStream_t stre
         if (wide)
             w_tile0 += (int64_t)b.w_strips * ((I.ny + b.w_band - 1) / b.w_band);
         else
-            s_tile0 += (int64_t)((b.tiles_x + 3) / 4) * ((I.ny + SB - 1) / SB);
+            s_tile0 += (int64_t)((b.tiles_x + SG - 1) / SG) * ((I.ny + SB - 1) / SB);
         use_stream = use_stream && (double)I.nx * I.ny * 2.0 * sizeof(R) < 2147483648.0 - 256.0;
         all_zero_y = all_zero_y && c.bc_y == PHX_BC_ZERO;
         all_periodic_y = all_periodic_y && c.bc_y == PHX_BC_PERIODIC;
