@@ -5,11 +5,12 @@
 // predicted correction to a coarse state).
 //
 // Convolutions are implicit GEMMs on v_mfma_f32_16x16x32_bf16, in persistent
-// workgroups that walk tiles of a few rows x 64 (or 32) pixels staged in LDS:
+// workgroups that walk tiles of a few rows x 32 (or 64) pixels staged in LDS:
 //   forward        M = 16 output channels, N = 16 pixels of one row, K = 9 taps x C_in;
 //                  the weights stay in LDS for all tiles of a workgroup (read from the
-//                  float32 master parameters and rounded to bf16 as they are staged);
-//                  the first layer of an inference pass reads the float32 features
+//                  float32 master parameters and rounded to bf16 as they are staged)
+//   fused pair     (inference) layers 1 and 2 in one pass, layer 1's output on the tile
+//                  and its one-pixel ring kept in LDS; layer 1 reads the float32 features
 //   backward-data  the forward kernel on dY with the weights flipped in the taps and
 //                  transposed in the channels, times the ReLU mask of the layer input
 //   backward-weight M = output channels, N = 9 taps x C_in, K = pixels: dY^T and three
@@ -69,7 +70,7 @@ enum ConvMode { CONV_RELU_BF16 = 0, CONV_LINEAR_F32 = 1, CONV_MASK_BF16 = 2 };
 // channels x 32 k) and the input as operand B (32 k x 16 pixels), so each lane's
 // accumulator holds 4 consecutive output channels of one pixel and stores them with
 // one write.  Taller tiles stage fewer halo rows per output row.
-// in: [P][CINP] bf16 (XF32: [P][4] float32), w: [COUTP][KP] bf16 or (WT = float) the
+// in: [P][CINP] bf16, w: [COUTP][KP] bf16 or (WT = float) the
 // float32 master weights, rounded to bf16 in LDS (zero beyond 9*CINP), bias: [COUTP] f32.
 // MODE: CONV_RELU_BF16 -> out_bf16[P][COUTP] = relu(acc + bias)
 //       CONV_LINEAR_F32 -> out_f32[P][out_stride], channels < out_stride, acc + bias
@@ -79,8 +80,6 @@ enum ConvMode { CONV_RELU_BF16 = 0, CONV_LINEAR_F32 = 1, CONV_MASK_BF16 = 2 };
 // circular halo, CINP channels) that this thread moves: chunk threadIdx.x + 256 k.
 // XCD-aware tile order (tile t = xcd_tile(v)): each XCD walks a contiguous band of
 // tiles, so the halo rows shared by vertically adjacent tiles are read through one L2.
-// XF32: the input is float32 with 4 channels per pixel (16 bytes), rounded to bf16
-// here and padded to the 8 staged channels with zeros.
 typedef unsigned int chunk16 __attribute__((ext_vector_type(4)));  // 16 bytes of a staged tile
 
 __device__ __forceinline__ unsigned int bf16_pair(float lo, float hi)
@@ -88,11 +87,10 @@ __device__ __forceinline__ unsigned int bf16_pair(float lo, float hi)
     return bf16_bits(lo) | ((unsigned int)bf16_bits(hi) << 16);
 }
 
-template <int CINP, int TR, int TW, int NPER, bool XF32>
-__device__ __forceinline__ void conv_fetch_tile(chunk16 (&stage)[NPER], const void* __restrict__ in, int t, int H,
+template <int CINP, int TR, int TW, int NPER>
+__device__ __forceinline__ void conv_fetch_tile(chunk16 (&stage)[NPER], const u16* __restrict__ in, int t, int H,
                                                 int W, int tx_n, int ty_n)
 {
-    static_assert(!XF32 || CINP == 8, "float32 input: 4 channels padded to 8");
     constexpr int C8 = CINP / 8, NE = (TR + 2) * (TW + 2) * C8;
     const int img = t / (ty_n * tx_n);
     const int rt = t - img * (ty_n * tx_n);
@@ -107,19 +105,13 @@ __device__ __forceinline__ void conv_fetch_tile(chunk16 (&stage)[NPER], const vo
             if (yy < 0) yy += H;
             if (yy >= H) yy %= H;
             xx += (xx < 0) ? W : (xx >= W ? -W : 0);
-            const size_t p = (size_t)(img * H + yy) * W + xx;
-            if (XF32) {
-                const float4 v = ((const float4*)in)[p];
-                stage[k] = chunk16{bf16_pair(v.x, v.y), bf16_pair(v.z, v.w), 0u, 0u};
-            } else {
-                stage[k] = *(const chunk16*)&((const u16*)in)[p * CINP + 8 * c8];
-            }
+            stage[k] = *(const chunk16*)&in[((size_t)(img * H + yy) * W + xx) * CINP + 8 * c8];
         }
     }
 }
 
-template <int CINP, int COUTP, int MODE, int MT, int TR, bool XF32, typename WT>
-__global__ __launch_bounds__(256) void conv_fwd_kernel(const void* __restrict__ in, const WT* __restrict__ w,
+template <int CINP, int COUTP, int MODE, int MT, int TR, typename WT>
+__global__ __launch_bounds__(256) void conv_fwd_kernel(const u16* __restrict__ in, const WT* __restrict__ w,
                                                        const float* __restrict__ bias, int H, int W, int images,
                                                        u16* __restrict__ out_bf16, float* __restrict__ out_f32,
                                                        int out_stride, const u16* __restrict__ mask)
@@ -156,7 +148,7 @@ __global__ __launch_bounds__(256) void conv_fwd_kernel(const void* __restrict__ 
     chunk16 stage[NPER];
     // (the last tile of a workgroup fetches its own tile again: no branch around the loads)
     if ((int)blockIdx.x < tiles)
-        conv_fetch_tile<CINP, TR, TW, NPER, XF32>(stage, in, xcd_tile(blockIdx.x, tiles), H, W, tx_n, ty_n);
+        conv_fetch_tile<CINP, TR, TW, NPER>(stage, in, xcd_tile(blockIdx.x, tiles), H, W, tx_n, ty_n);
     for (int v = blockIdx.x; v < tiles; v += gridDim.x) {
         const int t = xcd_tile(v, tiles);
         const int img = t / (ty_n * tx_n);
@@ -170,7 +162,7 @@ __global__ __launch_bounds__(256) void conv_fwd_kernel(const void* __restrict__ 
         }
         __syncthreads();
         const int vn = v + (int)gridDim.x < tiles ? v + (int)gridDim.x : v;
-        conv_fetch_tile<CINP, TR, TW, NPER, XF32>(stage, in, xcd_tile(vn, tiles), H, W, tx_n, ty_n);
+        conv_fetch_tile<CINP, TR, TW, NPER>(stage, in, xcd_tile(vn, tiles), H, W, tx_n, ty_n);
         f32x4 acc[RW][MT][NT];
 #pragma unroll
         for (int rr = 0; rr < RW; ++rr)
@@ -230,6 +222,214 @@ __global__ __launch_bounds__(256) void conv_fwd_kernel(const void* __restrict__ 
                         for (int r = 0; r < 4; ++r) o[r] = bf16_bits(bf16_value(mv[r]) > 0.f ? acc[rr][i][j][r] : 0.f);
                         *(uint2*)&out_bf16[q * COUTP + c0] =
                             uint2{o[0] | ((unsigned int)o[1] << 16), o[2] | ((unsigned int)o[3] << 16)};
+                    }
+                }
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------ fused layer pairs
+
+// Two consecutive layers in one pass, for inference: layer A (CINP -> 32, ReLU, bf16)
+// is evaluated on the tile and a one-pixel ring around it into LDS, and layer B
+// (32 -> COUTP, MODE as in conv_fwd_kernel) reads it there, so the 32-channel
+// activation between the two never goes through HBM.  A tile is 8 rows x 32 pixels of
+// one image and a workgroup has 8 waves, one output row of layer B each.  The input is
+// staged with a two-pixel circular ring (12 x 36 pixels); layer A's 10 x 34 pixels are
+// taken as 22 runs of 16 consecutive pixels of that region in row-major order (the
+// last run 12 pixels short), runs w, w + 8, w + 16 on wave w.  Every output element
+// is accumulated over the same K order as in the one-layer kernel, so the results are
+// the same bits.  Weights: the float32 master copies, rounded to bf16 in LDS.
+// XF32: the input is float32 with 4 channels per pixel (CINP = 8).
+constexpr int PAIR_R = 8, PAIR_W = 32, PAIR_THREADS = 512;
+
+template <int CINP, int NPER, bool XF32>
+__device__ __forceinline__ void pair_fetch_tile(chunk16 (&stage)[NPER], const void* __restrict__ in, int t, int H,
+                                                int W, int tx_n, int ty_n)
+{
+    static_assert(!XF32 || CINP == 8, "float32 input: 4 channels padded to 8");
+    constexpr int XR = PAIR_R + 4, XW = PAIR_W + 4, C8 = CINP / 8, NE = XR * XW * C8;
+    const int img = t / (ty_n * tx_n);
+    const int rt = t - img * (ty_n * tx_n);
+    const int y0 = (rt / tx_n) * PAIR_R, x0 = (rt - (rt / tx_n) * tx_n) * PAIR_W;
+#pragma unroll
+    for (int k = 0; k < NPER; ++k) {
+        const int e = threadIdx.x + PAIR_THREADS * k;
+        if (e < NE) {
+            const int c8 = e % C8, pix = e / C8;
+            const int r = pix / XW, c = pix - (pix / XW) * XW;
+            int yy = (y0 - 2 + r) % H;  // the grid may have fewer rows than the ring
+            if (yy < 0) yy += H;
+            int xx = x0 - 2 + c;  // W >= 32: one wrap at most
+            xx += (xx < 0) ? W : (xx >= W ? -W : 0);
+            const size_t p = (size_t)(img * H + yy) * W + xx;
+            if (XF32) {
+                const float4 v = ((const float4*)in)[p];
+                stage[k] = chunk16{bf16_pair(v.x, v.y), bf16_pair(v.z, v.w), 0u, 0u};
+            } else {
+                stage[k] = *(const chunk16*)&((const u16*)in)[p * CINP + 8 * c8];
+            }
+        }
+    }
+}
+
+template <int COUTP, int KP, int WS>
+__device__ __forceinline__ void stage_weights(u16* sw, const float* __restrict__ w)
+{
+    for (int e = threadIdx.x; e < COUTP * (KP / 8); e += PAIR_THREADS) {
+        const int o = e / (KP / 8), k8 = e - o * (KP / 8);
+        const float4 lo = *(const float4*)&w[(size_t)o * KP + 8 * k8];
+        const float4 hi = *(const float4*)&w[(size_t)o * KP + 8 * k8 + 4];
+        *(uint4*)&sw[o * WS + 8 * k8] =
+            uint4{bf16_pair(lo.x, lo.y), bf16_pair(lo.z, lo.w), bf16_pair(hi.x, hi.y), bf16_pair(hi.z, hi.w)};
+    }
+}
+
+template <int CINP, int COUTP, int MODE, bool XF32>
+__global__ __launch_bounds__(PAIR_THREADS) void conv_pair_kernel(const void* __restrict__ in,
+                                                                 const float* __restrict__ wa,
+                                                                 const float* __restrict__ ba,
+                                                                 const float* __restrict__ wb,
+                                                                 const float* __restrict__ bb, int H, int W, int images,
+                                                                 u16* __restrict__ out_bf16, float* __restrict__ out_f32,
+                                                                 int out_stride)
+{
+    static_assert(MODE == CONV_RELU_BF16 || MODE == CONV_LINEAR_F32, "forward modes only");
+    constexpr int XR = PAIR_R + 4, XW = PAIR_W + 4;  // staged input
+    constexpr int EW = PAIR_W + 2;                   // layer A's region: (PAIR_R + 2) x EW
+    constexpr int EP = (PAIR_R + 2) * EW;            // 340 pixels
+    constexpr int ENT = (EP + 15) / 16;              // 22 runs
+    constexpr int KPA = (9 * CINP + 31) / 32 * 32, KPB = 9 * 32;
+    constexpr int NTB = COUTP / 16, MT = PAIR_W / 16;
+    constexpr int CS0 = CINP + 8, CS1 = 32 + 8;  // LDS elements per pixel (padded)
+    constexpr int WSA = KPA + 8, WSB = KPB + 8;
+    constexpr int C8 = CINP / 8;
+    constexpr int NE = XR * XW * C8, NPER = (NE + PAIR_THREADS - 1) / PAIR_THREADS;
+    constexpr int RUNS = (ENT + 7) / 8;  // runs of layer A per wave
+    __shared__ __attribute__((aligned(16))) u16 swa[32 * WSA];
+    __shared__ __attribute__((aligned(16))) u16 swb[COUTP * WSB];
+    __shared__ __attribute__((aligned(16))) u16 sx0[XR * XW * CS0];
+    __shared__ __attribute__((aligned(16))) u16 sx1[EP * CS1];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int m = lane & 15, g = lane >> 4;
+    stage_weights<32, KPA, WSA>(swa, wa);
+    stage_weights<COUTP, KPB, WSB>(swb, wb);
+    const int tx_n = W / PAIR_W, ty_n = (H + PAIR_R - 1) / PAIR_R;
+    const int tiles = images * ty_n * tx_n;
+    chunk16 stage[NPER];
+    if ((int)blockIdx.x < tiles)
+        pair_fetch_tile<CINP, NPER, XF32>(stage, in, xcd_tile(blockIdx.x, tiles), H, W, tx_n, ty_n);
+    for (int v = blockIdx.x; v < tiles; v += gridDim.x) {
+        const int t = xcd_tile(v, tiles);
+        const int img = t / (ty_n * tx_n);
+        const int rt = t - img * (ty_n * tx_n);
+        const int y0 = (rt / tx_n) * PAIR_R, x0 = (rt - (rt / tx_n) * tx_n) * PAIR_W;
+        __syncthreads();  // the previous tile's reads of sx0 and sx1 are done
+#pragma unroll
+        for (int k = 0; k < NPER; ++k) {
+            const int e = threadIdx.x + PAIR_THREADS * k;
+            if (e < NE) *(chunk16*)&sx0[(e / C8) * CS0 + 8 * (e % C8)] = stage[k];
+        }
+        __syncthreads();
+        const int vn = v + (int)gridDim.x < tiles ? v + (int)gridDim.x : v;
+        pair_fetch_tile<CINP, NPER, XF32>(stage, in, xcd_tile(vn, tiles), H, W, tx_n, ty_n);
+
+        // layer A on the 10 x 34 region: run q covers region pixels 16 q .. 16 q + 15
+        {
+            f32x4 acc[RUNS][2];
+            int base[RUNS];  // the lane's pixel, as an offset of its top-left tap in sx0
+#pragma unroll
+            for (int u = 0; u < RUNS; ++u) {
+                const int q = wave + 8 * u;
+                const int p = q < ENT ? (16 * q + m < EP ? 16 * q + m : EP - 1) : 0;
+                const int er = p / EW, ec = p - (p / EW) * EW;
+                base[u] = er * XW + ec;
+                acc[u][0] = acc[u][1] = f32x4{0.f, 0.f, 0.f, 0.f};
+            }
+#pragma unroll
+            for (int c = 0; c < KPA / 32; ++c) {
+                const int k0 = 32 * c + 8 * g;
+                const int tap = k0 / CINP, ci = k0 - (k0 / CINP) * CINP;
+                const int dy = tap / 3, dx = tap - (tap / 3) * 3;
+                bf16x8 a[2];
+#pragma unroll
+                for (int j = 0; j < 2; ++j) a[j] = *(const bf16x8*)&swa[(j * 16 + m) * WSA + k0];
+#pragma unroll
+                for (int u = 0; u < RUNS; ++u) {
+                    if (wave + 8 * u < ENT) {  // uniform over the wave
+                        bf16x8 b = bf16x8{0, 0, 0, 0, 0, 0, 0, 0};
+                        if (tap < 9) b = *(const bf16x8*)&sx0[(base[u] + dy * XW + dx) * CS0 + ci];
+#pragma unroll
+                        for (int j = 0; j < 2; ++j)
+                            acc[u][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[j], b, acc[u][j], 0, 0, 0);
+                    }
+                }
+            }
+            // lane holds C[4g + r][m]: channel j*16 + 4g + r of region pixel 16 q + m
+#pragma unroll
+            for (int u = 0; u < RUNS; ++u) {
+                const int p = 16 * (wave + 8 * u) + m;
+                if (wave + 8 * u < ENT && p < EP) {
+#pragma unroll
+                    for (int j = 0; j < 2; ++j) {
+                        const int c0 = j * 16 + 4 * g;
+                        u16 o[4];
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            const float x = acc[u][j][r] + ba[c0 + r];
+                            o[r] = bf16_bits(x > 0.f ? x : 0.f);
+                        }
+                        *(uint2*)&sx1[p * CS1 + c0] =
+                            uint2{o[0] | ((unsigned int)o[1] << 16), o[2] | ((unsigned int)o[3] << 16)};
+                    }
+                }
+            }
+        }
+        __syncthreads();  // layer A's region is complete
+
+        // layer B: wave w computes output row w from region rows w .. w + 2
+        f32x4 acc[MT][NTB];
+#pragma unroll
+        for (int i = 0; i < MT; ++i)
+#pragma unroll
+            for (int j = 0; j < NTB; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int c = 0; c < KPB / 32; ++c) {
+            const int k0 = 32 * c + 8 * g;
+            const int tap = k0 / 32, ci = k0 - (k0 / 32) * 32;
+            const int dy = tap / 3, dx = tap - (tap / 3) * 3;
+            bf16x8 a[NTB];
+#pragma unroll
+            for (int j = 0; j < NTB; ++j) a[j] = *(const bf16x8*)&swb[(j * 16 + m) * WSB + k0];
+#pragma unroll
+            for (int i = 0; i < MT; ++i) {
+                const bf16x8 b = *(const bf16x8*)&sx1[((wave + dy) * EW + i * 16 + m + dx) * CS1 + ci];
+#pragma unroll
+                for (int j = 0; j < NTB; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[j], b, acc[i][j], 0, 0, 0);
+            }
+        }
+        const int yrow = y0 + wave;
+        if (yrow < H) {
+#pragma unroll
+            for (int i = 0; i < MT; ++i) {
+                const size_t q = (size_t)(img * H + yrow) * W + x0 + i * 16 + m;
+#pragma unroll
+                for (int j = 0; j < NTB; ++j) {
+                    const int c0 = j * 16 + 4 * g;
+                    if (MODE == CONV_RELU_BF16) {
+                        u16 o[4];
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            const float x = acc[i][j][r] + bb[c0 + r];
+                            o[r] = bf16_bits(x > 0.f ? x : 0.f);
+                        }
+                        *(uint2*)&out_bf16[q * COUTP + c0] =
+                            uint2{o[0] | ((unsigned int)o[1] << 16), o[2] | ((unsigned int)o[3] << 16)};
+                    } else {
+#pragma unroll
+                        for (int r = 0; r < 4; ++r)
+                            if (c0 + r < out_stride) out_f32[q * out_stride + c0 + r] = acc[i][j][r] + bb[c0 + r];
                     }
                 }
             }
@@ -688,17 +888,32 @@ static int resident_groups(K kernel, int threads, int& per_cu)
 // 2-3 % faster than 4 x 64 and than 8 x 64 (2 workgroups per CU) tiles.
 constexpr int kConvRows = 8, kConvMT = 2;
 
-template <int CINP, int COUTP, int MODE, bool XF32 = false, typename WT>
+template <int CINP, int COUTP, int MODE, typename WT>
 static hipError_t launch_conv(const void* in, const WT* w, const float* bias, int H, int W, int P, u16* ob,
                               float* of, int ostride, const u16* mask, hipStream_t s)
 {
     static int per_cu = 0;
     const int images = P / (H * W);
     const int tiles = images * ((H + kConvRows - 1) / kConvRows) * (W / (16 * kConvMT));
-    auto k = conv_fwd_kernel<CINP, COUTP, MODE, kConvMT, kConvRows, XF32, WT>;
+    auto k = conv_fwd_kernel<CINP, COUTP, MODE, kConvMT, kConvRows, WT>;
     const int res = resident_groups(k, 256, per_cu);
     const int grid = (res > 0 && res < tiles) ? res : tiles;
-    k<<<grid, 256, 0, s>>>(in, w, bias, H, W, images, ob, of, ostride, mask);
+    k<<<grid, 256, 0, s>>>((const u16*)in, w, bias, H, W, images, ob, of, ostride, mask);
+    return hipGetLastError();
+}
+
+// two fused layers (inference): persistent over 8 x 32 tiles
+template <int CINP, int COUTP, int MODE, bool XF32 = false>
+static hipError_t launch_pair(const void* in, const float* wa, const float* ba, const float* wb, const float* bb, int H,
+                              int W, int P, u16* ob, float* of, int ostride, hipStream_t s)
+{
+    static int per_cu = 0;
+    const int images = P / (H * W);
+    const int tiles = images * ((H + PAIR_R - 1) / PAIR_R) * (W / PAIR_W);
+    auto k = conv_pair_kernel<CINP, COUTP, MODE, XF32>;
+    const int res = resident_groups(k, PAIR_THREADS, per_cu);
+    const int grid = (res > 0 && res < tiles) ? res : tiles;
+    k<<<grid, PAIR_THREADS, 0, s>>>(in, wa, ba, wb, bb, H, W, images, ob, of, ostride);
     return hipGetLastError();
 }
 
@@ -718,10 +933,13 @@ static hipError_t cnn_pack_flipped(phx_cnn* h)
     return hipSuccess;
 }
 
-// Forward pass; activations of every layer input kept in the workspace.  The layers
-// read the float32 master weights.  With keep_input (training: the first layer's
-// weight gradient needs it) or an x that is not 16-byte aligned, x is first packed
-// into bf16 [P][8]; otherwise the first layer reads x itself.  Both give the same bits.
+// Forward pass.  Training (keep_input) keeps every layer's input in the workspace for
+// the backward passes: x packed into bf16 [P][8], then one launch per layer.  Inference
+// runs layers 1 and 2 as one fused pair, the first layer reading x itself when it is
+// 16-byte aligned (else from its bf16 copy), then layers 3 and 4 one launch each (the
+// fused pair of those two was slower: 25 % more matrix products for a 32-channel
+// layer A, and one 8-wave workgroup per CU with its LDS).  All paths give the same
+// bits.  Every layer reads the float32 master weights.
 static phx_status cnn_forward_impl(phx_cnn* h, const float* x, int batch, float* y, bool keep_input)
 {
     const int H = h->cfg.height, W = h->cfg.width, P = batch * H * W;
@@ -733,19 +951,26 @@ static phx_status cnn_forward_impl(phx_cnn* h, const float* x, int batch, float*
         bias[l] = h->buf.params + h->b_off[l];
         wf[l] = h->buf.params + h->w_off[l];
     }
-    if (keep_input || ((uintptr_t)x & 15u)) {
+    const bool aligned = ((uintptr_t)x & 15u) == 0;
+    if (keep_input || !aligned) {
         const int n0 = P * h->dims[0].cinp;
         pack_input_kernel<<<(n0 + 255) / 256, 256, 0, s>>>(x, h->dims[0].cin, h->dims[0].cinp, P,
                                                            (u16*)(ws + h->act[0]));
         CNN_HIP(hipGetLastError());
+    }
+    if (!keep_input) {
+        if (aligned)
+            CNN_HIP((launch_pair<8, 32, CONV_RELU_BF16, true>(x, wf[0], bias[0], wf[1], bias[1], H, W, P,
+                                                              (u16*)(ws + h->act[2]), nullptr, 0, s)));
+        else
+            CNN_HIP((launch_pair<8, 32, CONV_RELU_BF16>(ws + h->act[0], wf[0], bias[0], wf[1], bias[1], H, W, P,
+                                                        (u16*)(ws + h->act[2]), nullptr, 0, s)));
+    } else {
         CNN_HIP((launch_conv<8, 32, CONV_RELU_BF16>(ws + h->act[0], wf[0], bias[0], H, W, P, (u16*)(ws + h->act[1]),
                                                     nullptr, 0, nullptr, s)));
-    } else {
-        CNN_HIP((launch_conv<8, 32, CONV_RELU_BF16, true>(x, wf[0], bias[0], H, W, P, (u16*)(ws + h->act[1]),
-                                                          nullptr, 0, nullptr, s)));
+        CNN_HIP((launch_conv<32, 32, CONV_RELU_BF16>(ws + h->act[1], wf[1], bias[1], H, W, P, (u16*)(ws + h->act[2]),
+                                                     nullptr, 0, nullptr, s)));
     }
-    CNN_HIP((launch_conv<32, 32, CONV_RELU_BF16>(ws + h->act[1], wf[1], bias[1], H, W, P, (u16*)(ws + h->act[2]),
-                                                 nullptr, 0, nullptr, s)));
     CNN_HIP((launch_conv<32, 32, CONV_RELU_BF16>(ws + h->act[2], wf[2], bias[2], H, W, P, (u16*)(ws + h->act[3]),
                                                  nullptr, 0, nullptr, s)));
     CNN_HIP((launch_conv<32, 16, CONV_LINEAR_F32>(ws + h->act[3], wf[3], bias[3], H, W, P, nullptr, y,
