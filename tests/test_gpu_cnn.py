@@ -81,6 +81,23 @@ def test_forward_input_paths_agree():
     net.close()
 
 
+def test_inference_pass_matches_training_forward():
+    """Inference runs layers 1 and 2 as one fused kernel; training runs the layers one
+    by one.  Both accumulate every output in the same order, so their outputs are the
+    same bits: the loss that gradients() forms from its own forward pass equals the
+    loss of forward()'s output up to the order of the (exact) double-precision sum."""
+    import torch
+    net, x, t, xd, td = make(4, H=44, W=96, seed=23)
+    y = net.forward(xd).cpu().numpy()
+    net.gradients(xd, td)
+    torch.cuda.synchronize()
+    d = (y - t).astype(np.float64)  # float32 differences, as the loss kernel forms them
+    ref = float(np.sum(d * d) / d.size)
+    print(f"loss {net.loss.item():.17g} vs {ref:.17g}")
+    assert abs(net.loss.item() - ref) <= 1e-12 * ref
+    net.close()
+
+
 def test_gradients_parity():
     net, x, t, xd, td = make(2, seed=3)
     layers = [(conv_ref.to_bf16(w), b) for w, b in net.get_weights()]
