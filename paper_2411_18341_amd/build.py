@@ -35,6 +35,9 @@ FLAGS = [
 _FULL_UNROLL = ["-mllvm", "-pragma-unroll-threshold=40000"]
 EXTRA_FLAGS = {f"rk4_stream_spinor{t}.hip": _FULL_UNROLL
                for t in ("", "_res_f40", "_res_f64", "_res_d40", "_res_d64")}
+# the wide walk with the Wiener increment drawn at its final store (a generator call
+# per position) likewise exceeds the default limit
+EXTRA_FLAGS["rk4_stream_wide.hip"] = _FULL_UNROLL
 # Units whose streaming kernels are checked for private (scratch) memory: a ring
 # that is not in registers makes the walk several times slower.
 STREAM_SOURCES = {"rk4_step.hip", "rk4_stream_drive.hip", "rk4_stream_wide.hip", "batch.hip"} | set(EXTRA_FLAGS)

@@ -75,10 +75,10 @@ hipError_t launch_noise(const phx_handle* h, void* psi, const void* n, int64_t o
 {
     const phx_config& c = h->cfg;
     const int64_t cells = (int64_t)c.nx * c.ny;
-    const double scale = c.noise * c.dt / (4.0 * c.dx * c.dy);
-    const R a = (R)(scale * c.R), b = (R)(scale * c.gamma_c);
+    R a, b;
+    uint32_t k0, k1;
+    noise_coefs<R>(c, a, b, k0, k1);
     const uint64_t* base = (const uint64_t*)(h->ws + h->L.noise);
-    const uint32_t k0 = (uint32_t)c.seed, k1 = (uint32_t)(c.seed >> 32);
     using C = typename cvec<R>::type;
     const int64_t pairs = (cells + 1) / 2;
     const dim3 grid((unsigned)((pairs + 255) / 256), (unsigned)c.components);

@@ -237,10 +237,16 @@ phx_status rk4_fused_launches(phx_handle* h, int64_t n, hipStream_t s)
     void* SN[2] = {h->f.n, c.reservoir ? h->ws + h->L.alt_n : nullptr};
     const bool res = c.reservoir != 0, hv = h->f.V != nullptr;
     const StepShapeId sh = h->step_shape;
+    const bool fused_noise = c.noise > 0.0 && noise_in_step(c, sh);
     int cur = h->step_parity;
     for (int64_t k = 0; k < n; ++k) {
         StepArgs<R> a = step_args<R>(h, sh, S[cur], SN[cur], S[cur ^ 1], SN[cur ^ 1]);
         a.check = k == n - 1;  // the wide form tests the last step of the run (values stay non-finite)
+        if (fused_noise) {
+            a.noise_step = (const uint64_t*)(h->ws + h->L.noise);
+            a.noise_offset = k;
+            noise_coefs<R>(c, a.noise_a, a.noise_b, a.noise_k0, a.noise_k1);
+        }
         if (c.drive && launch_drive_phasors<R>(h, k, s) != hipSuccess)
             return fail(PHX_EHIP, "drive phasor launch failed");
         hipEvent_t t0 = nullptr;
@@ -255,7 +261,7 @@ phx_status rk4_fused_launches(phx_handle* h, int64_t n, hipStream_t s)
             if (e == hipSuccess) e = timing_end(h, t0, K_IMAG_NORM);
             if (e != hipSuccess) return fail(PHX_EHIP, "imaginary-time norm launch: %s", hipGetErrorString(e));
         }
-        if (c.noise > 0.0) {
+        if (c.noise > 0.0 && !fused_noise) {
             e = timing_begin(h, &t0);
             if (e == hipSuccess) e = launch_noise<R>(h, S[cur], SN[cur], k, s);
             if (e == hipSuccess) e = timing_end(h, t0, K_NOISE);

@@ -12,13 +12,14 @@
 
 namespace phx {
 
-template <bool RES, bool HASV, bool GHOSTS, bool YZERO, int K, int PF, int WPE, bool CHECK>
+template <bool RES, bool HASV, bool GHOSTS, bool YZERO, int K, int PF, int WPE, bool CHECK, bool NOISE>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE)))
 void rk4_stream_wide_kernel(const StepArgs<float> a)
 {
     const int t = xcd_tile(blockIdx.x, gridDim.x);
     const int band = t / a.tiles_x, strip = t - band * a.tiles_x;
-    if (stream_band_wide<RES, HASV, GHOSTS, YZERO, K, PF, CHECK>(a, strip, band, a.band_rows, (band & 1) ? -1 : 1))
+    if (stream_band_wide<RES, HASV, GHOSTS, YZERO, K, PF, CHECK, NOISE>(a, strip, band, a.band_rows,
+                                                                       (band & 1) ? -1 : 1))
         a.flag[0] = 1u;  // benign race: every writer stores 1
 }
 
@@ -37,10 +38,22 @@ static void launch_wide_k(const StepArgs<float>& a, hipStream_t s)
     // the checking variant (the last step of a run) needs a few more registers: with
     // the reservoir it is built for 2 waves per SIMD
     constexpr int WPE_CHECK = RES ? 2 : WPE;
+    // with the increment drawn in the step the reservoir variants need more than 168
+    // registers: built for 2 waves per SIMD
+    constexpr int WPE_NOISE = RES ? 2 : WPE;
+    if constexpr (!GHOSTS && !YZERO) {  // the increment in the step: periodic grids (noise_in_step)
+        if (a.noise_step) {
+            if (a.check)
+                rk4_stream_wide_kernel<RES, HASV, GHOSTS, YZERO, K, PF, WPE_CHECK, true, true><<<a.tiles, 64, 0, s>>>(a);
+            else
+                rk4_stream_wide_kernel<RES, HASV, GHOSTS, YZERO, K, PF, WPE_NOISE, false, true><<<a.tiles, 64, 0, s>>>(a);
+            return;
+        }
+    }
     if (a.check)
-        rk4_stream_wide_kernel<RES, HASV, GHOSTS, YZERO, K, PF, WPE_CHECK, true><<<a.tiles, 64, 0, s>>>(a);
+        rk4_stream_wide_kernel<RES, HASV, GHOSTS, YZERO, K, PF, WPE_CHECK, true, false><<<a.tiles, 64, 0, s>>>(a);
     else
-        rk4_stream_wide_kernel<RES, HASV, GHOSTS, YZERO, K, PF, WPE, false><<<a.tiles, 64, 0, s>>>(a);
+        rk4_stream_wide_kernel<RES, HASV, GHOSTS, YZERO, K, PF, WPE, false, false><<<a.tiles, 64, 0, s>>>(a);
 }
 
 template <bool RES, bool HASV, int K, int PF>

@@ -154,6 +154,20 @@ phx_status set_info_rk45(phx_handle* h, const phx_info* in);
 template <typename R> hipError_t launch_noise(const phx_handle* h, void* psi, const void* n, int64_t offset,
                                               hipStream_t s);
 hipError_t advance_noise_step(const phx_handle* h, int64_t by, hipStream_t s);
+// The increment's variance a n + b (a = nu R dt / (4 dV), b = nu gamma_c dt / (4 dV),
+// formed in double) and the generator key (the seed's two words).
+template <typename R>
+inline void noise_coefs(const phx_config& c, R& a, R& b, uint32_t& k0, uint32_t& k1)
+{
+    const double scale = c.noise * c.dt / (4.0 * c.dx * c.dy);
+    a = (R)(scale * c.R);
+    b = (R)(scale * c.gamma_c);
+    k0 = (uint32_t)c.seed;
+    k1 = (uint32_t)(c.seed >> 32);
+}
+// The wide streaming step adds the increment itself before its final store (one
+// component, complex64, periodic in x and y); elsewhere a separate pass follows the step.
+bool noise_in_step(const phx_config& c, const StepShapeId& sh);
 hipError_t set_noise_step(const phx_handle* h, int64_t value, hipStream_t s);
 // Drive phasors exp(-i omega t_s) of the four RK4 stage times of the step with index
 // base + offset, written to the workspace (one thread; graph-replay safe).

@@ -181,6 +181,12 @@ bool step_shape_fits(const phx_config& c, int waves)
 
 bool wide_shape(int waves) { return waves == 2 || waves == 3; }
 
+bool noise_in_step(const phx_config& c, const StepShapeId& sh)
+{
+    return wide_shape(sh.waves) && c.precision == PHX_C64 && c.components == 1 && c.bc_x == PHX_BC_PERIODIC &&
+           c.bc_y == PHX_BC_PERIODIC && !c.drive && !c.imag_time && c.nx % 2 == 0;
+}
+
 int wide_strips(int nx) { return (nx + 119) / 120; }
 
 // Band height of a wide shape.  rows > 0 is taken as given; rows = 0 picks the

@@ -45,6 +45,12 @@ struct StepArgs {
     int comps;  // 2: the spinor streaming kernel (component stride nx*ny)
     int band_rows;        // wide streaming form: rows per band (a launch argument)
     int check;            // wide streaming form: test the stored values for non-finite ones
+    // wide streaming form with the Wiener increment added before the final store
+    // (null: no noise): step index *noise_step + noise_offset, variance a n + b, key
+    const uint64_t* noise_step;
+    int64_t noise_offset;
+    R noise_a, noise_b;
+    uint32_t noise_k0, noise_k1;
 };
 
 // value held by lane-1 (lane 0 receives 0) and by lane+1 (lane 63 receives 0):

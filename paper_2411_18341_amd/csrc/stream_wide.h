@@ -25,6 +25,7 @@
 // even (a column pair never straddles the periodic seam or the right edge).
 #pragma once
 
+#include "philox.h"
 #include "stream_body.h"
 
 namespace phx {
@@ -66,8 +67,10 @@ __device__ __forceinline__ void wstore2(wf2 v, __amdgpu_buffer_rsrc_t r, int vof
 // j-4 .. j+PF must fit: PF <= K - 5) and must divide 24.  CHECK: returns true when a
 // stored value is not finite (else false without testing: a non-finite value never
 // becomes finite again in later steps, so testing the last step of a run of steps
-// detects it).
-template <bool RES, bool HASV, bool GHOSTS, bool YZERO, int K, int PF, bool CHECK>
+// detects it).  NOISE: each stored pair of cells (2p, 2p + 1) first gets its Wiener
+// increment, drawn exactly as the separate noise pass draws it (one generator call
+// per pair, the reservoir value after the step), so both give the same bits.
+template <bool RES, bool HASV, bool GHOSTS, bool YZERO, int K, int PF, bool CHECK, bool NOISE = false>
 __device__ __forceinline__ bool stream_band_wide(const StepArgs<float>& a, int strip, int band, int B, int dir)
 {
     using C = float2;
@@ -96,6 +99,9 @@ __device__ __forceinline__ bool stream_band_wide(const StepArgs<float>& a, int s
     const bool out_col = lane >= 2 && lane < 62 && gi < a.nx;
     const int o8 = out_col ? gi * 8 : kOutOfRange;
     const int o4 = out_col ? gi * 4 : kOutOfRange;
+
+    static_assert(!NOISE || (!GHOSTS && !YZERO), "the increment is drawn for periodic grids");
+    const uint64_t nstep = NOISE ? *a.noise_step + (uint64_t)a.noise_offset : 0u;  // uniform
 
     // rings: [slot][cell of the pair]
     C sp[K][2];
@@ -265,6 +271,19 @@ __device__ __forceinline__ bool stream_band_wide(const StepArgs<float>& a, int s
                 const int r = j - 4 * dir;
                 const bool st = r >= b0 && r < b0 + B && r < a.ny;  // uniform
                 const int rr = st ? r : 0;
+                if (NOISE && st) {
+                    const uint32_t pair = (uint32_t)(r * a.nx + gi) >> 1;  // nx and gi even
+                    const noise::Philox4 x = noise::philox4x32_10(pair, 0u, (uint32_t)nstep, (uint32_t)(nstep >> 32),
+                                                                  a.noise_k0, a.noise_k1);
+                    const C lo = noise::add_noise<float, RES>(C{y[0], y[1]}, yn[0], a.noise_a, a.noise_b, x.x[0],
+                                                              x.x[1]);
+                    const C hi = noise::add_noise<float, RES>(C{y[2], y[3]}, yn[1], a.noise_a, a.noise_b, x.x[2],
+                                                              x.x[3]);
+                    y[0] = lo.x;
+                    y[1] = lo.y;
+                    y[2] = hi.x;
+                    y[3] = hi.y;
+                }
                 wstore4(wf4{y[0], y[1], y[2], y[3]}, st ? rpo : rnull, o8, rr * row8);
                 if (RES) wstore2(wf2{yn[0], yn[1]}, st ? rno : rnull, o4, rr * row4);
                 if (CHECK) {

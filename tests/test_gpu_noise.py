@@ -64,6 +64,28 @@ def test_noise_launch_paths(steps, graph_steps, family):
     assert e_psi <= TOL[C128] and e_n <= TOL[C128]
 
 
+@pytest.mark.parametrize("shape", [(2, 0), (3, 0), (2, 40)])
+@pytest.mark.parametrize("graph_steps", [-1, 4])
+def test_noise_in_wide_step_bitwise(shape, graph_steps):
+    """The wide streaming step draws the increment itself before its final store
+    (periodic grid, complex64); the same steps on the one-column walk followed by the
+    separate noise pass give the same bits, with direct launches and graph replays,
+    and both match the oracle."""
+    ph, psi, n, V, P = workload("driven", 240, 90, (0, 0), seed=3)
+    q = quantize(C64, psi, n, V, P)
+    outs = []
+    for tile in (shape, (1, 40)):
+        run = GpuRun(ph, *q, precision=C64, noise=0.7, seed=77, tile_wx=tile[0], tile_rows=tile[1],
+                     graph_steps=graph_steps)
+        run.step(9)
+        outs.append(run.state())
+        run.close()
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+    o_psi, o_n = oracle.rk4_noise(oracle_physics(ph), q[0], q[1], q[2], q[3], dt=ph.dt, steps=9, nu=0.7,
+                                  seed=77, step0=0)
+    assert rel_l2(outs[0][0], o_psi) <= TOL[C64] and rel_l2(outs[0][1], o_n) <= TOL[C64]
+
+
 @pytest.mark.parametrize("family", FAMILIES)
 def test_noise_restart_bitwise(family):
     """Stopping, restoring the state and phx_info, and going on continues the noise
