@@ -226,13 +226,16 @@ def test_vacuum_occupation_and_renormalized_density(family):
 def test_batch_noise_parity(precision):
     """Noisy ensembles in one batched launch per step: instances of different sizes,
     each with its own seed, one parameter set without noise; two calls (the noise step
-    index runs on through the descriptor).  Every instance equals the oracle's noisy
-    run with its seed, and instance 0 equals a single-grid handle with that seed bit
-    for bit (the same region kernel and the same increments)."""
+    index runs on through the descriptor).  Instances of even width (complex64) take
+    the wide walk, which draws their increments itself; the others get them from the
+    noise pass.  Every instance equals the oracle's noisy run with its seed, instance 0
+    equals a single-grid handle with that seed bit for bit (the same region kernel and
+    the same increments), and in complex64 so does instance 1 against a single-grid
+    wide walk; the instances without noise stay the deterministic runs."""
     import torch
-    grids = [(97, 61), (64, 64), (33, 70), (128, 40), (51, 50)]
-    pidx = [0, 0, 1, 0, 0]
-    seeds = [11, 12, 13, (1 << 40) + 5, 99]
+    grids = [(97, 61), (64, 64), (33, 70), (128, 40), (51, 50), (36, 44)]
+    pidx = [0, 0, 1, 0, 0, 1]
+    seeds = [11, 12, 13, (1 << 40) + 5, 99, 7]
     nu = 0.8
     ph0 = workload("driven", 8, 8, (0, 0))[0]
     cfgs = [phx.config_from_physics(ph0, precision=precision, noise=nu),
@@ -267,6 +270,15 @@ def test_batch_noise_parity(precision):
     single.close()
     assert np.array_equal(s_psi[0], b.view(b.psi, 0).cpu().numpy().astype(np.complex128))
     assert np.array_equal(s_n[0], b.view(b.n, 0).cpu().numpy().astype(np.float64))
-    b_noisy = b.view(b.psi, 2).cpu().numpy()
-    d_psi, _ = oracle.rk4(oracle_physics(cases[2][0]), *cases[2][1], dt=ph.dt, steps=5)
-    assert rel_l2(b_noisy.astype(np.complex128)[None], d_psi) <= TOL[precision]  # the nu = 0 instance
+    for k in (2, 5):  # the nu = 0 instances (one-column and, in complex64, wide walk)
+        b_det = b.view(b.psi, k).cpu().numpy()
+        d_psi, _ = oracle.rk4(oracle_physics(cases[k][0]), *cases[k][1], dt=ph.dt, steps=5)
+        assert rel_l2(b_det.astype(np.complex128)[None], d_psi) <= TOL[precision]
+    if precision == C64:
+        ph, q = cases[1]
+        single = GpuRun(ph, *q, precision=precision, noise=nu, seed=seeds[1], tile_wx=2, tile_rows=0)
+        single.step(5)
+        s_psi, s_n = single.state()
+        single.close()
+        assert np.array_equal(s_psi[0], b.view(b.psi, 1).cpu().numpy().astype(np.complex128))
+        assert np.array_equal(s_n[0], b.view(b.n, 1).cpu().numpy().astype(np.float64))
