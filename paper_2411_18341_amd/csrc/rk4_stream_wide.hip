@@ -24,11 +24,12 @@ void rk4_stream_wide_kernel(const StepArgs<float> a)
 }
 
 // Waves per SIMD the register budget of the (non-checking) kernel is set for: 3 with
-// the 8-row ring (2 when the reservoir comes with a potential or a zero boundary,
-// whose extra registers would not fit in 168), 2 with the 12-row ring.
-int wide_waves_per_simd(int ring, bool reservoir, bool has_v, bool ghosts)
+// the 8-row ring (2 when the reservoir comes with a potential, a zero boundary or the
+// Wiener increment drawn in the step, whose extra registers would not fit in 168), 2
+// with the 12-row ring.
+int wide_waves_per_simd(int ring, bool reservoir, bool has_v, bool ghosts, bool noise)
 {
-    return ring == 8 && !(reservoir && (has_v || ghosts)) ? 3 : 2;
+    return ring == 8 && !(reservoir && (has_v || ghosts || noise)) ? 3 : 2;
 }
 
 template <bool RES, bool HASV, bool GHOSTS, bool YZERO, int K, int PF>

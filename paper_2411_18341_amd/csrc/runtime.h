@@ -144,7 +144,7 @@ template <typename R> struct StepArgs;
 bool wide_shape(int waves);
 int wide_strips(int nx);
 int wide_band_rows(const phx_config& c, const StepShapeId& sh, bool has_v, int cus);
-int wide_waves_per_simd(int ring, bool reservoir, bool has_v, bool ghosts);
+int wide_waves_per_simd(int ring, bool reservoir, bool has_v, bool ghosts, bool noise);
 hipError_t launch_stream_wide(bool reservoir, bool has_v, int ring, const StepArgs<float>& a, hipStream_t s);
 int rk4_family(const phx_config& c);
 phx_status step_rk45(phx_handle* h, int64_t n, phx_info* out);

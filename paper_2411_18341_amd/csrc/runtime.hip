@@ -196,7 +196,8 @@ int wide_band_rows(const phx_config& c, const StepShapeId& sh, bool has_v, int c
 {
     if (sh.rows > 0) return sh.rows;
     const bool ghosts = c.bc_x == PHX_BC_ZERO || c.bc_y == PHX_BC_ZERO;
-    const int per_simd = wide_waves_per_simd(sh.waves == 2 ? 8 : 12, c.reservoir != 0, has_v, ghosts);
+    const bool noise = c.noise > 0.0 && noise_in_step(c, sh);
+    const int per_simd = wide_waves_per_simd(sh.waves == 2 ? 8 : 12, c.reservoir != 0, has_v, ghosts, noise);
     const int slots = (cus > 0 ? cus : 256) * 4 * per_simd;
     const int per_strip = slots / wide_strips(c.nx);
     const int bands = per_strip > 0 ? per_strip : 1;
