@@ -143,7 +143,7 @@ hipError_t launch_rk4_step(bool reservoir, bool has_v, const StepShapeId& sh, co
     if (a.E) return sh.waves == 1 ? launch_stream_drive<R>(reservoir, has_v, sh.rows, a, s) : hipErrorInvalidValue;
     if (wide_shape(sh.waves)) {
         if constexpr (sizeof(R) == 4) {
-            if (a.comps != 1 || a.imag_partials) return hipErrorInvalidValue;
+            if (a.comps != 1) return hipErrorInvalidValue;
             return launch_stream_wide(reservoir, has_v, sh.waves == 2 ? 8 : 12, a, s);
         }
         return hipErrorInvalidValue;
@@ -257,7 +257,8 @@ phx_status rk4_fused_launches(phx_handle* h, int64_t n, hipStream_t s)
         cur ^= 1;
         if (c.imag_time) {  // the scale that restores the norm, applied by the next step
             e = timing_begin(h, &t0);
-            if (e == hipSuccess) e = launch_imag_finish(h, 4 * a.tiles, s);
+            // one norm partial per wave: 4 per workgroup of the one-column walk, 1 for the wide
+            if (e == hipSuccess) e = launch_imag_finish(h, wide_shape(sh.waves) ? a.tiles : 4 * a.tiles, s);
             if (e == hipSuccess) e = timing_end(h, t0, K_IMAG_NORM);
             if (e != hipSuccess) return fail(PHX_EHIP, "imaginary-time norm launch: %s", hipGetErrorString(e));
         }

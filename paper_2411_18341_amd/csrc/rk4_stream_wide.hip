@@ -12,15 +12,24 @@
 
 namespace phx {
 
-template <bool RES, bool HASV, bool GHOSTS, bool YZERO, int K, int PF, int WPE, bool CHECK, bool NOISE>
+// IMAG (imaginary time): the wave of tile t writes the FP64 norm partial of its cells
+// to a.imag_partials[t], reduced over the lanes in a fixed butterfly order.
+template <bool RES, bool HASV, bool GHOSTS, bool YZERO, int K, int PF, int WPE, bool CHECK, bool NOISE,
+          bool IMAG = false>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE)))
 void rk4_stream_wide_kernel(const StepArgs<float> a)
 {
     const int t = xcd_tile(blockIdx.x, gridDim.x);
     const int band = t / a.tiles_x, strip = t - band * a.tiles_x;
-    if (stream_band_wide<RES, HASV, GHOSTS, YZERO, K, PF, CHECK, NOISE>(a, strip, band, a.band_rows,
-                                                                       (band & 1) ? -1 : 1))
+    double nrm = 0.0;
+    if (stream_band_wide<RES, HASV, GHOSTS, YZERO, K, PF, CHECK, NOISE, IMAG>(a, strip, band, a.band_rows,
+                                                                             (band & 1) ? -1 : 1, &nrm))
         a.flag[0] = 1u;  // benign race: every writer stores 1
+    if constexpr (IMAG) {
+#pragma unroll
+        for (int m = 32; m >= 1; m >>= 1) nrm += __shfl_xor(nrm, m, 64);
+        if (threadIdx.x == 0) a.imag_partials[t] = nrm;
+    }
 }
 
 // Waves per SIMD the register budget of the (non-checking) kernel is set for: 3 with
@@ -42,6 +51,16 @@ static void launch_wide_k(const StepArgs<float>& a, hipStream_t s)
     // with the increment drawn in the step the reservoir variants need more than 168
     // registers: built for 2 waves per SIMD
     constexpr int WPE_NOISE = RES ? 2 : WPE;
+    if constexpr (!RES) {  // imaginary time (no reservoir)
+        if (a.imag_partials) {
+            if (a.check)
+                rk4_stream_wide_kernel<RES, HASV, GHOSTS, YZERO, K, PF, WPE_CHECK, true, false, true>
+                    <<<a.tiles, 64, 0, s>>>(a);
+            else
+                rk4_stream_wide_kernel<RES, HASV, GHOSTS, YZERO, K, PF, WPE, false, false, true><<<a.tiles, 64, 0, s>>>(a);
+            return;
+        }
+    }
     if constexpr (!GHOSTS && !YZERO) {  // the increment in the step: periodic grids (noise_in_step)
         if (a.noise_step) {
             if (a.check)

@@ -62,9 +62,12 @@ phx_status validate_config(const phx_config* c)
                                 "the wide streaming form with the device-filling band height)");
     if (c->tile_wx != 0) {
         if (c->integrator == PHX_RK4 && rk4_family(*c) == PHX_KERNEL_STEP) {
-            if ((c->imag_time || c->drive || c->components == 2) && c->tile_wx != 1)
-                return fail(PHX_EINVAL, "imaginary time, the drive and the spinor on the whole-step kernel use the "
-                                        "streaming shapes (tile_wx 1)");
+            if ((c->drive || c->components == 2) && c->tile_wx != 1)
+                return fail(PHX_EINVAL, "the drive and the spinor on the whole-step kernel use the streaming shapes "
+                                        "(tile_wx 1)");
+            if (c->imag_time && c->tile_wx != 1 && !wide_shape(c->tile_wx))
+                return fail(PHX_EINVAL, "imaginary time on the whole-step kernel uses the streaming shapes (tile_wx "
+                                        "1, 2 or 3)");
             if ((c->drive || c->components == 2) && !drive_stream_rows(c->tile_rows))
                 return fail(PHX_EINVAL, "the drive and the spinor on the whole-step kernel use bands of 40 or 64 rows");
             if (!valid_step_shape(c->precision, c->tile_wx, c->tile_rows))
@@ -136,8 +139,12 @@ Layout make_layout(const phx_config& c)
         // the streaming kernel (bands of at least 40 rows)
         L.imag = take(2 * sizeof(double));
         const int64_t stream_waves = 4 * (int64_t)((c.nx + 56 * 4 - 1) / (56 * 4)) * ((c.ny + 39) / 40);
+        // the wide walk: one wave per band of one strip, bands of at least 8 rows
+        const int64_t wide_waves = (int64_t)wide_strips(c.nx) * ((c.ny + 7) / 8);
         const int64_t blocks = imag_norm_blocks(c.nx * (int64_t)c.ny * c.components);
-        L.imag_partials = take((size_t)(stream_waves > blocks ? stream_waves : blocks) * sizeof(double));
+        int64_t slots = stream_waves > blocks ? stream_waves : blocks;
+        if (wide_waves > slots) slots = wide_waves;
+        L.imag_partials = take((size_t)slots * sizeof(double));
     }
     if (c.integrator == PHX_RK4) {
         L.family = rk4_family(c);
@@ -174,7 +181,8 @@ Layout make_layout(const phx_config& c)
 bool step_shape_fits(const phx_config& c, int waves)
 {
     const double bytes = (double)c.nx * c.ny * c.components * (c.precision == PHX_C64 ? 8.0 : 16.0);
-    if ((c.imag_time || c.drive || c.components == 2) && waves != 1) return false;  // streaming form only
+    if ((c.drive || c.components == 2) && waves != 1) return false;  // streaming form only
+    if (c.imag_time && waves != 1 && !wide_shape(waves)) return false;
     if (wide_shape(waves) && (c.precision != PHX_C64 || c.nx % 2 != 0)) return false;
     return waves > 3 || bytes < 2147483648.0 - 256.0;
 }

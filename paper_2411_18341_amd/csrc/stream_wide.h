@@ -69,9 +69,14 @@ __device__ __forceinline__ void wstore2(wf2 v, __amdgpu_buffer_rsrc_t r, int vof
 // becomes finite again in later steps, so testing the last step of a run of steps
 // detects it).  NOISE: each stored pair of cells (2p, 2p + 1) first gets its Wiener
 // increment, drawn exactly as the separate noise pass draws it (one generator call
-// per pair, the reservoir value after the step), so both give the same bits.
-template <bool RES, bool HASV, bool GHOSTS, bool YZERO, int K, int PF, bool CHECK, bool NOISE = false>
-__device__ __forceinline__ bool stream_band_wide(const StepArgs<float>& a, int strip, int band, int B, int dir)
+// per pair, the reservoir value after the step), so both give the same bits.  IMAG:
+// imaginary time (no reservoir): the derivative is rotated by -i, the input is
+// multiplied by the scale a.imag_slots[1] that restores the previous step's norm, and
+// *norm receives this lane's FP64 sum of |psi_out|^2 over the cells it stores.
+template <bool RES, bool HASV, bool GHOSTS, bool YZERO, int K, int PF, bool CHECK, bool NOISE = false,
+          bool IMAG = false>
+__device__ __forceinline__ bool stream_band_wide(const StepArgs<float>& a, int strip, int band, int B, int dir,
+                                                 double* norm = nullptr)
 {
     using C = float2;
     static_assert(24 % K == 0 && PF <= K - 5 && PF >= 1, "input ring");
@@ -101,6 +106,9 @@ __device__ __forceinline__ bool stream_band_wide(const StepArgs<float>& a, int s
     const int o4 = out_col ? gi * 4 : kOutOfRange;
 
     static_assert(!NOISE || (!GHOSTS && !YZERO), "the increment is drawn for periodic grids");
+    static_assert(!(IMAG && (RES || NOISE)), "imaginary time has no reservoir and no noise");
+    const float sc = IMAG ? (float)a.imag_slots[1] : 1.f;  // uniform
+    double nrm = 0.0;
     const uint64_t nstep = NOISE ? *a.noise_step + (uint64_t)a.noise_offset : 0u;  // uniform
 
     // rings: [slot][cell of the pair]
@@ -143,7 +151,10 @@ __device__ __forceinline__ bool stream_band_wide(const StepArgs<float>& a, int s
         const int rr = rw < 0 ? 0 : rw;
         const wf4 v = wload4(rpi, v8, rr * row8);
         const float rk = (YZERO && rw < 0) ? 0.f : 1.f;
-        if (YZERO) {
+        if (IMAG) {  // the input times the restoring scale (a ghost row reads 0 through rk)
+            sp[s][0] = C{rk * (v.x * sc), rk * (v.y * sc)};
+            sp[s][1] = C{rk * (v.z * sc), rk * (v.w * sc)};
+        } else if (YZERO) {
             sp[s][0] = C{rk * v.x, rk * v.y};
             sp[s][1] = C{rk * v.z, rk * v.w};
         } else {
@@ -190,10 +201,10 @@ __device__ __forceinline__ bool stream_band_wide(const StepArgs<float>& a, int s
         const float lry0 = lane_prev(cur[1].y) + cur[1].y;
         const float lrx1 = cur[0].x + lane_next(cur[0].x);
         const float lry1 = cur[0].y + lane_next(cur[0].y);
-        cell_rhs<float, RES>(c, cur[0], lrx0, lry0, up[0].x + dn[0].x, up[0].y + dn[0].y, nn[0], pv[0], kv[0],
-                             fx[0], fy[0], fn[0]);
-        cell_rhs<float, RES>(c, cur[1], lrx1, lry1, up[1].x + dn[1].x, up[1].y + dn[1].y, nn[1], pv[1], kv[1],
-                             fx[1], fy[1], fn[1]);
+        cell_rhs<float, RES, IMAG>(c, cur[0], lrx0, lry0, up[0].x + dn[0].x, up[0].y + dn[0].y, nn[0], pv[0],
+                                   kv[0], fx[0], fy[0], fn[0]);
+        cell_rhs<float, RES, IMAG>(c, cur[1], lrx1, lry1, up[1].x + dn[1].x, up[1].y + dn[1].y, nn[1], pv[1],
+                                   kv[1], fx[1], fy[1], fn[1]);
     };
 
     unsigned bad = 0u;
@@ -285,6 +296,11 @@ __device__ __forceinline__ bool stream_band_wide(const StepArgs<float>& a, int s
                     y[3] = hi.y;
                 }
                 wstore4(wf4{y[0], y[1], y[2], y[3]}, st ? rpo : rnull, o8, rr * row8);
+                if constexpr (IMAG) {
+                    const bool stn = st && out_col;
+                    nrm += stn ? (double)y[0] * y[0] + (double)y[1] * y[1] : 0.0;
+                    nrm += stn ? (double)y[2] * y[2] + (double)y[3] * y[3] : 0.0;
+                }
                 if (RES) wstore2(wf2{yn[0], yn[1]}, st ? rno : rnull, o4, rr * row4);
                 if (CHECK) {
                     unsigned nf = (unsigned)!isfinite(y[0]) | (unsigned)!isfinite(y[1]) |
@@ -295,6 +311,7 @@ __device__ __forceinline__ bool stream_band_wide(const StepArgs<float>& a, int s
             }
         }
     }
+    if constexpr (IMAG) *norm = nrm;
     return bad != 0u;
 }
 

@@ -156,7 +156,7 @@ def test_drive_config_validation():
 
 def test_imag_time_config_validation():
     """Imaginary time: the conservative equation; one component runs on the streaming
-    whole-step kernel (region shapes rejected), the stage-fused family on request or
+    whole-step kernel, one-column or wide walk (region shapes rejected), the stage-fused family on request or
     for the spinor; RK4's stability bound on the negative real axis (2.78) replaces the
     imaginary-axis one."""
     stage = phx.phx_workspace_bytes(good_config(kernel=phx.PHX_KERNEL_STAGE))
@@ -164,6 +164,8 @@ def test_imag_time_config_validation():
     assert phx.phx_workspace_bytes(good_config(imag_time=True, kernel=phx.PHX_KERNEL_STAGE)) == stage + 256 + 256
     assert phx.phx_workspace_bytes(good_config(imag_time=True)) == step + 256 + 256
     phx.phx_workspace_bytes(good_config(imag_time=True, tile_wx=1, tile_rows=64))
+    phx.phx_workspace_bytes(good_config(imag_time=True, tile_wx=2, tile_rows=0))    # the wide walk
+    phx.phx_workspace_bytes(good_config(imag_time=True, tile_wx=3, tile_rows=8))
     phx.phx_workspace_bytes(good_config(imag_time=True, components=2, delta_lt=0.1))   # stage-fused
     for bad in (dict(reservoir=True), dict(gamma_c=0.1), dict(R=0.1), dict(noise=1.0), dict(drive=True),
                 dict(tile_wx=8, tile_rows=4)):

@@ -82,6 +82,29 @@ def test_imag_streaming_shapes(precision, bc):
             assert e <= TOL[precision], (shape, nx, ny, e)
 
 
+@pytest.mark.parametrize("bc", [(0, 0), (1, 1), (0, 1)])
+@pytest.mark.parametrize("shape", [(2, 0), (3, 0), (2, 40)])
+def test_imag_wide_walk(shape, bc):
+    """The wide walk (two columns per lane, one norm partial per wave) in imaginary
+    time, complex64, on grids of even width spanning several strips and bands, odd and
+    even step counts over two calls; the norm is the one the call began with."""
+    for nx, ny, steps in ((130, 97, 5), (240, 75, 4)):
+        ph, psi, V = case("scalar", nx, ny, bc, 7)
+        q = quantize(C64, psi, None, V, None)
+        run = GpuRun(ph, q[0], None, q[2], None, precision=C64, imag_time=True, kernel=phx.PHX_KERNEL_STEP,
+                     tile_wx=shape[0], tile_rows=shape[1], graph_steps=2)
+        run.step(steps)
+        run.step(3)
+        g_psi, _ = run.state()
+        run.close()
+        o_psi = oracle.rk4_imag(oracle_physics(ph), q[0], V=q[2], dt=ph.dt, steps=steps)
+        o_psi = oracle.rk4_imag(oracle_physics(ph), o_psi, V=q[2], dt=ph.dt, steps=3)
+        e = rel_l2(g_psi, o_psi)
+        assert e <= TOL[C64], (shape, nx, ny, e)
+        n0 = np.sum(np.abs(q[0]) ** 2)
+        assert np.sum(np.abs(g_psi) ** 2) == pytest.approx(n0, rel=1e-5)
+
+
 def test_imag_autotune_keeps_parity(tmp_path, monkeypatch):
     monkeypatch.setenv("PHX_TUNE_CACHE", str(tmp_path / "tune.json"))
     ph, psi, V = case("scalar", 300, 170, (1, 1), 9)
