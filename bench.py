@@ -209,7 +209,7 @@ def main():
         ph.dt = 5e-5
         n0 = P = None
         workload = (f"imaginary-time ground state of the scalar GP (g 1) in a harmonic trap, {args.n}x{args.n}, "
-                    f"zero boundary, {'complex64' if real_bytes == 4 else 'complex128'}, dx 0.01, RK4 dtau {ph.dt}")
+                    f"periodic, {'complex64' if real_bytes == 4 else 'complex128'}, dx 0.01, RK4 dtau {ph.dt}")
     else:
         ph, psi0, n0, P = inputs.driven(args.n)
         workload = (f"driven-dissipative GP + reservoir, {args.n}x{args.n}, periodic, "

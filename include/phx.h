@@ -84,8 +84,10 @@ typedef struct phx_config {
                                whole-step kernel: waves per workgroup of the region form
                                (4, 8, 12, 16), 1 for the streaming form, 2 or 3 for the wide
                                streaming form (two columns per lane; complex64, one
-                               component, no drive or imaginary time, even nx; 2: 8-row
-                               input ring, 3: 12-row ring)                                 */
+                               component, no drive, even nx; 2: 8-row input ring, 3: 12-row
+                               ring; with the noise on periodic grids the increment is
+                               drawn in the step, with imaginary time the norm partials are
+                               written per wave)                                           */
     int32_t tile_rows;      /* rows per wave (stage-fused: 1..64); streaming form: rows per
                                band (40, 64, 88, 112); wide streaming form: rows per band
                                (8..4096), or 0 for the height that fills the device with
@@ -119,7 +121,8 @@ typedef struct phx_config {
                                of the conservative equation (reservoir, gamma_c, R, noise and
                                drive all off, else PHX_EINVAL): RK4 steps of
                                d psi/d tau = -(1/hbar) H psi (one component: the streaming
-                               whole-step kernel when the state is under 2 GiB, else the
+                               whole-step kernel, one-column or wide walk, when the state is
+                               under 2 GiB, else the
                                stage-fused kernels; two components: stage-fused), each
                                followed by scaling psi so that its total norm
                                dx dy sum_s,cells |psi_s|^2 equals the value it had when the

@@ -176,7 +176,7 @@ Layout make_layout(const phx_config& c)
 
 // The streaming shapes (waves 1, and 2 or 3 for the wide form) address their arrays
 // through 32-bit buffer offsets: the complex state array must stay below 2 GiB.  The
-// wide form runs complex64 with one component (no drive, no imaginary time) on grids
+// wide form runs complex64 with one component (no drive; imaginary time allowed) on grids
 // of even width.
 bool step_shape_fits(const phx_config& c, int waves)
 {
