@@ -120,10 +120,10 @@ typedef struct phx_config {
     int32_t imag_time;      /* 1: imaginary-time propagation (t -> -i tau, named in Sec. 6)
                                of the conservative equation (reservoir, gamma_c, R, noise and
                                drive all off, else PHX_EINVAL): RK4 steps of
-                               d psi/d tau = -(1/hbar) H psi (one component: the streaming
-                               whole-step kernel, one-column or wide walk, when the state is
-                               under 2 GiB, else the
-                               stage-fused kernels; two components: stage-fused), each
+                               d psi/d tau = -(1/hbar) H psi (the streaming whole-step
+                               kernel when the state is under 2 GiB: one component on the
+                               one-column or wide walk, two on the spinor walk; else, or
+                               on request, the stage-fused kernels), each
                                followed by scaling psi so that its total norm
                                dx dy sum_s,cells |psi_s|^2 equals the value it had when the
                                phx_step call began (deterministic FP64 reduction on the

@@ -64,8 +64,19 @@ __global__ __launch_bounds__(256) void norm_partials_kernel(const typename phx::
 __global__ __launch_bounds__(256) void norm_finish_kernel(const double* __restrict__ partials, int blocks,
                                                           double cell_area, int mode, double* __restrict__ slots)
 {
-    double s = 0.0;
-    for (int b = threadIdx.x; b < blocks; b += 256) s += partials[b];
+    // eight independent accumulators per thread keep eight loads in flight (the
+    // partials were just written by other XCDs: each load is a far miss); the order of
+    // the additions depends on `blocks` alone
+    double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    int b = threadIdx.x;
+    for (; b + 7 * 256 < blocks; b += 8 * 256) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) a[k] += partials[b + k * 256];
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+        if (b + k * 256 < blocks) a[k] += partials[b + k * 256];
+    double s = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
     s = block_sum_256(s);
     if (threadIdx.x == 0) {
         const double N = cell_area * s;

@@ -28,7 +28,7 @@ namespace phx {
 //   fn_s = P_s - (gamma_r + R rho_s) n_s,
 // X_o = dir (next(dy_o) - prev(dy_o)), sgn = +1 for psi_+, -1 for psi_-; dir bxy is passed in as
 // bxyd (dir is +-1: the same value bit for bit as multiplying X by dir).
-template <typename R, bool RES>
+template <typename R, bool RES, bool IMAG = false>
 __device__ __forceinline__ void spinor_rhs(const Coef<R>& c, const typename cvec<R>::type (&cur)[2],
                                            const typename cvec<R>::type (&lr)[2],
                                            const typename cvec<R>::type (&ud)[2],
@@ -61,12 +61,25 @@ __device__ __forceinline__ void spinor_rhs(const Coef<R>& c, const typename cvec
         const R sb = s == 0 ? -bxyd : bxyd;
         f[s].x = fma(sb, xx, fma(u, p.x, fma(om, p.y, -ty)));
         f[s].y = fma(sb, xy, fma(u, p.y, fma(-om, p.x, tx)));
+        if constexpr (IMAG) {  // imaginary time: -i f
+            const R t = f[s].x;
+            f[s].x = f[s].y;
+            f[s].y = -t;
+        }
     }
 }
 
-template <typename R, bool RES, bool HASV, bool GHOSTS, bool YZERO, int B>
-__device__ __forceinline__ bool stream_band_spinor(const StepArgs<R>& a, int strip, int band, int dir)
+// IMAG: imaginary time (no reservoirs): each stage's derivative is rotated by -i, the
+// input is multiplied by the scale a.imag_slots[1] that restores the previous step's
+// norm, and *norm receives this lane's FP64 sum of |psi_out|^2 over both components of
+// the cells it stores.
+template <typename R, bool RES, bool HASV, bool GHOSTS, bool YZERO, int B, bool IMAG = false>
+__device__ __forceinline__ bool stream_band_spinor(const StepArgs<R>& a, int strip, int band, int dir,
+                                                   double* norm = nullptr)
 {
+    static_assert(!(IMAG && RES), "imaginary time has no reservoir");
+    const R sc = IMAG ? (R)a.imag_slots[1] : R(1);  // uniform
+    double nrm = 0.0;
     using C = typename cvec<R>::type;
     static_assert((B + 8) % 24 == 0, "band rows + 8 must be a multiple of the unroll length");
     constexpr int PF = 3;
@@ -135,6 +148,10 @@ __device__ __forceinline__ bool stream_band_spinor(const StepArgs<R>& a, int str
         const int rr = grow ? 0 : rw;
         sp[0][s] = buf_load<C>(grow ? rnull : rpi, vc, rr * row_c);
         sp[1][s] = buf_load<C>(grow ? rnull : rpi, vc, comp_c + rr * row_c);
+        if constexpr (IMAG) {
+#pragma unroll
+            for (int m = 0; m < 2; ++m) sp[m][s] = C{sp[m][s].x * sc, sp[m][s].y * sc};
+        }
         if (RES) {
 #pragma unroll
             for (int m = 0; m < 2; ++m) {
@@ -195,7 +212,7 @@ __device__ __forceinline__ bool stream_band_spinor(const StepArgs<R>& a, int str
                     nn[m] = sn[m][s0];
                     pv[m] = sP[m][s0];
                 }
-                spinor_rhs<R, RES>(c, cur, lr, ud, dy, sk[s0], bxyd, nn, pv, f, fn);
+                spinor_rhs<R, RES, IMAG>(c, cur, lr, ud, dy, sk[s0], bxyd, nn, pv, f, fn);
                 const R hk = row_h(j - 1 * dir, kh2);
 #pragma unroll
                 for (int m = 0; m < 2; ++m) {
@@ -219,7 +236,7 @@ __device__ __forceinline__ bool stream_band_spinor(const StepArgs<R>& a, int str
                     nn[m] = n2[m][slot<2>(u, 2)];
                     pv[m] = sP[m][s0];
                 }
-                spinor_rhs<R, RES>(c, cur, lr, ud, dy, sk[s0], bxyd, nn, pv, f, fn);
+                spinor_rhs<R, RES, IMAG>(c, cur, lr, ud, dy, sk[s0], bxyd, nn, pv, f, fn);
                 const R hk = row_h(j - 2 * dir, kh2);
 #pragma unroll
                 for (int m = 0; m < 2; ++m) {
@@ -245,7 +262,7 @@ __device__ __forceinline__ bool stream_band_spinor(const StepArgs<R>& a, int str
                     nn[m] = n3[m][slot<2>(u, 3)];
                     pv[m] = sP[m][s0];
                 }
-                spinor_rhs<R, RES>(c, cur, lr, ud, dy, sk[s0], bxyd, nn, pv, f, fn);
+                spinor_rhs<R, RES, IMAG>(c, cur, lr, ud, dy, sk[s0], bxyd, nn, pv, f, fn);
                 const R hk = row_h(j - 3 * dir, kh);
 #pragma unroll
                 for (int m = 0; m < 2; ++m) {
@@ -272,7 +289,7 @@ __device__ __forceinline__ bool stream_band_spinor(const StepArgs<R>& a, int str
                     nn[m] = n4[m][slot<2>(u, 4)];
                     pv[m] = sP[m][s0];
                 }
-                spinor_rhs<R, RES>(c, cur, lr, ud, dy, sk[s0], bxyd, nn, pv, f, fn);
+                spinor_rhs<R, RES, IMAG>(c, cur, lr, ud, dy, sk[s0], bxyd, nn, pv, f, fn);
                 const int r = j - 4 * dir;
                 const bool st = out_col && r >= b0 && r < b0 + B && r < a.ny;
                 const int cell = r * a.nx + gi;
@@ -282,6 +299,7 @@ __device__ __forceinline__ bool stream_band_spinor(const StepArgs<R>& a, int str
                     const C p0 = sp[m][s0];
                     const C y = C{fma(a.dt6, ac.x + f[m].x, p0.x), fma(a.dt6, ac.y + f[m].y, p0.y)};
                     buf_store_nt(y, rpo, st ? (int)((m * cells + cell) * sizeof(C)) : kOutOfRange);
+                    if constexpr (IMAG) nrm += st ? (double)y.x * y.x + (double)y.y * y.y : 0.0;
                     bool b = !(isfinite(y.x) && isfinite(y.y));
                     if (RES) {
                         const R yn = fma(a.dt6, accn[m][slot<4>(u, 4)] + fn[m], sn[m][s0]);
@@ -293,6 +311,7 @@ __device__ __forceinline__ bool stream_band_spinor(const StepArgs<R>& a, int str
             }
         }
     }
+    if constexpr (IMAG) *norm = nrm;
     return bad;
 }
 

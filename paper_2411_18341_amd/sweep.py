@@ -193,6 +193,44 @@ def measure_spinor(n: int = 4096, accepted: int = 20, rk4_steps: int = 50, reser
     return out
 
 
+def measure_spinor_imag(n: int = 4096, steps: int = 50):
+    """The spinor workload (inputs.spinor, complex64, n x n) in imaginary time: RK4
+    steps on each kernel family (the two-component streaming whole-step kernel, which
+    writes one norm partial per wave, and the stage-fused family with its separate norm
+    pass), point updates per second of whole steps and per-kernel launch times."""
+    import torch
+    ph, psi0, V = inputs.spinor(n)
+    dev = torch.device("cuda:0")
+    out = {"n": n}
+    model = bytemodel.rk4_whole_step(4, reservoir=False, has_v=True, components=2)["step"]
+    for family, kernel in (("step", phx.PHX_KERNEL_STEP), ("stage", phx.PHX_KERNEL_STAGE)):
+        psi = torch.from_numpy(psi0).to(dtype=torch.complex64, device=dev).contiguous()
+        Vd = torch.from_numpy(V).to(dtype=torch.float32, device=dev).contiguous()
+        cfg = phx.config_from_physics(ph, precision=phx.PHX_C64, imag_time=True, kernel=kernel)
+        solver = phx.Solver(cfg, psi, None, Vd, None)
+        try:
+            solver.step(4)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            solver.step(steps)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            solver.set_timing(True)
+            solver.step(10)
+            torch.cuda.synchronize()
+            times = solver.kernel_times()
+        finally:
+            solver.close()
+        ks = {}
+        for k, v in times.items():
+            us = v["ms_total"] / v["launches"] * 1e3
+            ks[k] = {"launches": v["launches"], "avg_us": us}
+            if k == "rk4_step":
+                ks[k]["algorithmic_GBps"] = model * n * n / (us * 1e-6) / 1e9
+        out[family] = {"UPs": n * n * steps / wall, "us_per_step": wall / steps * 1e6, "kernels": ks}
+    return out
+
+
 def measure_noise(n: int = 4096, nu: float = 1.0, steps: int = 300, warmup: int = 20, timed_steps: int = 40):
     """The driven workload (complex64, n x n) with the complex Wiener noise of the
     truncated-Wigner form switched on: point updates per second of whole noisy RK4
@@ -330,6 +368,8 @@ def main():
     ap.add_argument("--spinor", action="store_true", help="also measure the 4096^2 spinor workload (RK4, RK45)")
     ap.add_argument("--spinor-reservoir", action="store_true",
                     help="also measure the 4096^2 spinor workload with a reservoir per component")
+    ap.add_argument("--spinor-imag", action="store_true",
+                    help="also measure the 4096^2 spinor workload in imaginary time on both kernel families")
     ap.add_argument("--noise", action="store_true", help="also measure the 4096^2 driven workload with Wiener noise")
     ap.add_argument("--drive", action="store_true", help="also measure the stage-fused kernels with a coherent drive")
     ap.add_argument("--ensemble", action="store_true", help="also measure a batched noisy ensemble (128 x 256^2)")
@@ -357,6 +397,12 @@ def main():
         print(json.dumps({"spinor": r}), flush=True)
         if args.out:
             with open(args.out + ".spinor.json", "w") as f:
+                json.dump(r, f, indent=1)
+    if args.spinor_imag:
+        r = measure_spinor_imag()
+        print(json.dumps({"spinor_imag": r}), flush=True)
+        if args.out:
+            with open(args.out + ".spinor_imag.json", "w") as f:
                 json.dump(r, f, indent=1)
     if args.spinor_reservoir:
         r = measure_spinor(reservoir=True)

@@ -93,8 +93,8 @@ def test_workspace_bytes_scale_with_precision_and_reservoir():
     assert 2 * 64 * 48 * 8 <= d < a
     assert phx.phx_workspace_bytes(good_config()) == d  # AUTO picks the whole-step kernel
     # spinor: the streaming whole-step kernel (two state buffers of both components,
-    # with the reservoir two of both reservoirs), bands of 40 or 64 rows; not with the
-    # drive or in imaginary time
+    # with the reservoir two of both reservoirs), bands of 40 or 64 rows, also in
+    # imaginary time; not with the drive
     s = phx.phx_workspace_bytes(good_config(kernel=phx.PHX_KERNEL_STEP, components=2, delta_lt=0.1))
     assert 2 * 2 * 64 * 48 * 8 <= s
     assert phx.phx_workspace_bytes(good_config(components=2, delta_lt=0.1)) == s
@@ -107,6 +107,9 @@ def test_workspace_bytes_scale_with_precision_and_reservoir():
     with pytest.raises(phx.PhxError) as e:
         phx.phx_workspace_bytes(good_config(kernel=phx.PHX_KERNEL_STEP, components=2, drive=True))
     assert e.value.status == phx.PHX_EUNSUPPORTED
+    si = phx.phx_workspace_bytes(good_config(kernel=phx.PHX_KERNEL_STEP, components=2, delta_lt=0.1,
+                                             imag_time=True, tile_wx=1, tile_rows=40))
+    assert phx.phx_workspace_bytes(good_config(components=2, delta_lt=0.1, imag_time=True)) == si
 
 
 @pytest.mark.parametrize("field,value", [
@@ -156,9 +159,9 @@ def test_drive_config_validation():
 
 def test_imag_time_config_validation():
     """Imaginary time: the conservative equation; one component runs on the streaming
-    whole-step kernel, one-column or wide walk (region shapes rejected), the stage-fused family on request or
-    for the spinor; RK4's stability bound on the negative real axis (2.78) replaces the
-    imaginary-axis one."""
+    whole-step kernel, one-column or wide walk (region shapes rejected), two on the spinor
+    walk, the stage-fused family on request; RK4's stability bound on the negative real
+    axis (2.78) replaces the imaginary-axis one."""
     stage = phx.phx_workspace_bytes(good_config(kernel=phx.PHX_KERNEL_STAGE))
     step = phx.phx_workspace_bytes(good_config())
     assert phx.phx_workspace_bytes(good_config(imag_time=True, kernel=phx.PHX_KERNEL_STAGE)) == stage + 256 + 256
@@ -166,7 +169,7 @@ def test_imag_time_config_validation():
     phx.phx_workspace_bytes(good_config(imag_time=True, tile_wx=1, tile_rows=64))
     phx.phx_workspace_bytes(good_config(imag_time=True, tile_wx=2, tile_rows=0))    # the wide walk
     phx.phx_workspace_bytes(good_config(imag_time=True, tile_wx=3, tile_rows=8))
-    phx.phx_workspace_bytes(good_config(imag_time=True, components=2, delta_lt=0.1))   # stage-fused
+    phx.phx_workspace_bytes(good_config(imag_time=True, components=2, delta_lt=0.1))   # spinor walk
     for bad in (dict(reservoir=True), dict(gamma_c=0.1), dict(R=0.1), dict(noise=1.0), dict(drive=True),
                 dict(tile_wx=8, tile_rows=4)):
         with pytest.raises(phx.PhxError) as e:

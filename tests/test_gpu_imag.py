@@ -3,9 +3,10 @@ oracle, through the C-ABI.
 
 Both kernel families rotate their derivative by -i.  The stage-fused family restores
 the norm after every step (deterministic FP64 reduction, scale pass); the streaming
-whole-step kernel (one component) writes per-wave norm partials, and the restoring
-scale is applied to the next step's input and, once, at the end of the call.  Both
-keep the total norm the state had when the phx_step call began.  Element-wise parity to relative L2 1e-12 (complex128)
+whole-step kernels (the scalar's one-column and wide walks, the spinor's walk) write
+per-wave norm partials, and the restoring scale is applied to the next step's input
+and, once, at the end of the call.  Both keep the total norm the state had when the
+phx_step call began.  Element-wise parity to relative L2 1e-12 (complex128)
 and 1e-5 (complex64) after 7 steps (scalar with V and g, TE-TM spinor, both boundary
 rules, direct launches and graph replays); the norm is kept at every call; and on a
 512^2 harmonic trap the state converges to the ground state of the discrete
@@ -133,6 +134,30 @@ def test_imag_norm_kept_per_call():
     run.step(4)
     assert run.observables()["norm"][0] == pytest.approx(4 * n0, rel=1e-13)
     run.close()
+
+
+@pytest.mark.parametrize("precision", [C64, C128])
+@pytest.mark.parametrize("bc", [(0, 0), (1, 1), (0, 1)])
+@pytest.mark.parametrize("rows", [40, 64])
+def test_imag_spinor_streaming(rows, bc, precision):
+    """The TE-TM spinor on its streaming whole-step walk in imaginary time: both band
+    heights, ragged grids spanning several strips and bands, odd and even step counts
+    over two calls; the total norm of both components is the one the call began with."""
+    for nx, ny, steps in ((130, 97, 5), (57, 150, 4)):
+        ph, psi, V = case("spinor", nx, ny, bc, 11)
+        q = quantize(precision, psi, None, V, None)
+        run = GpuRun(ph, q[0], None, q[2], None, precision=precision, imag_time=True,
+                     kernel=phx.PHX_KERNEL_STEP, tile_wx=1, tile_rows=rows, graph_steps=2)
+        run.step(steps)
+        run.step(3)
+        g_psi, _ = run.state()
+        run.close()
+        o_psi = oracle.rk4_imag(oracle_physics(ph), q[0], V=q[2], dt=ph.dt, steps=steps)
+        o_psi = oracle.rk4_imag(oracle_physics(ph), o_psi, V=q[2], dt=ph.dt, steps=3)
+        e = rel_l2(g_psi, o_psi)
+        assert e <= TOL[precision], (rows, nx, ny, e)
+        n0 = np.sum(np.abs(q[0]) ** 2)
+        assert np.sum(np.abs(g_psi) ** 2) == pytest.approx(n0, rel=TOL[precision])
 
 
 @pytest.mark.parametrize("precision", [C64, C128])
