@@ -53,7 +53,7 @@ def kernel_kind(name: str) -> str:
     m = re.search(r"(rk4_stage_kernel|dp_stage_kernel)<[^>]*?(\d+)>", name)
     if m:
         return ("rk4_stage" if m.group(1).startswith("rk4") else "dp_stage") + m.group(2)
-    m = re.search(r"rk4_stream_wide_kernel<[^>]*?, (\d+), \d+, \d+(?:, (?:true|false))?>", name)
+    m = re.search(r"rk4_stream_wide_kernel<[^>]*?, (\d+), \d+, \d+(?:, (?:true|false))*>", name)
     if m:  # wide streaming form: named by its input ring (8: shapes 2 x B, 12: shapes 3 x B)
         return f"rk4_step_wide{m.group(1)}"
     m = re.search(r"rk4_step_kernel<[^>]*?(\d+), (\d+)>", name)

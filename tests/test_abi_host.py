@@ -345,6 +345,10 @@ def test_profile_kernel_names():
             "rk4_step_wide8",
         "void phx::rk4_stream_wide_kernel<false, true, true, true, 12, 6, 2, true>(phx::StepArgs<float>)":
             "rk4_step_wide12",
+        "void phx::rk4_stream_wide_kernel<true, false, false, false, 8, 3, 2, false, true, false>(phx::StepArgs<float>)":
+            "rk4_step_wide8",   # with the noise drawn in the step
+        "void phx::rk4_stream_wide_kernel<false, true, false, false, 12, 6, 2, true, false, true>(phx::StepArgs<float>)":
+            "rk4_step_wide12",  # imaginary time
     }
     for name, kind in cases.items():
         assert kernel_kind(name) == kind, name
