@@ -113,9 +113,10 @@ typedef struct phx_config {
                                (RK4: t + {0, 1/2, 1/2, 1} dt; Dormand-Prince: its nodes c_s);
                                t is phx_info.t (a step taken k steps after the last
                                phx_set_info or phx_create starts at t_set + k dt).  RK4 on
-                               the streaming whole-step kernel (one component, bands of 40
-                               or 64 rows; PHX_KERNEL_AUTO picks it when the state is under
-                               2 GiB) or the stage-fused kernels (two components, or on
+                               the streaming whole-step kernel (one component, or two
+                               without reservoirs; bands of 40 or 64 rows; PHX_KERNEL_AUTO
+                               picks it when the state is under 2 GiB) or the stage-fused
+                               kernels (two components with reservoirs, or on
                                request), and RK45; batches: PHX_EUNSUPPORTED.  0: none      */
     int32_t imag_time;      /* 1: imaginary-time propagation (t -> -i tau, named in Sec. 6)
                                of the conservative equation (reservoir, gamma_c, R, noise and

@@ -19,7 +19,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 OUT = os.path.join(HERE, "libphx.so")
 BUILD_DIR = os.path.join(HERE, "_build")
-SOURCES = ["rk4_step.hip", "rk4_stream_spinor_res_f40.hip", "rk4_stream_spinor_res_f64.hip", "rk4_stream_spinor_res_d40.hip", "rk4_stream_spinor_res_d64.hip", "rk4_stream_spinor_imag_f.hip", "rk4_stream_spinor_imag_d.hip", "runtime.hip", "rk4.hip", "reduce.hip", "dopri5.hip", "batch.hip", "autotune.hip", "cnn.hip", "noise.hip", "drive.hip", "imag.hip", "rk4_stream_drive.hip", "rk4_stream_spinor.hip", "rk4_stream_wide.hip", "copy.hip", "static_obs.hip"]
+SOURCES = ["rk4_step.hip", "rk4_stream_spinor_res_f40.hip", "rk4_stream_spinor_res_f64.hip", "rk4_stream_spinor_res_d40.hip", "rk4_stream_spinor_res_d64.hip", "rk4_stream_spinor_imag_f.hip", "rk4_stream_spinor_imag_d.hip", "rk4_stream_spinor_drive_f.hip", "rk4_stream_spinor_drive_d.hip", "runtime.hip", "rk4.hip", "reduce.hip", "dopri5.hip", "batch.hip", "autotune.hip", "cnn.hip", "noise.hip", "drive.hip", "imag.hip", "rk4_stream_drive.hip", "rk4_stream_spinor.hip", "rk4_stream_wide.hip", "copy.hip", "static_obs.hip"]
 
 ARCH = "gfx950"
 FLAGS = [
@@ -34,7 +34,7 @@ FLAGS = [
 # for a requested full unroll, so its unit raises that limit.
 _FULL_UNROLL = ["-mllvm", "-pragma-unroll-threshold=40000"]
 EXTRA_FLAGS = {f"rk4_stream_spinor{t}.hip": _FULL_UNROLL
-               for t in ("", "_res_f40", "_res_f64", "_res_d40", "_res_d64", "_imag_f", "_imag_d")}
+               for t in ("", "_res_f40", "_res_f64", "_res_d40", "_res_d64", "_imag_f", "_imag_d", "_drive_f", "_drive_d")}
 # the wide walk with the Wiener increment drawn at its final store (a generator call
 # per position) likewise exceeds the default limit
 EXTRA_FLAGS["rk4_stream_wide.hip"] = _FULL_UNROLL

@@ -140,7 +140,8 @@ template <typename R>
 hipError_t launch_rk4_step(bool reservoir, bool has_v, const StepShapeId& sh, const StepArgs<R>& a,
                            hipStream_t s)
 {
-    if (a.E) return sh.waves == 1 ? launch_stream_drive<R>(reservoir, has_v, sh.rows, a, s) : hipErrorInvalidValue;
+    if (a.E && a.comps == 1)
+        return sh.waves == 1 ? launch_stream_drive<R>(reservoir, has_v, sh.rows, a, s) : hipErrorInvalidValue;
     if (wide_shape(sh.waves)) {
         if constexpr (sizeof(R) == 4) {
             if (a.comps != 1) return hipErrorInvalidValue;

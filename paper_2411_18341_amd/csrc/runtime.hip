@@ -53,9 +53,10 @@ phx_status validate_config(const phx_config* c)
         return fail(PHX_EINVAL, "integrator=%d must be PHX_RK4 or PHX_RK45", c->integrator);
     if (c->kernel < PHX_KERNEL_AUTO || c->kernel > PHX_KERNEL_STEP)
         return fail(PHX_EINVAL, "kernel=%d is not a PHX_KERNEL_* value", c->kernel);
-    if (c->kernel == PHX_KERNEL_STEP && (c->integrator != PHX_RK4 || (c->components == 2 && c->drive)))
-        return fail(PHX_EUNSUPPORTED, "the whole-step kernel covers RK4 with one component, or two without the "
-                                      "drive");
+    if (c->kernel == PHX_KERNEL_STEP &&
+        (c->integrator != PHX_RK4 || (c->components == 2 && c->drive && c->reservoir)))
+        return fail(PHX_EUNSUPPORTED, "the whole-step kernel covers RK4 with one component, or two (with the "
+                                      "drive: without reservoirs)");
     if ((c->tile_wx == 0) != (c->tile_rows == 0) && !(wide_shape(c->tile_wx) && c->kernel != PHX_KERNEL_STAGE))
         return fail(PHX_EINVAL, "tile_wx and tile_rows: both 0 or both set (tile_rows 0 with tile_wx 2 or 3: "
                                 "the wide streaming form with the device-filling band height)");
@@ -229,14 +230,14 @@ bool valid_step_shape(int precision, int waves, int rows)
 }
 
 // RK4 kernel family: the whole-step kernel (one launch per step, state read and
-// written once) for one component and for the spinor (its streaming form; also with
-// the drive or in imaginary time for one component), the stage-fused kernels
-// otherwise or on request.
+// written once) for one component and for the spinor (its streaming form), also with
+// the drive (the spinor without reservoirs) or in imaginary time, the stage-fused
+// kernels otherwise or on request.
 int rk4_family(const phx_config& c)
 {
     if (c.kernel == PHX_KERNEL_STAGE) return PHX_KERNEL_STAGE;
     if (c.drive)  // the streaming form when it fits, else the stage-fused kernels
-        return (c.components == 1 && step_shape_fits(c, 1)) ? PHX_KERNEL_STEP : PHX_KERNEL_STAGE;
+        return ((c.components == 1 || !c.reservoir) && step_shape_fits(c, 1)) ? PHX_KERNEL_STEP : PHX_KERNEL_STAGE;
     if (c.imag_time)  // one component or the spinor: the streaming form when it fits
         return step_shape_fits(c, 1) ? PHX_KERNEL_STEP : PHX_KERNEL_STAGE;
     if (c.components == 1) return PHX_KERNEL_STEP;

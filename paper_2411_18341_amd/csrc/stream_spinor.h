@@ -73,11 +73,15 @@ __device__ __forceinline__ void spinor_rhs(const Coef<R>& c, const typename cvec
 // input is multiplied by the scale a.imag_slots[1] that restores the previous step's
 // norm, and *norm receives this lane's FP64 sum of |psi_out|^2 over both components of
 // the cells it stores.
-template <typename R, bool RES, bool HASV, bool GHOSTS, bool YZERO, int B, bool IMAG = false>
+// DRIVE (no reservoirs, real time): the coherent drive -(i/hbar) E_s(r) exp(-i omega t_k)
+// joins the derivative of component s at stage k; both components of E ride in the
+// input ring beside psi, the four stage phasors come from a.drive_ph.
+template <typename R, bool RES, bool HASV, bool GHOSTS, bool YZERO, int B, bool IMAG = false, bool DRIVE = false>
 __device__ __forceinline__ bool stream_band_spinor(const StepArgs<R>& a, int strip, int band, int dir,
                                                    double* norm = nullptr)
 {
     static_assert(!(IMAG && RES), "imaginary time has no reservoir");
+    static_assert(!(DRIVE && (RES || IMAG)), "the drive runs without reservoirs, in real time");
     const R sc = IMAG ? (R)a.imag_slots[1] : R(1);  // uniform
     double nrm = 0.0;
     using C = typename cvec<R>::type;
@@ -107,8 +111,11 @@ __device__ __forceinline__ bool stream_band_spinor(const StepArgs<R>& a, int str
     const __amdgpu_buffer_rsrc_t rP = buffer_of(a.P, RES ? 2 * cells * sizeof(R) : 0);
     const __amdgpu_buffer_rsrc_t rV = buffer_of(a.V, HASV ? cells * sizeof(R) : 0);
     const __amdgpu_buffer_rsrc_t rnull = buffer_of(a.psi_in, 0);
+    const __amdgpu_buffer_rsrc_t rE = buffer_of(a.E, DRIVE ? 2 * cells * sizeof(C) : 0);
 
     C sp[2][8];
+    C sE[2][8];  // DRIVE: the profile of both components, in the input ring
+    C ph[4];     // DRIVE: the phasors of the four stage times
     R sk[8];
     R sn[2][8], sP[2][8];
     C acc[2][4];
@@ -120,7 +127,19 @@ __device__ __forceinline__ bool stream_band_spinor(const StepArgs<R>& a, int str
         sp[0][s] = sp[1][s] = czero<C>();
         sn[0][s] = sn[1][s] = sP[0][s] = sP[1][s] = R(0);
         sk[s] = kdiag;
+        if constexpr (DRIVE) sE[0][s] = sE[1][s] = czero<C>();
     }
+    if constexpr (DRIVE) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) ph[s] = a.drive_ph[s];
+    }
+    // DRIVE: adds -(i/hbar) E ph to f
+    auto drive = [&](C& f, const C e, const C p) {
+        const R zx = e.x * p.x - e.y * p.y;
+        const R zy = e.x * p.y + e.y * p.x;
+        f.x = fma(c.inv_hbar, zy, f.x);
+        f.y = fma(-c.inv_hbar, zx, f.y);
+    };
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
         acc[0][s] = acc[1][s] = czero<C>();
@@ -148,6 +167,10 @@ __device__ __forceinline__ bool stream_band_spinor(const StepArgs<R>& a, int str
         const int rr = grow ? 0 : rw;
         sp[0][s] = buf_load<C>(grow ? rnull : rpi, vc, rr * row_c);
         sp[1][s] = buf_load<C>(grow ? rnull : rpi, vc, comp_c + rr * row_c);
+        if constexpr (DRIVE) {
+            sE[0][s] = buf_load<C>(grow ? rnull : rE, vc, rr * row_c);
+            sE[1][s] = buf_load<C>(grow ? rnull : rE, vc, comp_c + rr * row_c);
+        }
         if constexpr (IMAG) {
 #pragma unroll
             for (int m = 0; m < 2; ++m) sp[m][s] = C{sp[m][s].x * sc, sp[m][s].y * sc};
@@ -213,6 +236,10 @@ __device__ __forceinline__ bool stream_band_spinor(const StepArgs<R>& a, int str
                     pv[m] = sP[m][s0];
                 }
                 spinor_rhs<R, RES, IMAG>(c, cur, lr, ud, dy, sk[s0], bxyd, nn, pv, f, fn);
+                if constexpr (DRIVE) {
+                    drive(f[0], sE[0][s0], ph[0]);
+                    drive(f[1], sE[1][s0], ph[0]);
+                }
                 const R hk = row_h(j - 1 * dir, kh2);
 #pragma unroll
                 for (int m = 0; m < 2; ++m) {
@@ -237,6 +264,10 @@ __device__ __forceinline__ bool stream_band_spinor(const StepArgs<R>& a, int str
                     pv[m] = sP[m][s0];
                 }
                 spinor_rhs<R, RES, IMAG>(c, cur, lr, ud, dy, sk[s0], bxyd, nn, pv, f, fn);
+                if constexpr (DRIVE) {
+                    drive(f[0], sE[0][s0], ph[1]);
+                    drive(f[1], sE[1][s0], ph[1]);
+                }
                 const R hk = row_h(j - 2 * dir, kh2);
 #pragma unroll
                 for (int m = 0; m < 2; ++m) {
@@ -263,6 +294,10 @@ __device__ __forceinline__ bool stream_band_spinor(const StepArgs<R>& a, int str
                     pv[m] = sP[m][s0];
                 }
                 spinor_rhs<R, RES, IMAG>(c, cur, lr, ud, dy, sk[s0], bxyd, nn, pv, f, fn);
+                if constexpr (DRIVE) {
+                    drive(f[0], sE[0][s0], ph[2]);
+                    drive(f[1], sE[1][s0], ph[2]);
+                }
                 const R hk = row_h(j - 3 * dir, kh);
 #pragma unroll
                 for (int m = 0; m < 2; ++m) {
@@ -290,6 +325,10 @@ __device__ __forceinline__ bool stream_band_spinor(const StepArgs<R>& a, int str
                     pv[m] = sP[m][s0];
                 }
                 spinor_rhs<R, RES, IMAG>(c, cur, lr, ud, dy, sk[s0], bxyd, nn, pv, f, fn);
+                if constexpr (DRIVE) {
+                    drive(f[0], sE[0][s0], ph[3]);
+                    drive(f[1], sE[1][s0], ph[3]);
+                }
                 const int r = j - 4 * dir;
                 const bool st = out_col && r >= b0 && r < b0 + B && r < a.ny;
                 const int cell = r * a.nx + gi;

@@ -193,21 +193,33 @@ def measure_spinor(n: int = 4096, accepted: int = 20, rk4_steps: int = 50, reser
     return out
 
 
-def measure_spinor_imag(n: int = 4096, steps: int = 50):
-    """The spinor workload (inputs.spinor, complex64, n x n) in imaginary time: RK4
-    steps on each kernel family (the two-component streaming whole-step kernel, which
-    writes one norm partial per wave, and the stage-fused family with its separate norm
-    pass), point updates per second of whole steps and per-kernel launch times."""
+def measure_spinor_imag(n: int = 4096, steps: int = 50, drive: bool = False, omega: float = 1.3):
+    """The spinor workload (inputs.spinor, complex64, n x n) in imaginary time, or with
+    `drive` in real time with a coherent drive (a Gaussian spot of amplitude 0.8 per
+    component, the two with opposite phase gradients): RK4 steps on each kernel family
+    (the two-component streaming whole-step kernel, which in imaginary time writes one
+    norm partial per wave, and the stage-fused family, with its separate norm pass in
+    imaginary time), point updates per second of whole steps and per-kernel launch
+    times."""
+    import numpy as np
     import torch
     ph, psi0, V = inputs.spinor(n)
     dev = torch.device("cuda:0")
-    out = {"n": n}
-    model = bytemodel.rk4_whole_step(4, reservoir=False, has_v=True, components=2)["step"]
+    out = {"n": n, "drive": drive}
+    model = bytemodel.rk4_whole_step(4, reservoir=False, has_v=True, components=2)["step"] + (16 if drive else 0)
+    X, Y = inputs.coords(n, n, ph.dx, ph.dy)
+    spot = 0.8 * np.exp(-(X * X + Y * Y) / (2 * 30.0 ** 2))
+    E0 = np.stack([spot * np.exp(0.5j * X), spot * np.exp(-0.5j * X)]).astype(np.complex64)
     for family, kernel in (("step", phx.PHX_KERNEL_STEP), ("stage", phx.PHX_KERNEL_STAGE)):
         psi = torch.from_numpy(psi0).to(dtype=torch.complex64, device=dev).contiguous()
         Vd = torch.from_numpy(V).to(dtype=torch.float32, device=dev).contiguous()
-        cfg = phx.config_from_physics(ph, precision=phx.PHX_C64, imag_time=True, kernel=kernel)
-        solver = phx.Solver(cfg, psi, None, Vd, None)
+        if drive:
+            cfg = phx.config_from_physics(ph, precision=phx.PHX_C64, drive=True, drive_omega=omega, kernel=kernel)
+            Ed = torch.from_numpy(E0).to(device=dev).contiguous()
+            solver = phx.Solver(cfg, psi, None, Vd, None, E=Ed)
+        else:
+            cfg = phx.config_from_physics(ph, precision=phx.PHX_C64, imag_time=True, kernel=kernel)
+            solver = phx.Solver(cfg, psi, None, Vd, None)
         try:
             solver.step(4)
             torch.cuda.synchronize()
@@ -370,6 +382,8 @@ def main():
                     help="also measure the 4096^2 spinor workload with a reservoir per component")
     ap.add_argument("--spinor-imag", action="store_true",
                     help="also measure the 4096^2 spinor workload in imaginary time on both kernel families")
+    ap.add_argument("--spinor-drive", action="store_true",
+                    help="also measure the 4096^2 spinor workload with a coherent drive on both kernel families")
     ap.add_argument("--noise", action="store_true", help="also measure the 4096^2 driven workload with Wiener noise")
     ap.add_argument("--drive", action="store_true", help="also measure the stage-fused kernels with a coherent drive")
     ap.add_argument("--ensemble", action="store_true", help="also measure a batched noisy ensemble (128 x 256^2)")
@@ -403,6 +417,12 @@ def main():
         print(json.dumps({"spinor_imag": r}), flush=True)
         if args.out:
             with open(args.out + ".spinor_imag.json", "w") as f:
+                json.dump(r, f, indent=1)
+    if args.spinor_drive:
+        r = measure_spinor_imag(drive=True)
+        print(json.dumps({"spinor_drive": r}), flush=True)
+        if args.out:
+            with open(args.out + ".spinor_drive.json", "w") as f:
                 json.dump(r, f, indent=1)
     if args.spinor_reservoir:
         r = measure_spinor(reservoir=True)

@@ -94,7 +94,7 @@ def test_workspace_bytes_scale_with_precision_and_reservoir():
     assert phx.phx_workspace_bytes(good_config()) == d  # AUTO picks the whole-step kernel
     # spinor: the streaming whole-step kernel (two state buffers of both components,
     # with the reservoir two of both reservoirs), bands of 40 or 64 rows, also in
-    # imaginary time; not with the drive
+    # imaginary time and with the drive (without reservoirs)
     s = phx.phx_workspace_bytes(good_config(kernel=phx.PHX_KERNEL_STEP, components=2, delta_lt=0.1))
     assert 2 * 2 * 64 * 48 * 8 <= s
     assert phx.phx_workspace_bytes(good_config(components=2, delta_lt=0.1)) == s
@@ -104,8 +104,12 @@ def test_workspace_bytes_scale_with_precision_and_reservoir():
         with pytest.raises(phx.PhxError) as e:
             phx.phx_workspace_bytes(good_config(kernel=phx.PHX_KERNEL_STEP, components=2, **bad))
         assert e.value.status == phx.PHX_EINVAL, bad
+    # with the drive: the streaming kernel without reservoirs, the stage-fused kernels with them
+    sd = phx.phx_workspace_bytes(good_config(kernel=phx.PHX_KERNEL_STEP, components=2, drive=True, tile_wx=1,
+                                             tile_rows=64))
+    assert phx.phx_workspace_bytes(good_config(components=2, drive=True)) == sd
     with pytest.raises(phx.PhxError) as e:
-        phx.phx_workspace_bytes(good_config(kernel=phx.PHX_KERNEL_STEP, components=2, drive=True))
+        phx.phx_workspace_bytes(good_config(kernel=phx.PHX_KERNEL_STEP, components=2, drive=True, reservoir=True))
     assert e.value.status == phx.PHX_EUNSUPPORTED
     si = phx.phx_workspace_bytes(good_config(kernel=phx.PHX_KERNEL_STEP, components=2, delta_lt=0.1,
                                              imag_time=True, tile_wx=1, tile_rows=40))

@@ -7,7 +7,8 @@ device memory (written per step from the device step index, so graph replays kee
 the phase), and the Dormand-Prince stages get theirs from the host.  Element-wise
 parity to relative L2 1e-12 (complex128) and 1e-5 (complex64) on small ragged grids
 (driven with and without V, spinor with reservoir, both boundary rules, direct
-launches and graph replays), together with the noise, after a phx_set_info to an
+launches and graph replays; the streaming walks of one component and of the spinor
+without reservoirs), together with the noise, after a phx_set_info to an
 arbitrary time, for RK45 (same accept/reject sequence), and for the observables'
 residual; at 2048^2 the plane-wave response against the exact driven solution on
 every cell.
@@ -174,6 +175,27 @@ def test_drive_streaming_shapes(rows, precision):
         assert rel_l2(g_psi, o_psi) <= TOL[precision] and rel_l2(g_n, o_n) <= TOL[precision], (bc, rows)
 
 
+@pytest.mark.parametrize("precision", [C64, C128])
+@pytest.mark.parametrize("rows", [40, 64])
+def test_drive_spinor_streaming(rows, precision):
+    """The spinor (no reservoirs) on its streaming walk with the drive: a profile per
+    component, both band heights, ragged grids of several strips and bands, three
+    boundary mixes, odd and even step counts over two calls; the same with the kernel
+    family left to the library, which picks this walk."""
+    for bc, (nx, ny) in (((0, 0), (130, 97)), ((1, 1), (57, 150)), ((0, 1), (200, 83))):
+        ph, psi, n, V, P = workload("spinor", nx, ny, bc, seed=13)
+        q = quantize(precision, psi, n, V, P)
+        E = quantize_e(precision, drive_profile(ph, 14))
+        o_psi, _ = oracle.rk4(oracle_drive(ph, E), *q, dt=ph.dt, steps=9)
+        for kw in (dict(kernel=phx.PHX_KERNEL_STEP, tile_wx=1, tile_rows=rows), dict()):
+            run = GpuRun(ph, *q, precision=precision, E=E, drive_omega=OMEGA, graph_steps=2, **kw)
+            run.step(5)
+            run.step(4)
+            g_psi, _ = run.state()
+            run.close()
+            assert rel_l2(g_psi, o_psi) <= TOL[precision], (bc, rows, kw)
+
+
 def test_drive_family_and_rejections():
     ph, psi, n, V, P = workload("driven", 64, 48, (0, 0))
     E = drive_profile(ph, 1)
@@ -183,6 +205,11 @@ def test_drive_family_and_rejections():
     with pytest.raises(phx.PhxError) as e:  # nor bands other than 40 and 64 rows
         GpuRun(ph, psi, n, V, P, precision=C64, E=E, kernel=phx.PHX_KERNEL_STEP, tile_wx=1, tile_rows=88)
     assert e.value.status == phx.PHX_EINVAL
+    ph2, psi2, n2, V2, P2 = workload("spinor_res", 64, 48, (0, 0))
+    with pytest.raises(phx.PhxError) as e:  # the spinor with reservoirs and the drive: stage-fused only
+        GpuRun(ph2, psi2, n2, V2, P2, precision=C64, E=drive_profile(ph2, 2), kernel=phx.PHX_KERNEL_STEP,
+               tile_wx=1, tile_rows=40)
+    assert e.value.status == phx.PHX_EUNSUPPORTED
     with pytest.raises(phx.PhxError) as e:
         GpuRun(ph, psi, n, V, P, precision=C64, E=E, drive=False)  # profile without drive
     assert e.value.status == phx.PHX_EINVAL
